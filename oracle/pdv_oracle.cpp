@@ -1,0 +1,441 @@
+// PDV multiple-scattering Monte Carlo — FP64 CPU ORACLE.
+//
+// TEST INFRASTRUCTURE ONLY.  Only tests/, __graft_entry__.smoke() and the
+// cpu_baseline leg of bench.py may load this library.  The product (the HIP
+// library under paper_2012_00963_amd/) never calls it and shares no code
+// with it.
+//
+// What it computes (Shi et al., "Reconstruction and interpretation of PDV
+// spectrum for ejecta particles", Sec. II):
+//   * photons enter the top of a laterally infinite slab of moving particles
+//     travelling straight down (Sec. II.B procedure step 1, boundary eq. 6);
+//   * free flight obeys Beer-Lambert attenuation (eq. 7-8) through layers of
+//     piecewise-constant extinction (Sec. II.B step 2 uses 1000 layers);
+//   * at an interaction the photon is scattered with probability K_sca/K_ext
+//     and absorbed otherwise (eq. 11); the packet weight carries this
+//     probability (implicit capture) or a Bernoulli draw decides (analog);
+//   * a scattered photon takes a new polar angle from the phase function
+//     (eq. 13-14, or Henyey-Greenstein) and a uniform azimuth (eq. 15); only
+//     the vertical direction cosine matters in a 1-D slab with vertical
+//     velocities, so it follows the third line of eq. 16;
+//   * each scattering changes the frequency by the Doppler term of eq. 4,
+//     kept in velocity units: a scatterer of speed V moving along +z shifts
+//     the apparent velocity by V*(mu_out - mu_in)/2;
+//   * at the free surface the photon is reflected diffusely with polar angle
+//     uniform over the upper hemisphere (Sec. II.B, text after eq. 18) or by
+//     Lambert's law (option), and the moving surface adds its own shift;
+//   * photons leaving the top inside the detector cone are histogrammed by
+//     apparent velocity (eq. 19, intensity form).
+//
+// Random numbers come from Philox4x32-10 (Salmon, Moraes, Dror, Shaw,
+// "Parallel random numbers: as easy as 1, 2, 3", SC'11), one 4-word block per
+// event: counter = (event k, pid low, pid high, stream), key = seed.
+//
+// Everything is plain scalar FP64 with no blocking or reordering; threads
+// take contiguous packet ranges and their tallies are added in thread order.
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+namespace {
+
+// ---- Philox4x32-10 from its published definition (Salmon et al. 2011) ----
+// Round function: two 32x32->64 products of words 0 and 2 with the fixed
+// multipliers; the high halves are xored with the other words and the key.
+// Between rounds the key is bumped by the Weyl constants (golden ratio and
+// sqrt(3)-1 scaled to 32 bits).
+const uint32_t PHILOX_M0 = 0xD2511F53u;
+const uint32_t PHILOX_M1 = 0xCD9E8D57u;
+const uint32_t PHILOX_W0 = 0x9E3779B9u;
+const uint32_t PHILOX_W1 = 0xBB67AE85u;
+
+void philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4]) {
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) { k0 += PHILOX_W0; k1 += PHILOX_W1; }
+        uint64_t p0 = (uint64_t)PHILOX_M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)PHILOX_M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// A 32-bit word to a uniform in (0,1): the top 23 bits give an odd multiple
+// of 2^-24, exactly representable in binary32 and binary64 alike.
+double uniform_from_word(uint32_t x) {
+    return (double)(2u * (x >> 9) + 1u) * (1.0 / 16777216.0);
+}
+
+const double PI = 3.14159265358979323846;
+
+enum { PHASE_HG = 0, PHASE_TABLE = 1 };
+enum { SURFACE_UNIFORM_THETA = 0, SURFACE_LAMBERT = 1 };
+enum { WEIGHT_IMPLICIT = 0, WEIGHT_ANALOG = 1 };
+enum { SINK_UNDER = 0, SINK_OVER, SINK_UNDETECTED, SINK_ABSORBED_PARTICLE,
+       SINK_ABSORBED_SURFACE, SINK_TRUNCATED, N_SINKS };
+enum { CNT_PACKETS = 0, CNT_COLLISIONS, CNT_SURFACE, CNT_EXITS, CNT_DETECTED, CNT_FLIGHTS, N_COUNTS };
+
+}  // namespace
+
+extern "C" {
+
+typedef struct {
+    /* slab in velocity coordinate zeta = z / t (m/s); particle speed = zeta */
+    double v_bottom, v_top;
+    int n_layers;
+    const double* T;          /* n_layers+1 cumulative extinction depth from the top */
+    double tau_total;
+    /* phase function */
+    int phase_kind;           /* PHASE_HG or PHASE_TABLE */
+    double hg_g;
+    int n_angles;             /* table grid theta_j = j*pi/(n_angles-1) */
+    const uint64_t* cdf;      /* n_angles entries, cdf[0]=0, cdf[n_angles-1]=2^32 */
+    double albedo;            /* single-scattering albedo K_sca/K_ext */
+    /* free surface */
+    double v_surface, surface_albedo;
+    int surface_law;
+    /* detector and histogram */
+    double cos_cone;
+    double v_lo, v_hi;
+    int n_bins;
+    int max_orders;
+    int weighting;
+    /* packets and random streams */
+    uint64_t pid_begin, n_packets;
+    uint64_t seed;
+    uint32_t stream;
+    int n_threads;
+} oracle_params;
+
+typedef struct {
+    double* W;                /* [n_bins] sum of w per velocity bin */
+    double* W2;               /* [n_bins] sum of w^2 */
+    double* W_single;         /* [n_bins] nullable: one particle scattering, no surface */
+    double* W_surface;        /* [n_bins] nullable: no particle scattering, one surface hit */
+    double sinks[N_SINKS];
+    uint64_t counts[N_COUNTS];
+    /* detected list (nullable arrays): weight, apparent velocity, beat phase in cycles, pid */
+    uint64_t list_capacity;
+    uint64_t list_count;      /* number that would have been written (may exceed capacity) */
+    double* list_w;
+    double* list_v;
+    double* list_phase;
+    uint64_t* list_pid;
+} oracle_out;
+
+void oracle_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
+    philox4x32_10(ctr, key, out);
+}
+
+}  // extern "C"
+
+namespace {
+
+struct Tally {
+    std::vector<double> W, W2, Ws, Wsurf;
+    double sinks[N_SINKS] = {0};
+    uint64_t counts[N_COUNTS] = {0};
+    bool keep_list = false;
+    std::vector<double> lw, lv, lph;
+    std::vector<uint64_t> lpid;
+};
+
+// Layer holding depth t, searched by bisection: T[j] <= t < T[j+1].
+int find_layer(const oracle_params& p, double t) {
+    int lo = 0, hi = p.n_layers - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) / 2;
+        if (p.T[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Velocity coordinate of a collision at depth t: linear inside the layer
+// (constant extinction per layer), layer j spanning zeta from
+// v_top - j*dzeta down to v_top - (j+1)*dzeta.
+double zeta_at_depth(const oracle_params& p, double t) {
+    int j = find_layer(p, t);
+    double dzeta = (p.v_top - p.v_bottom) / p.n_layers;
+    double frac = (t - p.T[j]) / (p.T[j + 1] - p.T[j]);
+    return p.v_top - ((double)j + frac) * dzeta;
+}
+
+// Cosine and sine of the scattering angle drawn from the tabulated phase
+// function: the cell is the last j with cdf[j] <= x (an integer comparison),
+// and the angle is uniform inside the cell.
+void table_angle(const oracle_params& p, uint32_t x, double* c, double* s) {
+    int lo = 0, hi = p.n_angles - 2;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) / 2;
+        if (p.cdf[mid] <= (uint64_t)x) lo = mid; else hi = mid - 1;
+    }
+    double width = (double)(p.cdf[lo + 1] - p.cdf[lo]);
+    double f = ((double)((uint64_t)x - p.cdf[lo]) + 0.5) / width;
+    double dtheta = PI / (double)(p.n_angles - 1);
+    double theta = ((double)lo + f) * dtheta;
+    *c = std::cos(theta);
+    *s = std::sin(theta);
+}
+
+// Henyey-Greenstein polar cosine by inversion of its cumulative distribution.
+void hg_angle(double g, double u, double* c, double* s) {
+    double ct;
+    if (g == 0.0) {
+        ct = 2.0 * u - 1.0;
+    } else {
+        double q = (1.0 - g * g) / (1.0 - g + 2.0 * g * u);
+        ct = (1.0 + g * g - q * q) / (2.0 * g);
+    }
+    if (ct > 1.0) ct = 1.0;
+    if (ct < -1.0) ct = -1.0;
+    *c = ct;
+    double s2 = (1.0 - ct) * (1.0 + ct);
+    *s = std::sqrt(s2 > 0.0 ? s2 : 0.0);
+}
+
+// New vertical direction cosine after a particle scattering: polar angle
+// from the phase function, azimuth uniform (eq. 15), and the third line of the
+// direction update (eq. 16), clamped to [-1, 1].
+double scattered_mu(const oracle_params& p, double mu, uint32_t x1, double u1, double u2) {
+    double cth, sth;
+    if (p.phase_kind == PHASE_TABLE) table_angle(p, x1, &cth, &sth);
+    else hg_angle(p.hg_g, u1, &cth, &sth);
+    const double cphi = std::cos(2.0 * PI * u2);
+    double mu_new = mu * cth + std::sqrt((1.0 - mu) * (1.0 + mu)) * sth * cphi;
+    if (mu_new > 1.0) mu_new = 1.0;
+    if (mu_new < -1.0) mu_new = -1.0;
+    return mu_new;
+}
+
+void run_packet(const oracle_params& p, uint64_t pid, Tally& t) {
+    const uint32_t key[2] = {(uint32_t)(p.seed & 0xffffffffu), (uint32_t)(p.seed >> 32)};
+    const uint32_t pid_lo = (uint32_t)(pid & 0xffffffffu), pid_hi = (uint32_t)(pid >> 32);
+    const uint32_t thr_albedo = (uint32_t)std::fmin(std::floor(p.albedo * 4294967296.0), 4294967295.0);
+    const uint32_t thr_surface = (uint32_t)std::fmin(std::floor(p.surface_albedo * 4294967296.0), 4294967295.0);
+    const bool albedo_one = p.albedo >= 1.0, surface_one = p.surface_albedo >= 1.0;
+
+    double T = 0.0, mu = -1.0, w = 1.0;
+    double big = 0.0, small = 0.0;   // apparent velocity = big - small
+    int n_sc = 0, n_surf = 0;
+    t.counts[CNT_PACKETS] += 1;
+
+    for (uint32_t k = 0;; ++k) {
+        const uint32_t ctr[4] = {k, pid_lo, pid_hi, p.stream};
+        uint32_t X[4];
+        philox4x32_10(ctr, key, X);
+        t.counts[CNT_FLIGHTS] += 1;
+        const double u0 = uniform_from_word(X[0]);
+        const double u1 = uniform_from_word(X[1]);
+        const double u2 = uniform_from_word(X[2]);
+
+        // Free flight: optical path s ~ Exp(1) (Beer-Lambert), vertical
+        // depth change -s*mu.
+        const double s = -std::log(u0);
+        const double Tn = T - s * mu;
+
+        if (mu < 0.0 && Tn >= p.tau_total) {
+            // ---- free surface ----
+            t.counts[CNT_SURFACE] += 1;
+            double mu_new, one_minus_mu_new;
+            if (p.surface_law == SURFACE_LAMBERT) {
+                double r = std::sqrt(u1);
+                mu_new = r;
+                one_minus_mu_new = (1.0 - u1) / (1.0 + r);
+            } else {
+                double psi = 0.5 * PI * u1;
+                double sh = std::sin(0.5 * psi);
+                mu_new = std::cos(psi);
+                one_minus_mu_new = 2.0 * sh * sh;
+            }
+            if (p.weighting == WEIGHT_ANALOG) {
+                if (!surface_one && X[3] >= thr_surface) {
+                    t.sinks[SINK_ABSORBED_SURFACE] += w;
+                    return;
+                }
+            } else {
+                t.sinks[SINK_ABSORBED_SURFACE] += w * (1.0 - p.surface_albedo);
+                w *= p.surface_albedo;
+            }
+            big += 0.5 * p.v_surface * (1.0 - mu);
+            small += 0.5 * p.v_surface * one_minus_mu_new;
+            mu = mu_new;
+            T = p.tau_total;
+            n_surf += 1;
+            continue;
+        }
+        if (mu > 0.0 && Tn <= 0.0) {
+            // ---- leaves the top of the cloud ----
+            t.counts[CNT_EXITS] += 1;
+            if (mu >= p.cos_cone) {
+                t.counts[CNT_DETECTED] += 1;
+                const double v = big - small;
+                const double dv = (p.v_hi - p.v_lo) / (double)p.n_bins;
+                const double b = std::floor((v - p.v_lo) / dv);
+                if (b < 0.0) {
+                    t.sinks[SINK_UNDER] += w;
+                } else if (b >= (double)p.n_bins) {
+                    t.sinks[SINK_OVER] += w;
+                } else {
+                    const int ib = (int)b;
+                    t.W[ib] += w;
+                    t.W2[ib] += w * w;
+                    if (!t.Ws.empty() && n_sc == 1 && n_surf == 0) t.Ws[ib] += w;
+                    if (!t.Wsurf.empty() && n_sc == 0 && n_surf == 1) t.Wsurf[ib] += w;
+                }
+                if (t.keep_list) {
+                    // beat phase from the reserved last event block of this packet
+                    const uint32_t pctr[4] = {0xffffffffu, pid_lo, pid_hi, p.stream};
+                    uint32_t P[4];
+                    philox4x32_10(pctr, key, P);
+                    t.lw.push_back(w);
+                    t.lv.push_back(v);
+                    t.lph.push_back((double)P[0] * (1.0 / 4294967296.0));
+                    t.lpid.push_back(pid);
+                }
+            } else {
+                t.sinks[SINK_UNDETECTED] += w;
+            }
+            return;
+        }
+
+        // ---- interaction with a particle at depth Tn ----
+        t.counts[CNT_COLLISIONS] += 1;
+        const double V = zeta_at_depth(p, Tn);
+        if (n_sc == p.max_orders) {
+            t.sinks[SINK_TRUNCATED] += w;
+            return;
+        }
+        if (p.weighting == WEIGHT_ANALOG) {
+            if (!albedo_one && X[3] >= thr_albedo) {
+                t.sinks[SINK_ABSORBED_PARTICLE] += w;
+                return;
+            }
+        } else {
+            t.sinks[SINK_ABSORBED_PARTICLE] += w * (1.0 - p.albedo);
+            w *= p.albedo;
+        }
+        n_sc += 1;
+
+        const double mu_new = scattered_mu(p, mu, X[1], u1, u2);
+        big += 0.5 * V * (1.0 - mu);
+        small += 0.5 * V * (1.0 - mu_new);
+        mu = mu_new;
+        T = Tn;
+    }
+}
+
+void run_range(const oracle_params* p, uint64_t begin, uint64_t end, Tally* t) {
+    for (uint64_t pid = begin; pid < end; ++pid) run_packet(*p, pid, *t);
+}
+
+}  // namespace
+
+extern "C" {
+
+// Returns 0 on success, -1 on invalid arguments.
+int oracle_run(const oracle_params* p, oracle_out* out) {
+    if (!p || !out || p->n_bins < 1 || p->n_layers < 1 || !p->T || !out->W || !out->W2) return -1;
+    if (p->phase_kind == PHASE_TABLE && (!p->cdf || p->n_angles < 2)) return -1;
+    int nt = p->n_threads > 0 ? p->n_threads : 1;
+    if ((uint64_t)nt > p->n_packets && p->n_packets > 0) nt = (int)p->n_packets;
+    if (nt < 1) nt = 1;
+    std::vector<Tally> tallies(nt);
+    for (auto& t : tallies) {
+        t.W.assign(p->n_bins, 0.0);
+        t.W2.assign(p->n_bins, 0.0);
+        if (out->W_single) t.Ws.assign(p->n_bins, 0.0);
+        if (out->W_surface) t.Wsurf.assign(p->n_bins, 0.0);
+        t.keep_list = out->list_capacity > 0;
+    }
+    std::vector<std::thread> threads;
+    for (int i = 0; i < nt; ++i) {
+        uint64_t b = p->pid_begin + p->n_packets * (uint64_t)i / (uint64_t)nt;
+        uint64_t e = p->pid_begin + p->n_packets * (uint64_t)(i + 1) / (uint64_t)nt;
+        threads.emplace_back(run_range, p, b, e, &tallies[i]);
+    }
+    for (auto& th : threads) th.join();
+
+    for (int b = 0; b < p->n_bins; ++b) {
+        out->W[b] = 0.0; out->W2[b] = 0.0;
+        if (out->W_single) out->W_single[b] = 0.0;
+        if (out->W_surface) out->W_surface[b] = 0.0;
+    }
+    for (int s = 0; s < N_SINKS; ++s) out->sinks[s] = 0.0;
+    for (int c = 0; c < N_COUNTS; ++c) out->counts[c] = 0;
+    uint64_t n_list = 0;
+    for (int i = 0; i < nt; ++i) {
+        const Tally& t = tallies[i];
+        for (int b = 0; b < p->n_bins; ++b) {
+            out->W[b] += t.W[b];
+            out->W2[b] += t.W2[b];
+            if (out->W_single) out->W_single[b] += t.Ws[b];
+            if (out->W_surface) out->W_surface[b] += t.Wsurf[b];
+        }
+        for (int s = 0; s < N_SINKS; ++s) out->sinks[s] += t.sinks[s];
+        for (int c = 0; c < N_COUNTS; ++c) out->counts[c] += t.counts[c];
+        for (size_t j = 0; j < t.lw.size(); ++j, ++n_list) {
+            if (n_list < out->list_capacity) {
+                if (out->list_w) out->list_w[n_list] = t.lw[j];
+                if (out->list_v) out->list_v[n_list] = t.lv[j];
+                if (out->list_phase) out->list_phase[n_list] = t.lph[j];
+                if (out->list_pid) out->list_pid[n_list] = t.lpid[j];
+            }
+        }
+    }
+    out->list_count = n_list;
+    return 0;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+// Test hook: the scattering-angle sampler alone.  Draw i uses the Philox
+// block with counter (i, 0, 0, stream) and the same words the transport uses
+// (X[1] for the table cell, u1 for Henyey-Greenstein).
+int oracle_sample_scatter(const oracle_params* p, uint64_t n, double* cos_out) {
+    if (!p || !cos_out) return -1;
+    if (p->phase_kind == PHASE_TABLE && (!p->cdf || p->n_angles < 2)) return -1;
+    const uint32_t key[2] = {(uint32_t)(p->seed & 0xffffffffu), (uint32_t)(p->seed >> 32)};
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint32_t ctr[4] = {(uint32_t)i, (uint32_t)(i >> 32), 0u, p->stream};
+        uint32_t X[4];
+        philox4x32_10(ctr, key, X);
+        double c, sn;
+        if (p->phase_kind == PHASE_TABLE) table_angle(*p, X[1], &c, &sn);
+        else hg_angle(p->hg_g, uniform_from_word(X[1]), &c, &sn);
+        cos_out[i] = c;
+    }
+    return 0;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+// Test hook: one scattering of a packet travelling with direction cosine
+// mu_in; draw i uses the Philox block with counter (i, 1, 0, stream).
+int oracle_scatter_direction(const oracle_params* p, double mu_in, uint64_t n, double* mu_out) {
+    if (!p || !mu_out || mu_in < -1.0 || mu_in > 1.0) return -1;
+    if (p->phase_kind == PHASE_TABLE && (!p->cdf || p->n_angles < 2)) return -1;
+    const uint32_t key[2] = {(uint32_t)(p->seed & 0xffffffffu), (uint32_t)(p->seed >> 32)};
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint32_t ctr[4] = {(uint32_t)i, 1u, (uint32_t)(i >> 32), p->stream};
+        uint32_t X[4];
+        philox4x32_10(ctr, key, X);
+        mu_out[i] = scattered_mu(*p, mu_in, X[1], uniform_from_word(X[1]), uniform_from_word(X[2]));
+    }
+    return 0;
+}
+
+}  // extern "C"
