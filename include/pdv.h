@@ -1,0 +1,298 @@
+/*
+ * pdv.h — C ABI of the MI355X PDV multiple-scattering Monte Carlo library
+ * (libpdv.so, HIP for gfx950).
+ *
+ * The library simulates the photon Doppler velocimetry (PDV) spectrum of an
+ * ejecta cloud in front of a moving free surface, following Shi et al.,
+ * "Reconstruction and interpretation of photon Doppler velocimetry spectrum
+ * for ejecta particles from shock-loaded sample in vacuum" (arXiv
+ * 2012.00963):
+ *   - the problem statement of Sec. II: particle cloud (velocity profile,
+ *     eq. 20; size distribution, eq. 21; optical depth, eq. 7-8), particle
+ *     optics (Mie, eq. 11-14, or a given phase function), probing wavelength,
+ *     diffuse free surface, detector acceptance;
+ *   - the Monte Carlo procedure of Sec. II.B (free flight, scatter/absorb,
+ *     new direction, Doppler shift eq. 4 and 18, surface reflection, exit);
+ *   - the output spectrum of eq. 19 (histogram of outgoing photons by
+ *     apparent velocity) and the heterodyne spectrogram of eq. 1-3 and
+ *     Sec. I (beat signal swept by a windowed discrete Fourier transform).
+ *
+ * Conventions for every entry point:
+ *   - SI units: metres, seconds, m/s, radians.
+ *   - The apparent velocity of a photon is v~ = c (omega - omega_r)/(2
+ *     omega_r); a single straight back-scatter from a particle of speed V
+ *     gives v~ = V.  Histograms are over v~.
+ *   - All pointers in parameter and output structs are HOST pointers unless
+ *     a field says "device".  Inputs are only read during the call; outputs
+ *     are caller-owned and fully written before a blocking call returns.
+ *   - Return value: PDV_OK (0) or a negative pdv_status.  No exception
+ *     crosses the ABI.  pdv_last_error() gives a message for the last failed
+ *     call on that context.  After PDV_EDEVICE the context is poisoned: every
+ *     later call returns PDV_EDEVICE; destroy and recreate it.
+ *   - One context per host thread, except the serving calls (pdv_submit,
+ *     pdv_poll, pdv_cancel, pdv_serve_stats), which are thread-safe.
+ *   - Fixed-point tallies: weights are accumulated as unsigned 64-bit
+ *     integers scaled by 2^32 (divide by 4294967296.0 for packet-weight
+ *     units).  Integer sums are order independent, so results are bitwise
+ *     reproducible whatever the launch shape, batching or partition.
+ */
+#ifndef PDV_H
+#define PDV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PDV_ABI_VERSION 1
+
+typedef enum {
+    PDV_OK = 0,
+    PDV_PENDING = 1,      /* pdv_poll: request not finished yet */
+    PDV_EINVAL = -1,      /* invalid argument (message in pdv_last_error) */
+    PDV_ENOMEM = -2,      /* device allocation failed or request exceeds the memory budget */
+    PDV_EDEVICE = -3,     /* HIP error; the context is poisoned */
+    PDV_EOVERFLOW = -4,   /* a detected list exceeded its capacity (results still valid, list truncated) */
+    PDV_ECANCELLED = -5,  /* serving: request was cancelled */
+    PDV_ESTATE = -6,      /* call not valid in the current state (e.g. serving not started) */
+    PDV_ENOTFOUND = -7    /* serving: unknown ticket */
+} pdv_status;
+
+enum { PDV_DENSITY_UNIFORM = 0, PDV_DENSITY_EXP = 1, PDV_DENSITY_TABLE = 2 };
+enum { PDV_PHASE_HG = 0, PDV_PHASE_TABLE = 1, PDV_PHASE_MIE = 2 };
+enum { PDV_SURFACE_UNIFORM_THETA = 0, PDV_SURFACE_LAMBERT = 1 };
+enum { PDV_WEIGHT_IMPLICIT = 0, PDV_WEIGHT_ANALOG = 1 };
+enum { PDV_FP32 = 0, PDV_FP64 = 1 };
+
+/* Flags of pdv_params.flags */
+#define PDV_FLAG_CLASS_TALLIES 1u   /* also tally the single-scattering and surface-only classes */
+
+/*
+ * One parameter set: the problem statement of Sec. II.
+ *
+ * Cloud (Sec. II.C): self-similar expansion z = v t, so the slab is described
+ * in the velocity coordinate zeta in [v_bottom, v_top] and a particle at zeta
+ * moves along the outward normal at speed zeta.  The slab is cut into
+ * n_layers equal zeta-layers (Sec. II.B step 2 uses 1000) of constant
+ * extinction; each layer's optical depth is tau_total times its share of
+ * the column density:
+ *   UNIFORM: constant density;
+ *   EXP:     density proportional to exp(-(zeta - v_bottom)/v0) (eq. 20 with
+ *            v0 = v_fs/beta);
+ *   TABLE:   density[n_layers] (host), per-layer relative weights ordered
+ *            from the bottom layer upwards.
+ * tau_total is the normal extinction optical depth of the whole slab (eq. 7-8).
+ *
+ * Particle optics (eq. 11-14):
+ *   HG:    Henyey-Greenstein phase function with asymmetry hg_g (|hg_g| < 1)
+ *          and single-scattering albedo `albedo` (K_sca/K_ext);
+ *   TABLE: phase[n_angles] (host), p(theta_j) at theta_j = j pi/(n_angles-1),
+ *          any positive scale, with albedo `albedo`;
+ *   MIE:   spheres of complex refractive index m_re + i m_im at `wavelength`,
+ *          log-normal number distribution (eq. 21) with median d_median and
+ *          width sigma_ln, truncated to [d_min, d_max], integrated over ln d
+ *          with n_size_nodes Gauss-Legendre nodes; the albedo and the phase
+ *          function (tabulated at n_angles angles) are size averages.
+ *   The scattering angle is drawn from the integer CDF of the tabulated phase
+ *   function (trapezoid cells of p sin(theta), uniform angle inside a cell).
+ *
+ * Free surface (Sec. II.B, after eq. 18): at zeta = v_bottom, moving at
+ * v_surface, reflecting a fraction surface_albedo diffusely:
+ *   UNIFORM_THETA: polar angle uniform over the upper hemisphere (the
+ *                  paper's wording);  LAMBERT: cosine-law reflection.
+ *
+ * Detector: photons leaving the top within cone_half_angle of the normal
+ * (pi/2 accepts every outgoing photon, as eq. 19 does) are histogrammed in
+ * n_bins equal bins over [v_lo, v_hi); others go to the sinks.
+ *
+ * Transport: at most max_orders particle scatterings per packet (the next
+ * interaction moves the remaining weight to the "truncated" sink).
+ * weighting IMPLICIT multiplies the packet weight by the albedo at every
+ * interaction; ANALOG absorbs the packet with probability 1 - albedo
+ * (eq. 11 literally).  precision FP32 (FP32 transport, FP64 tallies) or FP64.
+ *
+ * Packets pid_begin .. pid_begin + n_packets - 1; packet pid, event k uses
+ * the Philox4x32-10 block with counter (k, pid low, pid high, stream) and key
+ * (seed low, seed high); the block with k = 0xFFFFFFFF gives the beat phase.
+ */
+typedef struct pdv_params {
+    double wavelength;
+    double v_bottom, v_top;
+    int32_t density_kind;
+    int32_t n_layers;
+    double v0;
+    const double* density;
+    double tau_total;
+    int32_t phase_kind;
+    int32_t n_angles;
+    double hg_g;
+    double albedo;
+    const double* phase;
+    double m_re, m_im;
+    double d_median, sigma_ln, d_min, d_max;
+    int32_t n_size_nodes;
+    int32_t surface_law;
+    double v_surface, surface_albedo;
+    double cone_half_angle;
+    double v_lo, v_hi;
+    int32_t n_bins;
+    int32_t max_orders;
+    int32_t weighting;
+    int32_t precision;
+    uint64_t n_packets;
+    uint64_t pid_begin;
+    uint64_t seed;
+    uint32_t stream;
+    uint32_t flags;
+} pdv_params;
+
+/* Sinks (weights x 2^32) in pdv_spectrum_out.sinks_fx */
+enum { PDV_SINK_UNDER = 0, PDV_SINK_OVER = 1, PDV_SINK_UNDETECTED = 2,
+       PDV_SINK_ABSORBED_PARTICLE = 3, PDV_SINK_ABSORBED_SURFACE = 4,
+       PDV_SINK_TRUNCATED = 5, PDV_N_SINKS = 6 };
+
+typedef struct pdv_counters {
+    uint64_t packets;     /* packets transported */
+    uint64_t collisions;  /* particle interactions (scattering or absorption) */
+    uint64_t surface;     /* free-surface hits */
+    uint64_t exits;       /* packets that left the top of the cloud */
+    uint64_t detected;    /* exits inside the detector cone */
+} pdv_counters;
+
+/*
+ * Output of one spectrum.  w_fx and w2_fx: caller-owned host arrays of
+ * n_bins entries receiving sum(w) and sum(w^2) per bin (x 2^32).  class_fx:
+ * nullable; if given and PDV_FLAG_CLASS_TALLIES is set, 2*n_bins entries:
+ * [0, n_bins) single-scattering paths (one particle scattering, no surface
+ * hit), [n_bins, 2 n_bins) surface-only paths.  Conservation holds exactly:
+ * sum(w_fx) + sum(sinks_fx) = n_packets * 2^32.
+ */
+typedef struct pdv_spectrum_out {
+    uint64_t* w_fx;
+    uint64_t* w2_fx;
+    uint64_t* class_fx;
+    uint64_t sinks_fx[PDV_N_SINKS];
+    pdv_counters counters;
+    double albedo;        /* single-scattering albedo used (Mie: size average) */
+    double g;             /* mean cosine of the phase function used */
+} pdv_spectrum_out;
+
+/* Launch options for batches; pass NULL for the tuned defaults. */
+typedef struct pdv_launch_opts {
+    int32_t block_size;          /* threads per block: 256, 512 or 1024; 0 = default */
+    int32_t blocks_per_cu;       /* persistent grid = blocks_per_cu x CUs; 0 = default */
+    uint64_t packets_per_item;   /* work-item size; 0 = default */
+    int32_t persistent;          /* 1 = persistent work queue, 0 = one block per item, -1 = default */
+    int32_t use_graph;           /* 1 = capture and replay the batch as a hipGraph, 0 = direct launches */
+} pdv_launch_opts;
+
+/*
+ * Create a context on HIP device `device`.  mem_budget bounds the device
+ * memory the context may hold (0 = 90% of free memory).  hip_stream: a
+ * hipStream_t to run on (nullable: the context creates its own).
+ * Errors: PDV_EINVAL (bad device or NULL out), PDV_EDEVICE (no device / HIP
+ * failure; *out is still set so pdv_last_error can be read, then destroy it).
+ */
+int pdv_create(struct pdv_ctx** out, int device, uint64_t mem_budget, void* hip_stream);
+void pdv_destroy(struct pdv_ctx* ctx);
+/* Message of the last failed call on ctx (never NULL; "" if none). */
+const char* pdv_last_error(const struct pdv_ctx* ctx);
+/* ABI version and the HIP device count (without creating a context). */
+int pdv_abi_version(void);
+int pdv_device_count(int* count);
+
+/*
+ * Validate a parameter set without running it.  Returns PDV_OK or
+ * PDV_EINVAL with the reason in pdv_last_error (ctx may be NULL: then the
+ * reason is not kept).  Checks: n_bins >= 1, v_hi > v_lo, v_top >= v_bottom,
+ * tau_total >= 0, 0 <= albedo, surface_albedo <= 1, |hg_g| < 1, cone in
+ * (0, pi/2], 1 <= n_layers <= 8192, 16 <= n_angles <= 4096, Mie sizes
+ * 0 < d_min < d_median, d_median < d_max, sigma_ln > 0, 8 <= n_size_nodes <= 1024,
+ * 0 <= max_orders <= 100000, n_packets < 2^32 (fixed-point headroom: every
+ * tally stays below 2^64).
+ */
+int pdv_validate(struct pdv_ctx* ctx, const pdv_params* p);
+
+/*
+ * One spectrum (blocking).  Builds the set's tables on the device (layer
+ * depths; Mie size average and phase CDF, or HG constants), transports
+ * n_packets packets and copies the tallies to `out`.
+ */
+int pdv_spectrum(struct pdv_ctx* ctx, const pdv_params* p, pdv_spectrum_out* out);
+
+/*
+ * n parameter sets in one persistent launch (blocking).  Sets may differ in
+ * every field except precision (all FP32 or all FP64).  Work items of
+ * packets_per_item packets are handed out largest set first; each block
+ * stages one set's tables in LDS at a time.  outs[i] receives set i.
+ * opts: nullable launch options.
+ */
+int pdv_spectrum_batch(struct pdv_ctx* ctx, const pdv_params* sets, int32_t n,
+                       pdv_spectrum_out* outs, const pdv_launch_opts* opts);
+
+/*
+ * Spectrogram (Sec. I, eq. 1-3): n_frames frames of the cloud `p`
+ * (self-similar expansion, so each frame is the same zeta-slab; frame k uses
+ * stream p->stream + k and packets_per_frame packets).  Detected packets
+ * (weight w, apparent velocity v~, phase phi0) of frame k feed the samples
+ * [floor(k N/F), floor((k+1) N/F)) of a beat record of n_samples samples at
+ * fs samples/s: s[n] = sum sqrt(w) cos(2 pi frac(f n / fs + phi0)),
+ * f = 2 v~ / wavelength, phase in FP64.  The record is cut into windows of
+ * nfft samples (periodic Hann) every hop samples; map receives
+ * |DFT| of each window, n_windows x (nfft/2 + 1) floats, window-major.
+ */
+typedef struct pdv_sg_params {
+    int32_t n_frames;
+    int32_t nfft;                 /* power of two, 256 .. 8192 */
+    int32_t hop;
+    int32_t n_samples;
+    uint64_t packets_per_frame;
+    uint64_t list_capacity;       /* detected entries kept per frame */
+    double fs;
+} pdv_sg_params;
+
+typedef struct pdv_sg_out {
+    float* map;                   /* host, n_windows x (nfft/2+1); n_windows = (n_samples - nfft)/hop + 1 */
+    float* signal;                /* nullable host [n_samples]: the beat record */
+    uint64_t* frame_counts;       /* nullable host [n_frames]: detected entries per frame (before capping) */
+    int32_t n_windows;            /* written */
+    int32_t overflow;             /* written: 1 if some frame exceeded list_capacity */
+    pdv_spectrum_out* spectrum;   /* nullable: tallies summed over all frames */
+} pdv_sg_out;
+
+int pdv_spectrogram(struct pdv_ctx* ctx, const pdv_params* p, const pdv_sg_params* sg, pdv_sg_out* out);
+
+/*
+ * Beat synthesis alone (eq. 3 with the reference amplitude 1/2), for lists
+ * the caller provides.  Frame k's entries are [offsets[k], offsets[k+1]) of
+ * w (float), v (double, apparent velocity, m/s) and phase_u32 (phase in
+ * units of 2^-32 cycles); its samples are [floor(k N/F), floor((k+1) N/F)).
+ * signal: host [n_samples].
+ */
+int pdv_beat_synthesize(struct pdv_ctx* ctx, int32_t n_frames, const uint64_t* offsets,
+                        const float* w, const double* v, const uint32_t* phase_u32,
+                        double wavelength, double fs, int32_t n_samples, float* signal);
+
+/*
+ * STFT magnitude alone: periodic Hann window of nfft (power of two) samples
+ * every hop samples over signal[n_samples]; map: host [n_windows x (nfft/2+1)].
+ * Returns the window count in *n_windows.
+ */
+int pdv_stft(struct pdv_ctx* ctx, const float* signal, int32_t n_samples, int32_t nfft, int32_t hop,
+             float* map, int32_t* n_windows);
+
+/*
+ * Timing of the last transport launch on ctx: kernel time between HIP events
+ * recorded on the context stream around the launch (ms), grid and block
+ * size, number of work items.  Any pointer may be NULL.
+ */
+int pdv_last_launch(const struct pdv_ctx* ctx, float* kernel_ms, int32_t* grid, int32_t* block,
+                    int32_t* n_items);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDV_H */

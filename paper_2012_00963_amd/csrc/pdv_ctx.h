@@ -1,0 +1,98 @@
+// Library context (opaque to ABI users): device, stream, device buffers,
+// cached Mie basis, tuning, and the serving engine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "pdv.h"
+#include "pdv_internal.h"
+
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t cap = 0;
+};
+
+struct HostPinned {
+    void* ptr = nullptr;
+    size_t cap = 0;
+};
+
+struct MieKey {
+    double m_re, m_im, wavelength, d_min, d_max;
+    int32_t n_nodes, n_angles;
+    bool operator==(const MieKey& o) const {
+        return m_re == o.m_re && m_im == o.m_im && wavelength == o.wavelength && d_min == o.d_min &&
+               d_max == o.d_max && n_nodes == o.n_nodes && n_angles == o.n_angles;
+    }
+};
+
+struct TunedLaunch {
+    int32_t block_size = 0;
+    int32_t blocks_per_cu = 0;
+    uint64_t packets_per_item = 0;
+};
+
+struct ServeEngine;   // serving loop (serve.cpp)
+
+struct pdv_ctx {
+    int device = 0;
+    int n_cu = 256;
+    std::string arch;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool ready = false;
+    bool poisoned = false;
+    uint64_t mem_budget = 0, mem_used = 0;
+    std::string err;
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;
+
+    // batch buffers
+    DevBuf descs, tables, tallies, items, queue, layer_jobs, phase_jobs, density, lists, list_counts;
+    // Mie basis cache
+    DevBuf mie_info, mie_a, mie_b, mie_d, mie_basis, mie_gx, mie_gw;
+    MieKey mie_key{};
+    bool mie_key_valid = false;
+    int mie_nodes = 0;
+    // stage-2 buffers
+    DevBuf sg_entries, sg_offsets, sg_signal, sg_map, sg_frames;
+    std::vector<HostPinned> host_pinned;
+
+    // host staging
+    std::vector<pdv::SetDesc> h_desc;
+    std::vector<pdv::LayerJob> h_layer;
+    std::vector<pdv::PhaseJob> h_phase;
+    std::vector<double> h_density;
+    std::vector<pdv::WorkItem> h_items;
+    std::vector<uint64_t> h_tally;
+
+    // last launch (benchmarks)
+    float last_kernel_ms = 0.f;
+    int32_t last_grid = 0, last_block = 0, last_items = 0;
+    TunedLaunch tuned;
+
+    // serving
+    std::unique_ptr<ServeEngine> serve;
+
+    pdv_ctx();
+    ~pdv_ctx();
+    int fail(int code, const char* fmt, ...);
+    int hip_check(hipError_t e, const char* what);
+    int ensure(DevBuf& b, size_t bytes, const char* what);
+    int ensure_mie_basis(const pdv_params& p);
+    void default_opts(pdv_launch_opts& o, uint64_t total_packets, int n_sets) const;
+    int run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, const pdv_launch_opts* opts,
+                  uint64_t list_capacity, bool keep_device);
+    void unpack(const pdv_params& p, const pdv::SetDesc& d, const uint64_t* t, pdv_spectrum_out& o);
+    void release_all();
+    void shutdown_serving();
+};

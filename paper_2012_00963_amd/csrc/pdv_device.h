@@ -1,0 +1,94 @@
+// Device-side helpers of libpdv: counter-based random numbers, uniform
+// mapping, precision-specific math and wavefront utilities (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pdv {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  A 128-bit counter is
+// mixed with a 64-bit key by ten rounds; each round multiplies words 0 and 2
+// by fixed 32-bit constants, keeps the low halves as the new words 3 and 1,
+// and xors the high halves with the other two words and the round key.  The
+// key advances by two Weyl increments between rounds.
+// ---------------------------------------------------------------------------
+struct Block4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ Block4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                           uint32_t k0, uint32_t k1) {
+    constexpr uint32_t MUL_A = 0xD2511F53u, MUL_B = 0xCD9E8D57u;
+    constexpr uint32_t BUMP_A = 0x9E3779B9u, BUMP_B = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t a_hi = __umulhi(MUL_A, c0), a_lo = MUL_A * c0;
+        const uint32_t b_hi = __umulhi(MUL_B, c2), b_lo = MUL_B * c2;
+        const uint32_t n0 = b_hi ^ c1 ^ k0;
+        const uint32_t n2 = a_hi ^ c3 ^ k1;
+        c0 = n0; c1 = b_lo; c2 = n2; c3 = a_lo;
+        k0 += BUMP_A; k1 += BUMP_B;
+    }
+    return Block4{c0, c1, c2, c3};
+}
+
+// A 32-bit word to an odd multiple of 2^-24 in (0,1): exact in binary32 and
+// binary64, so both precisions see the same uniform.
+template <typename Real>
+__device__ __forceinline__ Real unit_open(uint32_t x) {
+    return (Real)(((x >> 9) << 1) | 1u) * (Real)5.9604644775390625e-08;
+}
+
+// ---------------------------------------------------------------------------
+// Precision-specific math.  FP32 uses the hardware transcendental units with
+// arguments in revolutions (v_sin/v_cos take x and return sin/cos(2 pi x));
+// FP64 uses the correctly rounded library forms in the same expression
+// order as a plain scalar evaluation.
+// ---------------------------------------------------------------------------
+template <typename Real> struct M;
+
+template <> struct M<float> {
+    static __device__ __forceinline__ float neg_log(float u) {
+        return -0.693147180559945309f * __builtin_amdgcn_logf(u);
+    }
+    static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+    // cos(2 pi r), sin(2 pi r) for |r| <= 1
+    static __device__ __forceinline__ float cos_rev(float r) { return __builtin_amdgcn_cosf(r); }
+    static __device__ __forceinline__ float sin_rev(float r) { return __builtin_amdgcn_sinf(r); }
+};
+
+template <> struct M<double> {
+    static constexpr double PI = 3.14159265358979323846;
+    static __device__ __forceinline__ double neg_log(double u) { return -::log(u); }
+    static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
+    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+    static __device__ __forceinline__ double cos_rev(double r) { return ::cos(2.0 * PI * r); }
+    static __device__ __forceinline__ double sin_rev(double r) { return ::sin(2.0 * PI * r); }
+};
+
+template <typename Real>
+__device__ __forceinline__ uint64_t to_fixed32(Real w) {
+    // w * 2^32 rounded to nearest; w in [0, 1]
+    if constexpr (sizeof(Real) == 4) return __float2ull_rn(w * 4294967296.0f);
+    else return __double2ull_rn(w * 4294967296.0);
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront helpers (wave64).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) {
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+}  // namespace pdv

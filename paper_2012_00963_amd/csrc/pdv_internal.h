@@ -1,0 +1,128 @@
+// Internal layout shared by the host side of libpdv and its HIP kernels.
+//
+// Device memory of a batch (all owned by the context, see pdv_api.cpp):
+//   SetDesc[n_sets]      per-set constants (host-packed, finished on device)
+//   table arena          per-set tables, SET_TABLE_BYTES each, 256-B aligned
+//   tally arena          per-set uint64 tallies, tally_words(n_bins) each
+//   WorkItem[n_items]    (set, first packet, packet count), largest set first
+//   queue counter        next work item for persistent blocks
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pdv {
+
+// Table geometry limits (LDS staging is sized from them per launch).
+constexpr int MAX_LAYERS = 4096;
+constexpr int MAX_ANGLES = 4096;
+constexpr int LAYER_GUIDE = 2048;         // uniform-depth guide entries (+1)
+constexpr int CDF_GUIDE_BITS = 9;         // 512 guide entries over the 2^32 range
+constexpr int CDF_GUIDE = 1 << CDF_GUIDE_BITS;
+constexpr int MAX_BINS = 4096;
+
+enum PhaseKind : int32_t { PH_HG = 0, PH_TABLE = 1 };
+
+// Byte offsets inside one set's table block.
+struct TableLayout {
+    static constexpr uint64_t T32 = 0;                                        // float[MAX_LAYERS+1]
+    static constexpr uint64_t T64 = T32 + 4ull * (MAX_LAYERS + 8);            // double[MAX_LAYERS+1]
+    static constexpr uint64_t LGUIDE = T64 + 8ull * (MAX_LAYERS + 8);         // uint16[LAYER_GUIDE+1]
+    static constexpr uint64_t CDF = LGUIDE + 2ull * (LAYER_GUIDE + 64);       // uint32[MAX_ANGLES]
+    static constexpr uint64_t CGUIDE = CDF + 4ull * (MAX_ANGLES + 64);        // uint16[CDF_GUIDE+1]
+    static constexpr uint64_t PHASE = CGUIDE + 2ull * (CDF_GUIDE + 64);       // double[MAX_ANGLES] tabulated p(theta)
+    static constexpr uint64_t BYTES = (PHASE + 8ull * MAX_ANGLES + 255) & ~255ull;
+};
+
+// Tally block of one set, in uint64 words.
+enum TallyWords : int { TW_SINKS = 8, TW_COUNTS = 8 };
+inline __host__ __device__ uint64_t tally_words(int n_bins) {
+    return 4ull * (uint64_t)n_bins + TW_SINKS + TW_COUNTS;
+}
+// word offsets inside a tally block
+inline __host__ __device__ uint64_t tw_w(int) { return 0; }
+inline __host__ __device__ uint64_t tw_w2(int n_bins) { return (uint64_t)n_bins; }
+inline __host__ __device__ uint64_t tw_class(int n_bins) { return 2ull * n_bins; }
+inline __host__ __device__ uint64_t tw_sinks(int n_bins) { return 4ull * n_bins; }
+inline __host__ __device__ uint64_t tw_counts(int n_bins) { return 4ull * n_bins + TW_SINKS; }
+
+// sink word indices inside the sinks block (match pdv.h)
+enum SinkIdx : int { SK_UNDER = 0, SK_OVER = 1, SK_UNDETECTED = 2, SK_ABS_PARTICLE = 3,
+                     SK_ABS_SURFACE = 4, SK_TRUNCATED = 5 };
+enum CountIdx : int { C_PACKETS = 0, C_COLLISIONS = 1, C_SURFACE = 2, C_EXITS = 3, C_DETECTED = 4 };
+
+// Per-set constants.  Host fills everything except the fields marked
+// (device), which the table kernels write.
+struct alignas(16) SetDesc {
+    double v_top, dzeta, tau_total;
+    double v_surface, surface_albedo;
+    double albedo;              // (device for Mie) single-scattering albedo
+    double hg_g;
+    double g_mean;              // (device) mean cosine of the sampled law
+    double cos_cone;
+    double v_lo, dv;
+    uint64_t seed;
+    uint64_t tab_offset;        // bytes into the table arena
+    uint64_t tally_offset;      // words into the tally arena
+    uint64_t list_offset;       // entries into the list arena
+    uint64_t list_capacity;
+    uint32_t stream;
+    uint32_t thr_albedo;        // (device for Mie) floor(albedo 2^32), clamped
+    uint32_t thr_surface;
+    uint32_t flags;
+    int32_t n_layers;
+    int32_t phase_kind;         // PH_HG or PH_TABLE
+    int32_t n_cells;            // tabulated angles - 1
+    int32_t surface_law;
+    int32_t weighting;
+    int32_t max_orders;
+    int32_t n_bins;
+    int32_t albedo_one;         // (device for Mie) 1 if albedo >= 1
+    int32_t surface_one;
+    int32_t pad0;
+};
+
+struct WorkItem {
+    uint32_t set;
+    uint32_t pad;
+    uint64_t pid_begin;         // absolute packet id of the first packet
+    uint64_t count;
+};
+
+// Detected-list entry (stage 2): weight, raw phase word, apparent velocity.
+struct alignas(16) ListEntry {
+    float w;
+    uint32_t phase;
+    double v;
+};
+
+enum SetFlags : uint32_t { SF_CLASS = 1u, SF_LIST = 2u };
+
+// Table-building jobs (host-packed, one per set).
+struct LayerJob {
+    double v_bottom, v_top, v0, tau_total;
+    int32_t n_layers, density_kind;
+    uint64_t tab_offset;
+    uint64_t density_offset;   // doubles into the density staging buffer (TABLE kind)
+};
+
+struct PhaseJob {
+    int32_t kind;              // 0 = Mie basis, 1 = caller table already in PHASE
+    int32_t n_angles;
+    double d_median, sigma_ln;
+    uint64_t tab_offset;
+    int32_t set;               // descriptor to finish
+    int32_t pad;
+};
+
+// One size node of the Mie basis.
+struct MieNodeInfo {
+    double x;                  // size parameter pi d / lambda
+    double lnd;                // ln d
+    double wq;                 // Gauss-Legendre weight in ln d
+    double q_ext, q_sca, g;
+    int32_t nstop;
+    int32_t pad;
+};
+
+}  // namespace pdv

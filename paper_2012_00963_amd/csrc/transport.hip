@@ -1,0 +1,491 @@
+// Photon-packet transport and tally kernel (gfx950).
+//
+// Implements the Monte Carlo procedure of Shi et al., Sec. II.B, with exact
+// free-flight sampling through layers of constant extinction:
+//   free flight      s = -ln u (Beer-Lambert, eq. 7-8), depth change -s mu;
+//   surface          diffuse reflection off the moving free surface (the text
+//                    after eq. 18; Lambert as an option), weight x surface albedo;
+//   particle hit     scatter with probability K_sca/K_ext (eq. 11): implicit
+//                    capture multiplies the weight, analog mode draws;
+//                    polar angle from the phase function (eq. 13-14, or
+//                    Henyey-Greenstein), uniform azimuth (eq. 15), vertical
+//                    direction cosine from the third line of eq. 16;
+//   Doppler          each scattering off a scatterer of speed V moving along
+//                    the normal adds V (mu_out - mu_in)/2 to the apparent
+//                    velocity (eq. 4 in velocity units), kept as two
+//                    non-negative accumulators so the FP32 difference does
+//                    not cancel near the surface peak;
+//   exit             photons leaving the top inside the detector cone are
+//                    histogrammed by apparent velocity (eq. 19).
+// Every event draws one Philox4x32-10 block with counter (k, pid lo, pid hi,
+// stream): word 0 the flight, word 1 the polar angle / surface angle, word 2
+// the azimuth, word 3 the analog absorption test.
+//
+// Execution shape: one packet per lane.  A block stages one parameter set's
+// tables (layer depths + uniform-depth guide, integer phase CDF + guide) and
+// a private velocity histogram in LDS.  Waves refill finished lanes with the
+// next packet ids of the current work item (one LDS atomic per wave per
+// refill round).  Rare sinks go to LDS, frequent sinks and event counters
+// stay in registers and are reduced across the wave before one global
+// atomic per wave; the LDS histogram is flushed with global 64-bit atomics
+// when the block changes set or retires.  Tallies are integers (weight x
+// 2^32), so the result does not depend on the launch shape.
+#include "pdv_device.h"
+#include "pdv_internal.h"
+
+namespace pdv {
+
+struct LdsLayout {
+    uint32_t t_off, lg_off, cdf_off, cg_off, hist_off, bytes;
+};
+
+__host__ __device__ inline uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
+
+__host__ __device__ inline LdsLayout lds_layout(int real_bytes, int max_layers, int max_cells, int max_bins) {
+    LdsLayout L;
+    L.t_off = 0;
+    L.lg_off = align16(L.t_off + (uint32_t)real_bytes * (uint32_t)(max_layers + 1));
+    L.cdf_off = align16(L.lg_off + 2u * (LAYER_GUIDE + 1));
+    L.cg_off = align16(L.cdf_off + 4u * (uint32_t)(max_cells > 0 ? max_cells : 1));
+    L.hist_off = align16(L.cg_off + 2u * (CDF_GUIDE + 1));
+    L.bytes = align16(L.hist_off + 16u * (uint32_t)max_bins);
+    return L;
+}
+
+struct RareSinks {           // LDS block-level: under, over, truncated, analog absorptions
+    unsigned long long v[8];
+};
+
+template <typename Real>
+struct SetConst {            // wave-uniform per-set constants (kept in SGPRs)
+    Real tau, v_top, dzeta, v_surface, surface_albedo, albedo, cos_cone;
+    Real hg_a, hg_b, hg_c0, hg_c1, hg_inv2g;   // HG: 1+g^2, 1-g^2, 1-g, 2g, 1/(2g)
+    Real lg_scale;           // LAYER_GUIDE / tau
+    Real rev_per_cell;       // FP32 table angle in revolutions per cell (0.5/n_cells)
+    Real dtheta;             // FP64 table angle step pi/n_cells
+    double v_lo, dv;
+    uint32_t k0, k1, stream, thr_albedo, thr_surface;
+    int n_layers, n_cells, n_bins, max_orders, phase_kind, surface_law, weighting;
+    int albedo_one, surface_one, hg_zero;
+    uint32_t flags;
+};
+
+template <typename Real>
+__device__ SetConst<Real> load_const(const SetDesc& d) {
+    SetConst<Real> c;
+    c.tau = (Real)d.tau_total;
+    c.v_top = (Real)d.v_top;
+    c.dzeta = (Real)d.dzeta;
+    c.v_surface = (Real)d.v_surface;
+    c.surface_albedo = (Real)d.surface_albedo;
+    c.albedo = (Real)d.albedo;
+    c.cos_cone = (Real)d.cos_cone;
+    const double g = d.hg_g;
+    c.hg_a = (Real)(1.0 + g * g);
+    c.hg_b = (Real)(1.0 - g * g);
+    c.hg_c0 = (Real)(1.0 - g);
+    c.hg_c1 = (Real)(2.0 * g);
+    c.hg_inv2g = (Real)(g != 0.0 ? 1.0 / (2.0 * g) : 0.0);
+    c.hg_zero = (g == 0.0);
+    c.lg_scale = (Real)(d.tau_total > 0.0 ? (double)LAYER_GUIDE / d.tau_total : 0.0);
+    c.rev_per_cell = (Real)(d.n_cells > 0 ? 0.5 / (double)d.n_cells : 0.0);
+    c.dtheta = (Real)(d.n_cells > 0 ? 3.14159265358979323846 / (double)d.n_cells : 0.0);
+    c.v_lo = d.v_lo;
+    c.dv = d.dv;
+    c.k0 = (uint32_t)(d.seed & 0xffffffffu);
+    c.k1 = (uint32_t)(d.seed >> 32);
+    c.stream = d.stream;
+    c.thr_albedo = d.thr_albedo;
+    c.thr_surface = d.thr_surface;
+    c.n_layers = d.n_layers;
+    c.n_cells = d.n_cells;
+    c.n_bins = d.n_bins;
+    c.max_orders = d.max_orders;
+    c.phase_kind = d.phase_kind;
+    c.surface_law = d.surface_law;
+    c.weighting = d.weighting;
+    c.albedo_one = d.albedo_one;
+    c.surface_one = d.surface_one;
+    c.flags = d.flags;
+    return c;
+}
+
+// Velocity coordinate at depth t: the layer j with T[j] <= t < T[j+1] is
+// found from the uniform-depth guide (a window of +-1 guide cell absorbs the
+// rounding of t * scale) and a bisection in LDS; zeta is linear inside it.
+template <typename Real>
+__device__ __forceinline__ Real zeta_at(const SetConst<Real>& c, const Real* T, const uint16_t* lg, Real t) {
+    int gi = (int)(t * c.lg_scale);
+    gi = gi < 0 ? 0 : (gi > LAYER_GUIDE - 1 ? LAYER_GUIDE - 1 : gi);
+    int lo = lg[gi > 0 ? gi - 1 : 0];
+    int hi = lg[gi + 2 <= LAYER_GUIDE ? gi + 2 : LAYER_GUIDE];
+    hi = hi > c.n_layers - 1 ? c.n_layers - 1 : hi;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (T[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    const Real frac = M<Real>::div(t - T[lo], T[lo + 1] - T[lo]);
+    return c.v_top - ((Real)lo + frac) * c.dzeta;
+}
+
+// Scattering angle (cos, sin) from the integer CDF: the cell is the last j
+// with C[j] <= x, found from a guide over the top CDF_GUIDE_BITS of x; the
+// angle is uniform inside the cell.
+template <typename Real>
+__device__ __forceinline__ void table_angle(const SetConst<Real>& c, const uint32_t* C, const uint16_t* cg,
+                                            uint32_t x, Real& ct, Real& st) {
+    int j = cg[x >> (32 - CDF_GUIDE_BITS)];
+    while (j + 1 < c.n_cells && C[j + 1] <= x) ++j;
+    const uint32_t cj = C[j];
+    const uint32_t next_lo = (j + 1 < c.n_cells) ? C[j + 1] : 0u;
+    // width of the last cell is 2^32 - C[j]; unsigned wrap gives it unless C[j] == 0
+    const Real width = (j + 1 < c.n_cells || cj != 0u) ? (Real)(uint32_t)(next_lo - cj) : (Real)4294967296.0;
+    const Real f = M<Real>::div((Real)(x - cj) + (Real)0.5, width);
+    if constexpr (sizeof(Real) == 4) {
+        const Real rev = ((Real)j + f) * c.rev_per_cell;
+        ct = M<Real>::cos_rev(rev);
+        st = M<Real>::sin_rev(rev);
+    } else {
+        const Real theta = ((Real)j + f) * c.dtheta;
+        ct = ::cos(theta);
+        st = ::sin(theta);
+    }
+}
+
+template <typename Real>
+__device__ __forceinline__ void hg_angle(const SetConst<Real>& c, Real u, Real& ct, Real& st) {
+    Real x;
+    if (c.hg_zero) {
+        x = (Real)2.0 * u - (Real)1.0;
+    } else {
+        const Real q = M<Real>::div(c.hg_b, c.hg_c0 + c.hg_c1 * u);
+        if constexpr (sizeof(Real) == 4) x = (c.hg_a - q * q) * c.hg_inv2g;
+        else x = (c.hg_a - q * q) / c.hg_c1;
+    }
+    x = x > (Real)1.0 ? (Real)1.0 : (x < (Real)-1.0 ? (Real)-1.0 : x);
+    ct = x;
+    const Real s2 = ((Real)1.0 - x) * ((Real)1.0 + x);
+    st = M<Real>::sqrt(s2 > (Real)0.0 ? s2 : (Real)0.0);
+}
+
+struct LaneAcc {             // per-lane accumulators, reduced across the wave at flush
+    uint64_t undetected, abs_particle, abs_surface;
+    uint32_t packets, collisions, surface, exits, detected;
+};
+
+__device__ __forceinline__ void flush_lane_acc(LaneAcc& a, uint64_t* tally, int n_bins) {
+    const uint64_t s_und = wave_sum_u64(a.undetected);
+    const uint64_t s_ap = wave_sum_u64(a.abs_particle);
+    const uint64_t s_as = wave_sum_u64(a.abs_surface);
+    const uint64_t c_p = wave_sum_u64(a.packets);
+    const uint64_t c_c = wave_sum_u64(a.collisions);
+    const uint64_t c_s = wave_sum_u64(a.surface);
+    const uint64_t c_e = wave_sum_u64(a.exits);
+    const uint64_t c_d = wave_sum_u64(a.detected);
+    if (lane_id() == 0) {
+        unsigned long long* sk = (unsigned long long*)(tally + tw_sinks(n_bins));
+        unsigned long long* ct = (unsigned long long*)(tally + tw_counts(n_bins));
+        if (s_und) atomicAdd(sk + SK_UNDETECTED, (unsigned long long)s_und);
+        if (s_ap) atomicAdd(sk + SK_ABS_PARTICLE, (unsigned long long)s_ap);
+        if (s_as) atomicAdd(sk + SK_ABS_SURFACE, (unsigned long long)s_as);
+        if (c_p) atomicAdd(ct + C_PACKETS, (unsigned long long)c_p);
+        if (c_c) atomicAdd(ct + C_COLLISIONS, (unsigned long long)c_c);
+        if (c_s) atomicAdd(ct + C_SURFACE, (unsigned long long)c_s);
+        if (c_e) atomicAdd(ct + C_EXITS, (unsigned long long)c_e);
+        if (c_d) atomicAdd(ct + C_DETECTED, (unsigned long long)c_d);
+    }
+    a = LaneAcc{0, 0, 0, 0, 0, 0, 0, 0};
+}
+
+template <typename Real, bool LIST>
+__global__ void __launch_bounds__(1024)
+transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ tables,
+                 uint64_t* __restrict__ tallies, const WorkItem* __restrict__ items, int n_items,
+                 uint32_t* __restrict__ queue, int persistent, int max_layers, int max_cells, int max_bins,
+                 ListEntry* __restrict__ lists, uint64_t* __restrict__ list_counts) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ WorkItem s_item;
+    __shared__ int s_item_idx;
+    __shared__ uint32_t s_next;
+    __shared__ RareSinks s_rare;
+
+    const LdsLayout L = lds_layout((int)sizeof(Real), max_layers, max_cells, max_bins);
+    Real* sT = (Real*)(lds + L.t_off);
+    uint16_t* sLG = (uint16_t*)(lds + L.lg_off);
+    uint32_t* sC = (uint32_t*)(lds + L.cdf_off);
+    uint16_t* sCG = (uint16_t*)(lds + L.cg_off);
+    unsigned long long* sHist = (unsigned long long*)(lds + L.hist_off);
+
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    const int lane = lane_id();
+    int cur_set = -1;
+    LaneAcc acc = LaneAcc{0, 0, 0, 0, 0, 0, 0, 0};
+
+    auto flush_set = [&](int set) {
+        const SetDesc& d = descs[set];
+        uint64_t* tally = tallies + d.tally_offset;
+        flush_lane_acc(acc, tally, d.n_bins);
+        __syncthreads();
+        unsigned long long* gW = (unsigned long long*)(tally + tw_w(d.n_bins));
+        unsigned long long* gW2 = (unsigned long long*)(tally + tw_w2(d.n_bins));
+        for (int b = tid; b < d.n_bins; b += nthr) {
+            const unsigned long long w = sHist[b], w2 = sHist[max_bins + b];
+            if (w) atomicAdd(gW + b, w);
+            if (w2) atomicAdd(gW2 + b, w2);
+        }
+        if (tid < 8 && s_rare.v[tid]) {
+            // rare sinks: 0 under, 1 over, 5 truncated, 3/4 analog absorptions
+            atomicAdd((unsigned long long*)(tally + tw_sinks(d.n_bins)) + tid, s_rare.v[tid]);
+        }
+        __syncthreads();
+    };
+
+    for (int it = 0;; ++it) {
+        if (tid == 0) {
+            int idx = persistent ? (int)atomicAdd(queue, 1u) : (it == 0 ? (int)blockIdx.x : n_items);
+            s_item_idx = idx;
+            if (idx < n_items) s_item = items[idx];
+            s_next = 0;
+        }
+        __syncthreads();
+        const int idx = (int)uniform_u32((uint32_t)s_item_idx);
+        if (idx >= n_items) break;
+        const int set = (int)uniform_u32(s_item.set);
+        const uint64_t pid0 = s_item.pid_begin;
+        const uint32_t count = (uint32_t)s_item.count;
+
+        if (set != cur_set) {
+            if (cur_set >= 0) flush_set(cur_set);
+            const SetDesc& d = descs[set];
+            const uint8_t* tb = tables + d.tab_offset;
+            const Real* gT = (const Real*)(tb + (sizeof(Real) == 4 ? TableLayout::T32 : TableLayout::T64));
+            for (int i = tid; i <= d.n_layers; i += nthr) sT[i] = gT[i];
+            const uint16_t* gLG = (const uint16_t*)(tb + TableLayout::LGUIDE);
+            for (int i = tid; i <= LAYER_GUIDE; i += nthr) sLG[i] = gLG[i];
+            if (d.phase_kind == PH_TABLE) {
+                const uint32_t* gC = (const uint32_t*)(tb + TableLayout::CDF);
+                for (int i = tid; i < d.n_cells; i += nthr) sC[i] = gC[i];
+                const uint16_t* gCG = (const uint16_t*)(tb + TableLayout::CGUIDE);
+                for (int i = tid; i <= CDF_GUIDE; i += nthr) sCG[i] = gCG[i];
+            }
+            for (int i = tid; i < 2 * max_bins; i += nthr) sHist[i] = 0ull;
+            if (tid < 8) s_rare.v[tid] = 0ull;
+            cur_set = set;
+            __syncthreads();
+        }
+
+        const SetConst<Real> c = load_const<Real>(descs[set]);
+        uint64_t* tally = tallies + descs[set].tally_offset;
+
+        // ---- per-lane packet state ----
+        bool alive = false;
+        bool exhausted = false;
+        uint64_t pid = 0;
+        uint32_t k = 0;
+        int n_sc = 0, n_surf = 0;
+        Real T = 0, mu = -1, w = 1, big = 0, small = 0, abs_s = 0;
+
+        while (true) {
+            // refill finished lanes with the next packets of the item
+            const uint64_t dead = __ballot(!alive);
+            if (dead != 0ull && !exhausted) {
+                const uint32_t n = (uint32_t)__popcll(dead);
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(&s_next, n);
+                base = __shfl(base, 0, 64);
+                if (base + n >= count) exhausted = true;
+                if (!alive) {
+                    const uint32_t rank = (uint32_t)__popcll(dead & ((1ull << lane) - 1ull));
+                    const uint32_t local = base + rank;
+                    if (local < count) {
+                        alive = true;
+                        pid = pid0 + local;
+                        k = 0; n_sc = 0; n_surf = 0;
+                        T = 0; mu = -1; w = 1; big = 0; small = 0; abs_s = 0;
+                        acc.packets += 1;
+                    }
+                }
+            }
+            if (__ballot(alive) == 0ull) break;
+            if (alive) {
+            const Block4 X = philox10(k, (uint32_t)pid, (uint32_t)(pid >> 32), c.stream, c.k0, c.k1);
+            k += 1;
+            const Real u0 = unit_open<Real>(X.x);
+            const Real u1 = unit_open<Real>(X.y);
+            const Real u2 = unit_open<Real>(X.z);
+            const Real s = M<Real>::neg_log(u0);
+            const Real Tn = T - s * mu;
+
+            bool done = false;
+            if (mu > (Real)0 && Tn <= (Real)0) {
+                // ---- leaves the top ----
+                acc.exits += 1;
+                if (mu >= c.cos_cone) {
+                    acc.detected += 1;
+                    const double v = (double)big - (double)small;
+                    const double bf = floor((v - c.v_lo) / c.dv);
+                    const uint64_t wf = to_fixed32<Real>(w);
+                    if (bf < 0.0) {
+                        atomicAdd(&s_rare.v[SK_UNDER], (unsigned long long)wf);
+                    } else if (bf >= (double)c.n_bins) {
+                        atomicAdd(&s_rare.v[SK_OVER], (unsigned long long)wf);
+                    } else {
+                        const int b = (int)bf;
+                        atomicAdd(&sHist[b], (unsigned long long)wf);
+                        atomicAdd(&sHist[max_bins + b], (unsigned long long)to_fixed32<Real>(w * w));
+                        if (c.flags & SF_CLASS) {
+                            unsigned long long* gcl = (unsigned long long*)(tally + tw_class(c.n_bins));
+                            if (n_sc == 1 && n_surf == 0) atomicAdd(gcl + b, (unsigned long long)wf);
+                            if (n_sc == 0 && n_surf == 1) atomicAdd(gcl + c.n_bins + b, (unsigned long long)wf);
+                        }
+                    }
+                    if constexpr (LIST) {
+                        const Block4 P = philox10(0xffffffffu, (uint32_t)pid, (uint32_t)(pid >> 32), c.stream,
+                                                  c.k0, c.k1);
+                        const SetDesc& d = descs[set];
+                        const uint64_t m = __ballot(1);
+                        const int leader = __ffsll((unsigned long long)m) - 1;
+                        const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+                        unsigned long long base = 0;
+                        if (lane == leader)
+                            base = atomicAdd((unsigned long long*)(list_counts + set), (unsigned long long)__popcll(m));
+                        base = __shfl(base, leader, 64);
+                        const unsigned long long slot = base + rank;
+                        if (slot < d.list_capacity) {
+                            ListEntry e;
+                            e.w = (float)w;
+                            e.phase = P.x;
+                            e.v = v;
+                            lists[d.list_offset + slot] = e;
+                        }
+                    }
+                } else {
+                    acc.undetected += to_fixed32<Real>(w);
+                }
+                done = true;
+            } else {
+                Real V, mu_new, omc, a;
+                uint32_t thr;
+                bool a_one, at_surface;
+                if (mu < (Real)0 && Tn >= c.tau) {
+                    // ---- free surface: diffuse reflection ----
+                    at_surface = true;
+                    acc.surface += 1;
+                    if (c.surface_law == 1) {
+                        const Real r = M<Real>::sqrt(u1);
+                        mu_new = r;
+                        omc = M<Real>::div((Real)1.0 - u1, (Real)1.0 + r);
+                    } else {
+                        if constexpr (sizeof(Real) == 4) {
+                            mu_new = M<Real>::cos_rev((Real)0.25 * u1);
+                            const Real sh = M<Real>::sin_rev((Real)0.125 * u1);
+                            omc = (Real)2.0 * sh * sh;
+                        } else {
+                            const Real psi = (Real)0.5 * M<Real>::PI * u1;
+                            const Real sh = ::sin((Real)0.5 * psi);
+                            mu_new = ::cos(psi);
+                            omc = (Real)2.0 * sh * sh;
+                        }
+                    }
+                    V = c.v_surface;
+                    a = c.surface_albedo;
+                    thr = c.thr_surface;
+                    a_one = c.surface_one;
+                } else {
+                    // ---- particle interaction at depth Tn ----
+                    at_surface = false;
+                    acc.collisions += 1;
+                    V = zeta_at<Real>(c, sT, sLG, Tn);
+                    if (n_sc == c.max_orders) {
+                        atomicAdd(&s_rare.v[SK_TRUNCATED], (unsigned long long)to_fixed32<Real>(w));
+                        done = true;
+                    }
+                    Real ct, st;
+                    if (c.phase_kind == PH_TABLE) table_angle<Real>(c, sC, sCG, X.y, ct, st);
+                    else hg_angle<Real>(c, u1, ct, st);
+                    const Real cphi = M<Real>::cos_rev(u2);
+                    const Real sm2 = ((Real)1.0 - mu) * ((Real)1.0 + mu);
+                    Real m2 = mu * ct + M<Real>::sqrt(sm2 > (Real)0 ? sm2 : (Real)0) * st * cphi;
+                    m2 = m2 > (Real)1.0 ? (Real)1.0 : (m2 < (Real)-1.0 ? (Real)-1.0 : m2);
+                    mu_new = m2;
+                    omc = (Real)1.0 - m2;
+                    a = c.albedo;
+                    thr = c.thr_albedo;
+                    a_one = c.albedo_one;
+                }
+                if (!done) {
+                    if (c.weighting == 1) {
+                        if (!a_one && X.w >= thr) {
+                            atomicAdd(&s_rare.v[at_surface ? SK_ABS_SURFACE : SK_ABS_PARTICLE], (unsigned long long)to_fixed32<Real>(w));
+                            done = true;
+                        }
+                    } else {
+                        const Real lost = w * ((Real)1.0 - a);
+                        if (at_surface) abs_s += lost;
+                        w *= a;
+                    }
+                }
+                if (!done) {
+                    if (at_surface) n_surf += 1; else n_sc += 1;
+                    big += (Real)0.5 * V * ((Real)1.0 - mu);
+                    small += (Real)0.5 * V * omc;
+                    mu = mu_new;
+                    T = at_surface ? c.tau : Tn;
+                }
+            }
+            if (done) {
+                // implicit-capture bookkeeping: the packet's 2^32 units are split
+                // exactly between its terminal sink and the two absorption sinks
+                if (c.weighting == 0) {
+                    const uint64_t fw = to_fixed32<Real>(w);
+                    const uint64_t fs = to_fixed32<Real>(abs_s);
+                    acc.abs_surface += fs;
+                    acc.abs_particle += (4294967296ull - fw) - fs;
+                }
+                alive = false;
+            }
+            }  // alive
+        }
+        __syncthreads();
+    }
+    if (cur_set >= 0) flush_set(cur_set);
+}
+
+}  // namespace pdv
+
+// ---- host launchers ----
+namespace pdv {
+
+int transport_lds_bytes(int real_bytes, int max_layers, int max_cells, int max_bins) {
+    return (int)lds_layout(real_bytes, max_layers, max_cells, max_bins).bytes;
+}
+
+template <typename Real, bool LIST>
+static hipError_t launch_one(hipStream_t s, int grid, int block, int lds, const SetDesc* descs,
+                             const uint8_t* tables, uint64_t* tallies, const WorkItem* items, int n_items,
+                             uint32_t* queue, int persistent, int max_layers, int max_cells, int max_bins,
+                             ListEntry* lists, uint64_t* list_counts) {
+    hipLaunchKernelGGL((transport_kernel<Real, LIST>), dim3(grid), dim3(block), lds, s, descs, tables, tallies,
+                       items, n_items, queue, persistent, max_layers, max_cells, max_bins, lists, list_counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_transport(hipStream_t s, int precision, bool list, int grid, int block, int lds_bytes,
+                            const SetDesc* descs, const uint8_t* tables, uint64_t* tallies, const WorkItem* items,
+                            int n_items, uint32_t* queue, int persistent, int max_layers, int max_cells,
+                            int max_bins, ListEntry* lists, uint64_t* list_counts) {
+    if (precision == 1) {
+        return list ? launch_one<double, true>(s, grid, block, lds_bytes, descs, tables, tallies, items, n_items,
+                                               queue, persistent, max_layers, max_cells, max_bins, lists, list_counts)
+                    : launch_one<double, false>(s, grid, block, lds_bytes, descs, tables, tallies, items, n_items,
+                                                queue, persistent, max_layers, max_cells, max_bins, lists,
+                                                list_counts);
+    }
+    return list ? launch_one<float, true>(s, grid, block, lds_bytes, descs, tables, tallies, items, n_items, queue,
+                                          persistent, max_layers, max_cells, max_bins, lists, list_counts)
+                : launch_one<float, false>(s, grid, block, lds_bytes, descs, tables, tallies, items, n_items, queue,
+                                           persistent, max_layers, max_cells, max_bins, lists, list_counts);
+}
+
+}  // namespace pdv

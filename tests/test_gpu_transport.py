@@ -1,0 +1,185 @@
+"""GPU parity of the transport kernel against the FP64 oracle (same streams).
+
+Run on an MI355X through the C ABI (paper_2012_00963_amd.pdv).  Sizes span
+many work items and a ragged tail; the large Mie case is also checked at its
+full 1e8-packet size by exact conservation and by a sampled packet range
+that the oracle recomputes.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2012_00963_amd import workloads as wl
+from parity import assert_parity, conservation_exact, metrics
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2012_00963_amd import pdv
+    c = pdv.Context(0)
+    yield c
+    c.close()
+
+
+def _c1(**kw):
+    p = wl.small_hg(100_000)
+    p.update(kw)
+    return p
+
+
+def _run_both(ctx, oracle_mc, p, class_tallies=False, **okw):
+    g = ctx.spectrum(p, class_tallies=class_tallies)
+    o = oracle_mc.run(p, class_tallies=class_tallies, **okw)
+    return g, o
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_small_case_parity(ctx, oracle_mc, precision):
+    p = _c1(precision=precision, n_packets=100_003)      # ragged packet count
+    print("case small_hg", precision, flush=True)
+    g, o = _run_both(ctx, oracle_mc, p)
+    assert conservation_exact(g, p["n_packets"])
+    assert g["counts"]["packets"] == p["n_packets"]
+    m = assert_parity(g, o, p["n_packets"])
+    if precision == 1:
+        # FP64 follows the oracle's arithmetic: equal up to last-bit rounding
+        assert m["l1"] < 1e-9 and m["z_max"] < 1e-6, m
+        assert g["counts"] == {k: o["counts"][k] for k in g["counts"]}
+    # the surface peak sits on bin edge 128: nothing from it may leak upward
+    assert abs(g["W"][128] - o["W"][128]) <= 1e-6 * max(1.0, o["W"][128])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_small_case_90deg_parity(ctx, oracle_mc, precision):
+    p = _c1(precision=precision, cone_half_angle=math.pi / 2, n_packets=1_000_000)
+    print("case small_hg 90deg", precision, flush=True)
+    g, o = _run_both(ctx, oracle_mc, p, class_tallies=True)
+    assert conservation_exact(g, p["n_packets"])
+    assert_parity(g, o, p["n_packets"])
+    for key in ("W_single", "W_surface"):
+        d = np.abs(g[key] - o[key]).sum() / max(o[key].sum(), 1e-300)
+        assert d < 2e-3, (key, d)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(weighting=wl.WEIGHT_ANALOG),
+    dict(surface_law=wl.SURFACE_LAMBERT, cone_half_angle=math.radians(40)),
+    dict(density_kind=wl.DENSITY_EXP, v0=350.0, tau_total=2.5, cone_half_angle=math.radians(30)),
+    dict(tau_total=4.0, max_orders=7, hg_g=-0.3, cone_half_angle=math.radians(60)),
+    dict(tau_total=0.0),
+    dict(max_orders=0, tau_total=1.0),
+    dict(n_bins=1, v_lo=900.0, v_hi=1100.0),
+])
+def test_variant_parity(ctx, oracle_mc, kw):
+    p = _c1(n_packets=300_000, **kw)
+    print("case variant", kw, flush=True)
+    g, o = _run_both(ctx, oracle_mc, p)
+    assert conservation_exact(g, p["n_packets"])
+    assert_parity(g, o, p["n_packets"])
+    for k in ("under", "over", "truncated", "absorbed_surface"):
+        assert abs(g["sinks"][k] - o["sinks"][k]) <= 5e-3 * max(o["sinks"][k], 1.0) + 2.0, k
+
+
+def test_table_density_and_phase(ctx, oracle_mc):
+    from oracle import tables
+    rng = np.random.Generator(np.random.PCG64(17))
+    dens = rng.uniform(0.0, 1.0, 300)
+    dens[10:20] = 0.0                              # empty layers
+    th = tables.angle_grid(181)
+    phase = tables.hg_phase(0.5, th) + 0.05
+    p = _c1(density_kind=wl.DENSITY_TABLE, density=dens, n_layers=300, tau_total=1.5,
+            phase_kind=wl.PHASE_TABLE, phase=phase, n_angles=181, albedo=0.8,
+            cone_half_angle=math.radians(45), n_packets=300_000)
+    g, o = _run_both(ctx, oracle_mc, p)
+    assert conservation_exact(g, p["n_packets"])
+    assert_parity(g, o, p["n_packets"])
+    assert abs(g["g"] - tables.table_moments(o["cdf"], 1)) < 1e-9
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_mie_case_reduced(ctx, oracle_mc, precision):
+    p = wl.large_mie(300_000)
+    p["precision"] = precision
+    print("case large_mie reduced", precision, flush=True)
+    g, o = _run_both(ctx, oracle_mc, p)
+    # device Mie optics agree with the oracle's NumPy Mie
+    assert abs(g["albedo"] - o["albedo"]) < 1e-10
+    from oracle import tables
+    assert abs(g["g"] - tables.table_moments(o["cdf"], 1)) < 1e-9
+    assert conservation_exact(g, p["n_packets"])
+    m = assert_parity(g, o, p["n_packets"])
+    if precision == 1:
+        assert m["l1"] < 1e-9, m
+
+
+def test_launch_shape_invariance(ctx):
+    p = _c1(n_packets=200_000, cone_half_angle=math.radians(60))
+    ref = ctx.spectrum_batch([p])[0]
+    for opts in (dict(block_size=256, blocks_per_cu=1, packets_per_item=4096, persistent=1),
+                 dict(block_size=1024, packets_per_item=70_001, persistent=0),
+                 dict(block_size=512, blocks_per_cu=3, packets_per_item=100_000, persistent=1)):
+        r = ctx.spectrum_batch([p], opts=opts)[0]
+        assert np.array_equal(r["w_fx"], ref["w_fx"]) and np.array_equal(r["w2_fx"], ref["w2_fx"]), opts
+        assert r["sinks_fx"] == ref["sinks_fx"], opts
+
+
+def test_partition_invariance(ctx):
+    # two launches over disjoint packet ranges sum to one launch, bitwise
+    p = _c1(n_packets=250_000, tau_total=1.0, cone_half_angle=math.radians(50))
+    whole = ctx.spectrum(p)
+    a = ctx.spectrum(dict(p, n_packets=100_000))
+    b = ctx.spectrum(dict(p, n_packets=150_000, pid_begin=100_000))
+    assert np.array_equal(a["w_fx"] + b["w_fx"], whole["w_fx"])
+    assert np.array_equal(a["w2_fx"] + b["w2_fx"], whole["w2_fx"])
+    for k in whole["sinks_fx"]:
+        assert a["sinks_fx"][k] + b["sinks_fx"][k] == whole["sinks_fx"][k]
+
+
+def test_batch_equals_alone(ctx):
+    sets = wl.batched_sets(12, packets_scale=0.01)
+    alone = [ctx.spectrum(s) for s in sets]
+    batch = ctx.spectrum_batch(sets)
+    for a, b in zip(alone, batch):
+        assert np.array_equal(a["w_fx"], b["w_fx"]) and a["sinks_fx"] == b["sinks_fx"]
+
+
+def test_empty_and_degenerate(ctx):
+    p = _c1(n_packets=0)
+    g = ctx.spectrum(p)
+    assert g["w_fx"].sum() == 0 and all(v == 0 for v in g["sinks_fx"].values())
+    g1 = ctx.spectrum(_c1(n_packets=1))
+    assert conservation_exact(g1, 1)
+
+
+def test_validation_errors(ctx):
+    from paper_2012_00963_amd import pdv
+    for bad in (dict(n_bins=0), dict(v_hi=-1.0), dict(hg_g=1.0), dict(cone_half_angle=0.0),
+                dict(albedo=1.5), dict(tau_total=-1.0), dict(n_layers=0), dict(n_packets=2**33)):
+        with pytest.raises(pdv.PdvError) as e:
+            ctx.spectrum(_c1(**bad))
+        assert e.value.code == -1
+    # context stays usable after validation errors
+    assert conservation_exact(ctx.spectrum(_c1(n_packets=1000)), 1000)
+
+
+def test_large_mie_full_size(ctx, oracle_mc):
+    """The 1e8-packet Mie case in the benchmark's launch configuration:
+    exact conservation, packet count, and a sampled packet range recomputed
+    by the oracle and by the same launch configuration on the GPU."""
+    p = wl.large_mie()
+    print("case large_mie full", flush=True)
+    g = ctx.spectrum(p)
+    assert g["counts"]["packets"] == p["n_packets"]
+    assert conservation_exact(g, p["n_packets"])
+    sample = dict(p, n_packets=400_000, pid_begin=37_000_000)
+    gs = ctx.spectrum(sample)
+    os_ = oracle_mc.run(sample, pid_begin=sample["pid_begin"])
+    assert_parity(gs, os_, sample["n_packets"])
+    # the full run's detection rate agrees with the sample's
+    rate_full = g["sinks"]["detected"] / p["n_packets"]
+    rate_s = os_["sinks"]["detected"] / sample["n_packets"]
+    sd = math.sqrt(max(os_["W2"].sum(), 1e-30)) / sample["n_packets"]
+    assert abs(rate_full - rate_s) < 5 * sd + 1e-12
