@@ -1,0 +1,241 @@
+#!/usr/bin/env python3
+"""Benchmark of the PDV multiple-scattering Monte Carlo on one MI355X.
+
+One step = one complete spectrum of the large Mie workload: device table
+build (Gauss-Legendre size quadrature, Mie basis cached after the first
+step, size-averaged phase function and albedo, integer phase CDF, layer
+depths), transport of 1e8 photon packets in FP32 with fixed-point tallies,
+and the copy of the tallies to the host.  The headline value is scatter
+events per second (particle interactions + free-surface hits) over the
+timed steps.
+
+Also reported on the same JSON line:
+  roofline      the transport kernel's algorithmic issue rate (32-bit lane
+                operations per event x events / kernel time from HIP events
+                on the library stream) against the VALU issue peak;
+  cpu_baseline  the FP64 oracle on the host cores over a bounded packet
+                sample of the same workload;
+  extra         FP64 ("plain") spectrum of the same workload and its error
+                against FP32, plus optional legs (--legs).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+                       [--legs batched,spectrogram] [--calib-copy BYTES]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Issue-slot cost of one scatter event in the transport kernel, counted from
+# the algorithm: Philox4x32-10 (10 rounds x
+# 2 mul_hi + 2 mul_lo + 4 xor = 80), three uniforms (12), flight (3),
+# branch tests (4), layer/angle lookup (13), angle sampling (11), azimuth (1),
+# rotation (8), Doppler (6), weight (4): 142 full-rate lane operations, of
+# which 6 are transcendental (log, rcp, 2 sqrt, sin/cos) and occupy 4 issue
+# slots each: 142 + 6 * 3 = 160 slots.
+SLOTS_PER_EVENT = 160
+FP32_FLOPS_PER_EVENT = 40
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane operations/s
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+FP32_PEAK_TFLOPS = 157.3
+
+METRIC = "scatter events/s; spectra/s batched-FP32 vs plain-FP64 at <=1% error; p99 lat"
+KERNEL_SOURCES = ("paper_2012_00963_amd/csrc/transport.hip", "paper_2012_00963_amd/csrc/pdv_device.h",
+                  "paper_2012_00963_amd/csrc/pdv_internal.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "transport_large_mie_hbm_traffic.txt")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic():
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel sources; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m_hash = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", txt)
+    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m_hash or not m_b or m_hash.group(1) != kernel_hash():
+        return None
+    return float(m_b.group(1))
+
+
+def l1_err(a, b):
+    import numpy as np
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    s = b.sum()
+    return float(np.abs(a - b).sum() / s) if s > 0 else 0.0
+
+
+def run_calib_copy(nbytes: int):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    import torch
+    n = nbytes // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda")
+    b = torch.empty(n, dtype=torch.float32, device="cuda")
+    a.fill_(1.0)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes_each_way": n * 4, "launches": 3}))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
+    ap.add_argument("--legs", default="", help="comma list of extra legs: batched,spectrogram")
+    ap.add_argument("--cpu-sample", type=int, default=20_000_000, help="packets in the oracle sample")
+    ap.add_argument("--calib-copy", type=int, default=0, help="only run a copy of this many bytes")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the transport would shard by packet-id ranges with one all-reduce of the tallies; "
+              "see DESIGN.md)", file=sys.stderr)
+        return 2
+    if args.calib_copy:
+        run_calib_copy(args.calib_copy)
+        return 0
+
+    import numpy as np
+    import torch
+    from paper_2012_00963_amd import pdv, workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    ctx = pdv.Context(0)
+    p = workloads.large_mie()
+    n_packets = p["n_packets"]
+
+    for _ in range(args.warmup):
+        ctx.spectrum(p)
+    torch.cuda.synchronize()
+    kernel_ms = []
+    t0 = time.perf_counter()
+    res = None
+    for _ in range(args.steps):
+        res = ctx.spectrum(p)
+        kernel_ms.append(ctx.last_launch()["kernel_ms"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launch = ctx.last_launch()
+    wall = t1 - t0
+    c = res["counts"]
+    events = c["collisions"] + c["surface"]
+    value = events * args.steps / wall
+    k_ms = float(np.mean(kernel_ms))
+    achieved_tops = events * SLOTS_PER_EVENT / (k_ms * 1e-3) / 1e12
+    conserved = (int(np.sum(res["w_fx"], dtype=np.uint64)) + sum(res["sinks_fx"].values())) == n_packets * 2**32
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "scatter events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "large Mie cloud: 1e8 packets, log-normal d (median 3 um, sigma 0.5, 0.5-20 um), "
+                        "m=2+4i at 1550 nm, 2048-angle phase CDF, exp(-(v-1.5 km/s)/0.4 km/s) density "
+                        "to 4 km/s, tau 2, cap 50 orders, 1024 bins, FP32 transport, fixed-point tallies",
+            "packets": n_packets,
+            "events_per_step": events,
+            "events_per_packet": events / n_packets,
+            "launch": launch,
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved_tops,
+            "peak": VALU_PEAK_TOPS,
+            "unit": "T lane-op slots/s",
+            "frac": achieved_tops / VALU_PEAK_TOPS,
+            "traffic": committed_traffic(),
+            "kernel": "transport_kernel<float,false>",
+            "kernel_ms": k_ms,
+            "slots_per_event": SLOTS_PER_EVENT,
+            "fp32_flop_frac": events * FP32_FLOPS_PER_EVENT / (k_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
+        },
+        "extra": {
+            "spectra_per_s_fp32": args.steps / wall,
+            "packets_per_s": n_packets * args.steps / wall,
+            "conservation_exact": bool(conserved),
+            "albedo": res["albedo"],
+            "g": res["g"],
+        },
+    }
+
+    if not args.no_fp64:
+        p64 = dict(p, precision=1)
+        ctx.spectrum(p64)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        r64 = ctx.spectrum(p64)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        out["extra"].update({
+            "spectra_per_s_fp64_plain": 1.0 / (t3 - t2),
+            "events_per_s_fp64_plain": (r64["counts"]["collisions"] + r64["counts"]["surface"]) / (t3 - t2),
+            "fp32_vs_fp64_l1": l1_err(res["W"], r64["W"]),
+            "fp32_vs_fp64_total_rel": abs(res["W"].sum() - r64["W"].sum()) / r64["W"].sum(),
+        })
+
+    legs = [x for x in args.legs.split(",") if x]
+    if "batched" in legs:
+        from bench_legs import batched_leg
+        out["extra"]["batched"] = batched_leg(ctx)
+    if "spectrogram" in legs:
+        from bench_legs import spectrogram_leg
+        out["extra"]["spectrogram"] = spectrogram_leg(ctx)
+
+    if not args.no_cpu:
+        from oracle import mc
+        sample = dict(p, n_packets=args.cpu_sample)
+        tabs = mc.set_tables(sample)
+        threads = os.cpu_count() or 1
+        tc0 = time.perf_counter()
+        ro = mc.run(sample, tabs=tabs, n_threads=threads)
+        tc1 = time.perf_counter()
+        ev = ro["counts"]["collisions"] + ro["counts"]["surface"]
+        out["cpu_baseline"] = {
+            "value": ev / (tc1 - tc0),
+            "unit": "scatter events/s",
+            "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {args.cpu_sample} packets of the same workload (FP64 scalar C++ oracle, "
+                      f"{threads} threads, tables built beforehand), {tc1 - tc0:.2f} s",
+        }
+    ctx.close()
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -19,7 +19,8 @@ using namespace pdv;
 
 // ---- kernels (defined in the .hip translation units) ----
 namespace pdv {
-void launch_layer_tables(hipStream_t s, int n_jobs, const void* jobs, const double* density, uint8_t* tables);
+void launch_layer_tables(hipStream_t s, int n_jobs, const void* jobs, const double* density, uint8_t* tables,
+                         SetDesc* descs);
 void launch_gauss_legendre(hipStream_t s, int n, double* x, double* w);
 void launch_mie_nodes(hipStream_t s, int n, const double* gx, const double* gw, double ln_dmin, double ln_dmax,
                       double wavelength, void* info);
@@ -289,6 +290,19 @@ static void fill_desc(SetDesc& d, const pdv_params& p) {
     d.cos_cone = std::cos(p.cone_half_angle);
     d.v_lo = p.v_lo;
     d.dv = (p.v_hi - p.v_lo) / (double)p.n_bins;
+    d.inv_dv = 1.0 / d.dv;
+    d.zeta_per_tau = p.tau_total > 0.0 ? (p.v_top - p.v_bottom) / p.tau_total : 0.0;
+    d.hg_a = 1.0 + d.hg_g * d.hg_g;
+    d.hg_b = 1.0 - d.hg_g * d.hg_g;
+    d.hg_c0 = 1.0 - d.hg_g;
+    d.hg_c1 = 2.0 * d.hg_g;
+    d.hg_inv2g = d.hg_g != 0.0 ? 1.0 / (2.0 * d.hg_g) : 0.0;
+    d.lg_scale = p.tau_total > 0.0 ? (double)LAYER_GUIDE / p.tau_total : 0.0;
+    d.rev_per_cell = p.phase_kind == PDV_PHASE_HG ? 0.0 : 0.5 / (double)(p.n_angles - 1);
+    d.dtheta = p.phase_kind == PDV_PHASE_HG ? 0.0 : 3.14159265358979323846 / (double)(p.n_angles - 1);
+    d.uniform_density = p.density_kind == PDV_DENSITY_UNIFORM;
+    d.layer_steps = 13;   // replaced by the table kernels with the exact bound
+    d.cdf_steps = 13;
     d.seed = p.seed;
     d.stream = p.stream;
     auto thr = [](double a) {
@@ -373,6 +387,8 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
         L.density_kind = p.density_kind;
         L.tab_offset = d.tab_offset;
         L.density_offset = h_density.size();
+        L.set = i;
+        L.pad = 0;
         if (p.density_kind == PDV_DENSITY_TABLE) h_density.insert(h_density.end(), p.density, p.density + p.n_layers);
         max_layers = std::max(max_layers, p.n_layers);
         max_bins = std::max(max_bins, p.n_bins);
@@ -424,7 +440,8 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
         if ((r = hip_check(H2D(items.ptr, h_items.data(), sizeof(WorkItem) * n_items), "copy work items"))) return r;
 
     // ---- tables ----
-    launch_layer_tables(s, n, layer_jobs.ptr, (const double*)density.ptr, (uint8_t*)tables.ptr);
+    launch_layer_tables(s, n, layer_jobs.ptr, (const double*)density.ptr, (uint8_t*)tables.ptr,
+                        (SetDesc*)descs.ptr);
     // caller phase tables and Mie sets
     for (int i = 0; i < n; ++i) {
         const pdv_params& p = sets[i];

@@ -17,7 +17,7 @@ namespace pdv {
 constexpr int MAX_LAYERS = 4096;
 constexpr int MAX_ANGLES = 4096;
 constexpr int LAYER_GUIDE = 2048;         // uniform-depth guide entries (+1)
-constexpr int CDF_GUIDE_BITS = 9;         // 512 guide entries over the 2^32 range
+constexpr int CDF_GUIDE_BITS = 11;        // 2048 guide entries over the 2^32 range
 constexpr int CDF_GUIDE = 1 << CDF_GUIDE_BITS;
 constexpr int MAX_BINS = 4096;
 
@@ -60,7 +60,13 @@ struct alignas(16) SetDesc {
     double hg_g;
     double g_mean;              // (device) mean cosine of the sampled law
     double cos_cone;
-    double v_lo, dv;
+    double v_lo, dv, inv_dv;
+    double zeta_per_tau;        // uniform density: (v_top - v_bottom) / tau_total
+    // precomputed Henyey-Greenstein constants: 1+g^2, 1-g^2, 1-g, 2g, 1/(2g)
+    double hg_a, hg_b, hg_c0, hg_c1, hg_inv2g;
+    double lg_scale;            // LAYER_GUIDE / tau_total
+    double rev_per_cell;        // 0.5 / n_cells (table angle in revolutions)
+    double dtheta;              // pi / n_cells
     uint64_t seed;
     uint64_t tab_offset;        // bytes into the table arena
     uint64_t tally_offset;      // words into the tally arena
@@ -79,7 +85,9 @@ struct alignas(16) SetDesc {
     int32_t n_bins;
     int32_t albedo_one;         // (device for Mie) 1 if albedo >= 1
     int32_t surface_one;
-    int32_t pad0;
+    int32_t uniform_density;    // 1: zeta is linear in depth, no table search
+    int32_t layer_steps;        // (device) bisection steps inside a layer-guide window
+    int32_t cdf_steps;          // (device) bisection steps inside a CDF-guide window
 };
 
 struct WorkItem {
@@ -104,6 +112,8 @@ struct LayerJob {
     int32_t n_layers, density_kind;
     uint64_t tab_offset;
     uint64_t density_offset;   // doubles into the density staging buffer (TABLE kind)
+    int32_t set;               // descriptor to finish (layer_steps)
+    int32_t pad;
 };
 
 struct PhaseJob {

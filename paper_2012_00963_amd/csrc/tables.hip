@@ -54,7 +54,8 @@ __device__ __forceinline__ double cabs2(Cplx a) { return a.re * a.re + a.im * a.
 // --------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(1024)
-layer_table_kernel(const LayerJob* __restrict__ jobs, const double* __restrict__ density, uint8_t* tables) {
+layer_table_kernel(const LayerJob* __restrict__ jobs, const double* __restrict__ density, uint8_t* tables,
+                   SetDesc* descs) {
     const LayerJob J = jobs[blockIdx.x];
     const int n = J.n_layers;
     uint8_t* tb = tables + J.tab_offset;
@@ -106,6 +107,9 @@ layer_table_kernel(const LayerJob* __restrict__ jobs, const double* __restrict__
     if (tid == 0) { T64[0] = 0.0; T32[0] = 0.0f; }
     __syncthreads();
     // guide over uniform depth cells
+    __shared__ uint16_t s_lg[LAYER_GUIDE + 1];
+    __shared__ int s_maxwin;
+    if (tid == 0) s_maxwin = 0;
     for (int i = tid; i <= LAYER_GUIDE; i += nt) {
         const double t = J.tau_total * (double)i / (double)LAYER_GUIDE;
         int lo = 0, hi = n - 1;
@@ -114,6 +118,23 @@ layer_table_kernel(const LayerJob* __restrict__ jobs, const double* __restrict__
             if (s_mass[mid - 1] <= t) lo = mid; else hi = mid - 1;
         }
         lg[i] = (uint16_t)lo;
+        s_lg[i] = (uint16_t)lo;
+    }
+    __syncthreads();
+    // widest search window of the transport kernel (+-1 guide cell)
+    int win = 0;
+    for (int g = tid; g < LAYER_GUIDE; g += nt) {
+        const int lo = s_lg[g > 0 ? g - 1 : 0];
+        int hi = s_lg[g + 2 <= LAYER_GUIDE ? g + 2 : LAYER_GUIDE];
+        hi = hi > n - 1 ? n - 1 : hi;
+        win = max(win, hi - lo);
+    }
+    atomicMax(&s_maxwin, win);
+    __syncthreads();
+    if (tid == 0) {
+        int steps = 0;
+        while ((1 << steps) < s_maxwin + 1) ++steps;
+        descs[J.set].layer_steps = steps;
     }
 }
 
@@ -126,7 +147,7 @@ __global__ void gauss_legendre_kernel(int n, double* __restrict__ x_out, double*
     // i-th root from the top, initial guess cos(pi (i + 0.75)/(n + 0.5))
     double x = cos(PI_D * ((double)i + 0.75) / ((double)n + 0.5));
     double dp = 1.0;
-    for (int iter = 0; iter < 100; ++iter) {
+    for (int iter = 0; iter < 12; ++iter) {
         double p0 = 1.0, p1 = x;
         for (int k = 2; k <= n; ++k) {
             const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / (double)k;
@@ -136,7 +157,7 @@ __global__ void gauss_legendre_kernel(int n, double* __restrict__ x_out, double*
         dp = (double)n * (x * pn - pn1) / (x * x - 1.0);
         const double dx = pn / dp;
         x -= dx;
-        if (fabs(dx) <= 1e-16 * fabs(x) + 1e-300) break;
+        if (fabs(dx) <= 4e-16) break;
     }
     // recompute the derivative at the converged root
     {
@@ -385,6 +406,9 @@ phase_cdf_kernel(const PhaseJob* __restrict__ jobs, int n_nodes, const MieNodeIn
     }
     gpart = block_sum(gpart, s_red);
     // guide: last cell with C[j] <= i 2^(32-bits)
+    __shared__ uint16_t s_cg[CDF_GUIDE + 1];
+    __shared__ int s_maxwin;
+    if (tid == 0) s_maxwin = 0;
     for (int i = tid; i <= CDF_GUIDE; i += nt) {
         const uint64_t key = (uint64_t)i << (32 - CDF_GUIDE_BITS);
         int lo = 0, hi = nc - 1;
@@ -393,8 +417,19 @@ phase_cdf_kernel(const PhaseJob* __restrict__ jobs, int n_nodes, const MieNodeIn
             if ((uint64_t)s_C[mid] <= key) lo = mid; else hi = mid - 1;
         }
         cg[i] = (uint16_t)lo;
+        s_cg[i] = (uint16_t)lo;
     }
-    if (tid == 0) d.g_mean = gpart;
+    __syncthreads();
+    int win = 0;
+    for (int i = tid; i < CDF_GUIDE; i += nt) win = max(win, (int)s_cg[i + 1] - (int)s_cg[i]);
+    atomicMax(&s_maxwin, win);
+    __syncthreads();
+    if (tid == 0) {
+        d.g_mean = gpart;
+        int steps = 0;
+        while ((1 << steps) < s_maxwin + 1) ++steps;
+        d.cdf_steps = steps;
+    }
 }
 
 // Fill a uint64 range with zeros (graph-safe replacement for a memset).
@@ -408,9 +443,11 @@ __global__ void zero_u64_kernel(uint64_t* p, uint64_t n) {
 // ---- host launchers ----
 namespace pdv {
 
-void launch_layer_tables(hipStream_t s, int n_jobs, const void* jobs, const double* density, uint8_t* tables) {
+void launch_layer_tables(hipStream_t s, int n_jobs, const void* jobs, const double* density, uint8_t* tables,
+                         SetDesc* descs) {
     if (n_jobs <= 0) return;
-    hipLaunchKernelGGL(layer_table_kernel, dim3(n_jobs), dim3(1024), 0, s, (const LayerJob*)jobs, density, tables);
+    hipLaunchKernelGGL(layer_table_kernel, dim3(n_jobs), dim3(1024), 0, s, (const LayerJob*)jobs, density, tables,
+                       descs);
 }
 
 void launch_gauss_legendre(hipStream_t s, int n, double* x, double* w) {

@@ -23,23 +23,29 @@
 //
 // Execution shape: one packet per lane.  A block stages one parameter set's
 // tables (layer depths + uniform-depth guide, integer phase CDF + guide) and
-// a private velocity histogram in LDS.  Waves refill finished lanes with the
-// next packet ids of the current work item (one LDS atomic per wave per
-// refill round).  Rare sinks go to LDS, frequent sinks and event counters
-// stay in registers and are reduced across the wave before one global
-// atomic per wave; the LDS histogram is flushed with global 64-bit atomics
-// when the block changes set or retires.  Tallies are integers (weight x
-// 2^32), so the result does not depend on the launch shape.
+// a private histogram in LDS; the histogram carries the velocity bins and
+// one slot per terminal sink, so every finished packet costs one LDS atomic
+// (two for a binned detection).  Waves refill finished lanes with the next
+// packet ids of the current work item (one LDS atomic per wave per refill
+// round).  Table searches are bisections with a per-set step count, so
+// lanes never diverge on loop trip counts.  Event counters and absorbed
+// weight live in registers, are reduced across the wave and reach global
+// memory with one atomic per wave; the LDS histogram is flushed with global
+// 64-bit atomics when the block changes set or retires.  Tallies are
+// integers (weight x 2^32), so results do not depend on the launch shape.
 #include "pdv_device.h"
 #include "pdv_internal.h"
 
 namespace pdv {
 
 struct LdsLayout {
-    uint32_t t_off, lg_off, cdf_off, cg_off, hist_off, bytes;
+    uint32_t t_off, lg_off, cdf_off, cg_off, hist_off, hist2_off, bytes;
 };
 
 __host__ __device__ inline uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
+
+// terminal-sink slots follow the velocity bins in the LDS histogram
+constexpr int N_SINK_SLOTS = 8;
 
 __host__ __device__ inline LdsLayout lds_layout(int real_bytes, int max_layers, int max_cells, int max_bins) {
     LdsLayout L;
@@ -48,55 +54,51 @@ __host__ __device__ inline LdsLayout lds_layout(int real_bytes, int max_layers, 
     L.cdf_off = align16(L.lg_off + 2u * (LAYER_GUIDE + 1));
     L.cg_off = align16(L.cdf_off + 4u * (uint32_t)(max_cells > 0 ? max_cells : 1));
     L.hist_off = align16(L.cg_off + 2u * (CDF_GUIDE + 1));
-    L.bytes = align16(L.hist_off + 16u * (uint32_t)max_bins);
+    L.hist2_off = align16(L.hist_off + 8u * (uint32_t)(max_bins + N_SINK_SLOTS));
+    L.bytes = align16(L.hist2_off + 8u * (uint32_t)max_bins);
     return L;
 }
 
-struct RareSinks {           // LDS block-level: under, over, truncated, analog absorptions
-    unsigned long long v[8];
-};
-
 template <typename Real>
 struct SetConst {            // wave-uniform per-set constants (kept in SGPRs)
-    Real tau, v_top, dzeta, v_surface, surface_albedo, albedo, cos_cone;
-    Real hg_a, hg_b, hg_c0, hg_c1, hg_inv2g;   // HG: 1+g^2, 1-g^2, 1-g, 2g, 1/(2g)
-    Real lg_scale;           // LAYER_GUIDE / tau
-    Real rev_per_cell;       // FP32 table angle in revolutions per cell (0.5/n_cells)
-    Real dtheta;             // FP64 table angle step pi/n_cells
-    double v_lo, dv;
-    uint32_t k0, k1, stream, thr_albedo, thr_surface;
+    Real tau, v_top, dzeta, zeta_per_tau, v_surface, surface_albedo, albedo, cos_cone;
+    Real hg_a, hg_b, hg_c0, hg_c1, hg_inv2g;
+    Real lg_scale, rev_per_cell, dtheta;
+    double v_lo, dv, inv_dv;
+    uint32_t k0, k1, stream, thr_albedo, thr_surface, flags;
     int n_layers, n_cells, n_bins, max_orders, phase_kind, surface_law, weighting;
-    int albedo_one, surface_one, hg_zero;
-    uint32_t flags;
+    int albedo_one, surface_one, hg_zero, uniform_density, layer_steps, cdf_steps;
 };
 
 template <typename Real>
-__device__ SetConst<Real> load_const(const SetDesc& d) {
+__device__ __forceinline__ SetConst<Real> load_const(const SetDesc& d) {
     SetConst<Real> c;
     c.tau = (Real)d.tau_total;
     c.v_top = (Real)d.v_top;
     c.dzeta = (Real)d.dzeta;
+    c.zeta_per_tau = (Real)d.zeta_per_tau;
     c.v_surface = (Real)d.v_surface;
     c.surface_albedo = (Real)d.surface_albedo;
     c.albedo = (Real)d.albedo;
     c.cos_cone = (Real)d.cos_cone;
-    const double g = d.hg_g;
-    c.hg_a = (Real)(1.0 + g * g);
-    c.hg_b = (Real)(1.0 - g * g);
-    c.hg_c0 = (Real)(1.0 - g);
-    c.hg_c1 = (Real)(2.0 * g);
-    c.hg_inv2g = (Real)(g != 0.0 ? 1.0 / (2.0 * g) : 0.0);
-    c.hg_zero = (g == 0.0);
-    c.lg_scale = (Real)(d.tau_total > 0.0 ? (double)LAYER_GUIDE / d.tau_total : 0.0);
-    c.rev_per_cell = (Real)(d.n_cells > 0 ? 0.5 / (double)d.n_cells : 0.0);
-    c.dtheta = (Real)(d.n_cells > 0 ? 3.14159265358979323846 / (double)d.n_cells : 0.0);
+    c.hg_a = (Real)d.hg_a;
+    c.hg_b = (Real)d.hg_b;
+    c.hg_c0 = (Real)d.hg_c0;
+    c.hg_c1 = (Real)d.hg_c1;
+    c.hg_inv2g = (Real)d.hg_inv2g;
+    c.hg_zero = d.hg_g == 0.0;
+    c.lg_scale = (Real)d.lg_scale;
+    c.rev_per_cell = (Real)d.rev_per_cell;
+    c.dtheta = (Real)d.dtheta;
     c.v_lo = d.v_lo;
     c.dv = d.dv;
+    c.inv_dv = d.inv_dv;
     c.k0 = (uint32_t)(d.seed & 0xffffffffu);
     c.k1 = (uint32_t)(d.seed >> 32);
     c.stream = d.stream;
     c.thr_albedo = d.thr_albedo;
     c.thr_surface = d.thr_surface;
+    c.flags = d.flags;
     c.n_layers = d.n_layers;
     c.n_cells = d.n_cells;
     c.n_bins = d.n_bins;
@@ -106,47 +108,63 @@ __device__ SetConst<Real> load_const(const SetDesc& d) {
     c.weighting = d.weighting;
     c.albedo_one = d.albedo_one;
     c.surface_one = d.surface_one;
-    c.flags = d.flags;
+    c.uniform_density = d.uniform_density;
+    c.layer_steps = d.layer_steps;
+    c.cdf_steps = d.cdf_steps;
     return c;
 }
 
-// Velocity coordinate at depth t: the layer j with T[j] <= t < T[j+1] is
-// found from the uniform-depth guide (a window of +-1 guide cell absorbs the
-// rounding of t * scale) and a bisection in LDS; zeta is linear inside it.
+// Velocity coordinate at depth t.  Uniform density: zeta is linear in depth.
+// Otherwise the layer j with T[j] <= t < T[j+1] lies in the window of the
+// uniform-depth guide (+-1 cell absorbs the rounding of t * scale) and is
+// found by a bisection with the set's fixed step count; zeta is linear
+// inside the layer.
 template <typename Real>
 __device__ __forceinline__ Real zeta_at(const SetConst<Real>& c, const Real* T, const uint16_t* lg, Real t) {
+    if (c.uniform_density) return c.v_top - t * c.zeta_per_tau;
     int gi = (int)(t * c.lg_scale);
     gi = gi < 0 ? 0 : (gi > LAYER_GUIDE - 1 ? LAYER_GUIDE - 1 : gi);
     int lo = lg[gi > 0 ? gi - 1 : 0];
     int hi = lg[gi + 2 <= LAYER_GUIDE ? gi + 2 : LAYER_GUIDE];
     hi = hi > c.n_layers - 1 ? c.n_layers - 1 : hi;
-    while (lo < hi) {
+    for (int s = 0; s < c.layer_steps; ++s) {
         const int mid = (lo + hi + 1) >> 1;
-        if (T[mid] <= t) lo = mid; else hi = mid - 1;
+        const bool le = T[mid] <= t;
+        lo = le ? mid : lo;
+        hi = le ? hi : mid - 1;
     }
     const Real frac = M<Real>::div(t - T[lo], T[lo + 1] - T[lo]);
     return c.v_top - ((Real)lo + frac) * c.dzeta;
 }
 
 // Scattering angle (cos, sin) from the integer CDF: the cell is the last j
-// with C[j] <= x, found from a guide over the top CDF_GUIDE_BITS of x; the
-// angle is uniform inside the cell.
+// with C[j] <= x; it lies between the guide entries of the top bits of x
+// and is found by a bisection with the set's fixed step count; the angle is
+// uniform inside the cell.
 template <typename Real>
 __device__ __forceinline__ void table_angle(const SetConst<Real>& c, const uint32_t* C, const uint16_t* cg,
                                             uint32_t x, Real& ct, Real& st) {
-    int j = cg[x >> (32 - CDF_GUIDE_BITS)];
-    while (j + 1 < c.n_cells && C[j + 1] <= x) ++j;
-    const uint32_t cj = C[j];
-    const uint32_t next_lo = (j + 1 < c.n_cells) ? C[j + 1] : 0u;
-    // width of the last cell is 2^32 - C[j]; unsigned wrap gives it unless C[j] == 0
-    const Real width = (j + 1 < c.n_cells || cj != 0u) ? (Real)(uint32_t)(next_lo - cj) : (Real)4294967296.0;
+    const uint32_t gi = x >> (32 - CDF_GUIDE_BITS);
+    int lo = cg[gi];
+    int hi = cg[gi + 1];
+    for (int s = 0; s < c.cdf_steps; ++s) {
+        const int mid = (lo + hi + 1) >> 1;
+        const bool le = C[mid] <= x;
+        lo = le ? mid : lo;
+        hi = le ? hi : mid - 1;
+    }
+    const uint32_t cj = C[lo];
+    const bool last = lo + 1 >= c.n_cells;
+    const uint32_t cn = last ? 0u : C[lo + 1];
+    // last cell's width is 2^32 - C[j] (unsigned wrap), or 2^32 if it holds everything
+    const Real width = (!last || cj != 0u) ? (Real)(uint32_t)(cn - cj) : (Real)4294967296.0;
     const Real f = M<Real>::div((Real)(x - cj) + (Real)0.5, width);
     if constexpr (sizeof(Real) == 4) {
-        const Real rev = ((Real)j + f) * c.rev_per_cell;
+        const Real rev = ((Real)lo + f) * c.rev_per_cell;
         ct = M<Real>::cos_rev(rev);
         st = M<Real>::sin_rev(rev);
     } else {
-        const Real theta = ((Real)j + f) * c.dtheta;
+        const Real theta = ((Real)lo + f) * c.dtheta;
         ct = ::cos(theta);
         st = ::sin(theta);
     }
@@ -169,12 +187,11 @@ __device__ __forceinline__ void hg_angle(const SetConst<Real>& c, Real u, Real& 
 }
 
 struct LaneAcc {             // per-lane accumulators, reduced across the wave at flush
-    uint64_t undetected, abs_particle, abs_surface;
+    uint64_t abs_particle, abs_surface;
     uint32_t packets, collisions, surface, exits, detected;
 };
 
 __device__ __forceinline__ void flush_lane_acc(LaneAcc& a, uint64_t* tally, int n_bins) {
-    const uint64_t s_und = wave_sum_u64(a.undetected);
     const uint64_t s_ap = wave_sum_u64(a.abs_particle);
     const uint64_t s_as = wave_sum_u64(a.abs_surface);
     const uint64_t c_p = wave_sum_u64(a.packets);
@@ -185,7 +202,6 @@ __device__ __forceinline__ void flush_lane_acc(LaneAcc& a, uint64_t* tally, int 
     if (lane_id() == 0) {
         unsigned long long* sk = (unsigned long long*)(tally + tw_sinks(n_bins));
         unsigned long long* ct = (unsigned long long*)(tally + tw_counts(n_bins));
-        if (s_und) atomicAdd(sk + SK_UNDETECTED, (unsigned long long)s_und);
         if (s_ap) atomicAdd(sk + SK_ABS_PARTICLE, (unsigned long long)s_ap);
         if (s_as) atomicAdd(sk + SK_ABS_SURFACE, (unsigned long long)s_as);
         if (c_p) atomicAdd(ct + C_PACKETS, (unsigned long long)c_p);
@@ -194,7 +210,7 @@ __device__ __forceinline__ void flush_lane_acc(LaneAcc& a, uint64_t* tally, int 
         if (c_e) atomicAdd(ct + C_EXITS, (unsigned long long)c_e);
         if (c_d) atomicAdd(ct + C_DETECTED, (unsigned long long)c_d);
     }
-    a = LaneAcc{0, 0, 0, 0, 0, 0, 0, 0};
+    a = LaneAcc{0, 0, 0, 0, 0, 0, 0};
 }
 
 template <typename Real, bool LIST>
@@ -207,20 +223,20 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
     __shared__ WorkItem s_item;
     __shared__ int s_item_idx;
     __shared__ uint32_t s_next;
-    __shared__ RareSinks s_rare;
 
     const LdsLayout L = lds_layout((int)sizeof(Real), max_layers, max_cells, max_bins);
     Real* sT = (Real*)(lds + L.t_off);
     uint16_t* sLG = (uint16_t*)(lds + L.lg_off);
     uint32_t* sC = (uint32_t*)(lds + L.cdf_off);
     uint16_t* sCG = (uint16_t*)(lds + L.cg_off);
-    unsigned long long* sHist = (unsigned long long*)(lds + L.hist_off);
+    unsigned long long* sW = (unsigned long long*)(lds + L.hist_off);     // bins, then sink slots
+    unsigned long long* sW2 = (unsigned long long*)(lds + L.hist2_off);
 
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
     const int lane = lane_id();
     int cur_set = -1;
-    LaneAcc acc = LaneAcc{0, 0, 0, 0, 0, 0, 0, 0};
+    LaneAcc acc = LaneAcc{0, 0, 0, 0, 0, 0, 0};
 
     auto flush_set = [&](int set) {
         const SetDesc& d = descs[set];
@@ -229,14 +245,15 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
         __syncthreads();
         unsigned long long* gW = (unsigned long long*)(tally + tw_w(d.n_bins));
         unsigned long long* gW2 = (unsigned long long*)(tally + tw_w2(d.n_bins));
+        unsigned long long* gS = (unsigned long long*)(tally + tw_sinks(d.n_bins));
         for (int b = tid; b < d.n_bins; b += nthr) {
-            const unsigned long long w = sHist[b], w2 = sHist[max_bins + b];
+            const unsigned long long w = sW[b], w2 = sW2[b];
             if (w) atomicAdd(gW + b, w);
             if (w2) atomicAdd(gW2 + b, w2);
         }
-        if (tid < 8 && s_rare.v[tid]) {
-            // rare sinks: 0 under, 1 over, 5 truncated, 3/4 analog absorptions
-            atomicAdd((unsigned long long*)(tally + tw_sinks(d.n_bins)) + tid, s_rare.v[tid]);
+        if (tid < N_SINK_SLOTS) {
+            const unsigned long long v = sW[d.n_bins + tid];
+            if (v) atomicAdd(gS + tid, v);
         }
         __syncthreads();
     };
@@ -259,24 +276,26 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
             if (cur_set >= 0) flush_set(cur_set);
             const SetDesc& d = descs[set];
             const uint8_t* tb = tables + d.tab_offset;
-            const Real* gT = (const Real*)(tb + (sizeof(Real) == 4 ? TableLayout::T32 : TableLayout::T64));
-            for (int i = tid; i <= d.n_layers; i += nthr) sT[i] = gT[i];
-            const uint16_t* gLG = (const uint16_t*)(tb + TableLayout::LGUIDE);
-            for (int i = tid; i <= LAYER_GUIDE; i += nthr) sLG[i] = gLG[i];
+            if (!d.uniform_density) {
+                const Real* gT = (const Real*)(tb + (sizeof(Real) == 4 ? TableLayout::T32 : TableLayout::T64));
+                for (int i = tid; i <= d.n_layers; i += nthr) sT[i] = gT[i];
+                const uint16_t* gLG = (const uint16_t*)(tb + TableLayout::LGUIDE);
+                for (int i = tid; i <= LAYER_GUIDE; i += nthr) sLG[i] = gLG[i];
+            }
             if (d.phase_kind == PH_TABLE) {
                 const uint32_t* gC = (const uint32_t*)(tb + TableLayout::CDF);
                 for (int i = tid; i < d.n_cells; i += nthr) sC[i] = gC[i];
                 const uint16_t* gCG = (const uint16_t*)(tb + TableLayout::CGUIDE);
                 for (int i = tid; i <= CDF_GUIDE; i += nthr) sCG[i] = gCG[i];
             }
-            for (int i = tid; i < 2 * max_bins; i += nthr) sHist[i] = 0ull;
-            if (tid < 8) s_rare.v[tid] = 0ull;
+            for (int i = tid; i < d.n_bins + N_SINK_SLOTS; i += nthr) sW[i] = 0ull;
+            for (int i = tid; i < d.n_bins; i += nthr) sW2[i] = 0ull;
             cur_set = set;
             __syncthreads();
         }
 
         const SetConst<Real> c = load_const<Real>(descs[set]);
-        uint64_t* tally = tallies + descs[set].tally_offset;
+        const int nb = c.n_bins;
 
         // ---- per-lane packet state ----
         bool alive = false;
@@ -293,17 +312,17 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                 const uint32_t n = (uint32_t)__popcll(dead);
                 uint32_t base = 0;
                 if (lane == 0) base = atomicAdd(&s_next, n);
-                base = __shfl(base, 0, 64);
+                base = uniform_u32(base);
                 if (base + n >= count) exhausted = true;
                 if (!alive) {
-                    const uint32_t rank = (uint32_t)__popcll(dead & ((1ull << lane) - 1ull));
+                    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(dead >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)dead, 0u));
                     const uint32_t local = base + rank;
                     if (local < count) {
                         alive = true;
                         pid = pid0 + local;
                         k = 0; n_sc = 0; n_surf = 0;
                         T = 0; mu = -1; w = 1; big = 0; small = 0; abs_s = 0;
-                        acc.packets += 1;
                     }
                 }
             }
@@ -314,135 +333,131 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
             const Real u0 = unit_open<Real>(X.x);
             const Real u1 = unit_open<Real>(X.y);
             const Real u2 = unit_open<Real>(X.z);
-            const Real s = M<Real>::neg_log(u0);
-            const Real Tn = T - s * mu;
+            const Real Tn = T - M<Real>::neg_log(u0) * mu;
+            const bool leave = mu > (Real)0 && Tn <= (Real)0;
+            const bool surf = mu < (Real)0 && Tn >= c.tau;
+            const bool coll = !leave && !surf;
 
-            bool done = false;
-            if (mu > (Real)0 && Tn <= (Real)0) {
-                // ---- leaves the top ----
-                acc.exits += 1;
-                if (mu >= c.cos_cone) {
-                    acc.detected += 1;
-                    const double v = (double)big - (double)small;
-                    const double bf = floor((v - c.v_lo) / c.dv);
-                    const uint64_t wf = to_fixed32<Real>(w);
-                    if (bf < 0.0) {
-                        atomicAdd(&s_rare.v[SK_UNDER], (unsigned long long)wf);
-                    } else if (bf >= (double)c.n_bins) {
-                        atomicAdd(&s_rare.v[SK_OVER], (unsigned long long)wf);
-                    } else {
-                        const int b = (int)bf;
-                        atomicAdd(&sHist[b], (unsigned long long)wf);
-                        atomicAdd(&sHist[max_bins + b], (unsigned long long)to_fixed32<Real>(w * w));
-                        if (c.flags & SF_CLASS) {
-                            unsigned long long* gcl = (unsigned long long*)(tally + tw_class(c.n_bins));
-                            if (n_sc == 1 && n_surf == 0) atomicAdd(gcl + b, (unsigned long long)wf);
-                            if (n_sc == 0 && n_surf == 1) atomicAdd(gcl + c.n_bins + b, (unsigned long long)wf);
-                        }
+            // particle interaction: scatterer speed, new direction
+            Real Vc = 0, mu_c = 0, omc_c = 0;
+            if (coll) {
+                Vc = zeta_at<Real>(c, sT, sLG, Tn);
+                Real ct, st;
+                if (c.phase_kind == PH_TABLE) table_angle<Real>(c, sC, sCG, X.y, ct, st);
+                else hg_angle<Real>(c, u1, ct, st);
+                const Real cphi = M<Real>::cos_rev(u2);
+                const Real sm2 = ((Real)1.0 - mu) * ((Real)1.0 + mu);
+                Real m2 = mu * ct + M<Real>::sqrt(sm2 > (Real)0 ? sm2 : (Real)0) * st * cphi;
+                m2 = m2 > (Real)1.0 ? (Real)1.0 : (m2 < (Real)-1.0 ? (Real)-1.0 : m2);
+                mu_c = m2;
+                omc_c = (Real)1.0 - m2;
+            }
+            // free-surface reflection (computed for every lane, selected below)
+            Real mu_s, omc_s;
+            if (c.surface_law == 1) {
+                const Real r = M<Real>::sqrt(u1);
+                mu_s = r;
+                omc_s = M<Real>::div((Real)1.0 - u1, (Real)1.0 + r);
+            } else {
+                if constexpr (sizeof(Real) == 4) {
+                    mu_s = M<Real>::cos_rev((Real)0.25 * u1);
+                    const Real sh = M<Real>::sin_rev((Real)0.125 * u1);
+                    omc_s = (Real)2.0 * sh * sh;
+                } else {
+                    const Real psi = (Real)0.5 * M<Real>::PI * u1;
+                    const Real sh = ::sin((Real)0.5 * psi);
+                    mu_s = ::cos(psi);
+                    omc_s = (Real)2.0 * sh * sh;
+                }
+            }
+            const Real V = surf ? c.v_surface : Vc;
+            const Real mu_new = surf ? mu_s : mu_c;
+            const Real omc = surf ? omc_s : omc_c;
+            const Real a = surf ? c.surface_albedo : c.albedo;
+
+            const bool trunc = coll && n_sc == c.max_orders;
+            bool absorbed = false;
+            if (c.weighting == 1) {
+                const uint32_t thr = surf ? c.thr_surface : c.thr_albedo;
+                const bool one = surf ? (bool)c.surface_one : (bool)c.albedo_one;
+                absorbed = !leave && !trunc && !one && X.w >= thr;
+            }
+            if (!(leave || trunc || absorbed)) {
+                if (c.weighting == 0) {
+                    const Real lost = w * ((Real)1.0 - a);
+                    abs_s += surf ? lost : (Real)0;
+                    w *= a;
+                }
+                big += (Real)0.5 * V * ((Real)1.0 - mu);
+                small += (Real)0.5 * V * omc;
+                mu = mu_new;
+                T = surf ? c.tau : Tn;
+                n_surf += surf ? 1 : 0;
+                n_sc += surf ? 0 : 1;
+            } else {
+                // ---- the packet ends: one terminal slot of the LDS histogram ----
+                const bool detected = leave && mu >= c.cos_cone;
+                int slot;
+                double vt = 0.0;
+                if (detected) {
+                    vt = (double)big - (double)small;
+                    double bf;
+                    if constexpr (sizeof(Real) == 8) bf = floor((vt - c.v_lo) / c.dv);
+                    else bf = floor((vt - c.v_lo) * c.inv_dv);
+                    slot = bf < 0.0 ? nb + SK_UNDER : (bf >= (double)nb ? nb + SK_OVER : (int)bf);
+                } else if (leave) {
+                    slot = nb + SK_UNDETECTED;
+                } else if (trunc) {
+                    slot = nb + SK_TRUNCATED;
+                } else {
+                    slot = nb + (surf ? SK_ABS_SURFACE : SK_ABS_PARTICLE);
+                }
+                const uint64_t fw = to_fixed32<Real>(w);
+                atomicAdd(&sW[slot], (unsigned long long)fw);
+                if (slot < nb) {
+                    atomicAdd(&sW2[slot], (unsigned long long)to_fixed32<Real>(w * w));
+                    if (c.flags & SF_CLASS) {
+                        unsigned long long* gcl =
+                            (unsigned long long*)(tallies + descs[set].tally_offset + tw_class(nb));
+                        if (n_sc == 1 && n_surf == 0) atomicAdd(gcl + slot, (unsigned long long)fw);
+                        if (n_sc == 0 && n_surf == 1) atomicAdd(gcl + nb + slot, (unsigned long long)fw);
                     }
-                    if constexpr (LIST) {
+                }
+                if constexpr (LIST) {
+                    if (detected) {
                         const Block4 P = philox10(0xffffffffu, (uint32_t)pid, (uint32_t)(pid >> 32), c.stream,
                                                   c.k0, c.k1);
                         const SetDesc& d = descs[set];
                         const uint64_t m = __ballot(1);
                         const int leader = __ffsll((unsigned long long)m) - 1;
                         const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-                        unsigned long long base = 0;
+                        unsigned long long lbase = 0;
                         if (lane == leader)
-                            base = atomicAdd((unsigned long long*)(list_counts + set), (unsigned long long)__popcll(m));
-                        base = __shfl(base, leader, 64);
-                        const unsigned long long slot = base + rank;
-                        if (slot < d.list_capacity) {
+                            lbase = atomicAdd((unsigned long long*)(list_counts + set),
+                                              (unsigned long long)__popcll(m));
+                        lbase = __shfl(lbase, leader, 64);
+                        const unsigned long long lslot = lbase + rank;
+                        if (lslot < d.list_capacity) {
                             ListEntry e;
                             e.w = (float)w;
                             e.phase = P.x;
-                            e.v = v;
-                            lists[d.list_offset + slot] = e;
+                            e.v = vt;
+                            lists[d.list_offset + lslot] = e;
                         }
                     }
-                } else {
-                    acc.undetected += to_fixed32<Real>(w);
                 }
-                done = true;
-            } else {
-                Real V, mu_new, omc, a;
-                uint32_t thr;
-                bool a_one, at_surface;
-                if (mu < (Real)0 && Tn >= c.tau) {
-                    // ---- free surface: diffuse reflection ----
-                    at_surface = true;
-                    acc.surface += 1;
-                    if (c.surface_law == 1) {
-                        const Real r = M<Real>::sqrt(u1);
-                        mu_new = r;
-                        omc = M<Real>::div((Real)1.0 - u1, (Real)1.0 + r);
-                    } else {
-                        if constexpr (sizeof(Real) == 4) {
-                            mu_new = M<Real>::cos_rev((Real)0.25 * u1);
-                            const Real sh = M<Real>::sin_rev((Real)0.125 * u1);
-                            omc = (Real)2.0 * sh * sh;
-                        } else {
-                            const Real psi = (Real)0.5 * M<Real>::PI * u1;
-                            const Real sh = ::sin((Real)0.5 * psi);
-                            mu_new = ::cos(psi);
-                            omc = (Real)2.0 * sh * sh;
-                        }
-                    }
-                    V = c.v_surface;
-                    a = c.surface_albedo;
-                    thr = c.thr_surface;
-                    a_one = c.surface_one;
-                } else {
-                    // ---- particle interaction at depth Tn ----
-                    at_surface = false;
-                    acc.collisions += 1;
-                    V = zeta_at<Real>(c, sT, sLG, Tn);
-                    if (n_sc == c.max_orders) {
-                        atomicAdd(&s_rare.v[SK_TRUNCATED], (unsigned long long)to_fixed32<Real>(w));
-                        done = true;
-                    }
-                    Real ct, st;
-                    if (c.phase_kind == PH_TABLE) table_angle<Real>(c, sC, sCG, X.y, ct, st);
-                    else hg_angle<Real>(c, u1, ct, st);
-                    const Real cphi = M<Real>::cos_rev(u2);
-                    const Real sm2 = ((Real)1.0 - mu) * ((Real)1.0 + mu);
-                    Real m2 = mu * ct + M<Real>::sqrt(sm2 > (Real)0 ? sm2 : (Real)0) * st * cphi;
-                    m2 = m2 > (Real)1.0 ? (Real)1.0 : (m2 < (Real)-1.0 ? (Real)-1.0 : m2);
-                    mu_new = m2;
-                    omc = (Real)1.0 - m2;
-                    a = c.albedo;
-                    thr = c.thr_albedo;
-                    a_one = c.albedo_one;
-                }
-                if (!done) {
-                    if (c.weighting == 1) {
-                        if (!a_one && X.w >= thr) {
-                            atomicAdd(&s_rare.v[at_surface ? SK_ABS_SURFACE : SK_ABS_PARTICLE], (unsigned long long)to_fixed32<Real>(w));
-                            done = true;
-                        }
-                    } else {
-                        const Real lost = w * ((Real)1.0 - a);
-                        if (at_surface) abs_s += lost;
-                        w *= a;
-                    }
-                }
-                if (!done) {
-                    if (at_surface) n_surf += 1; else n_sc += 1;
-                    big += (Real)0.5 * V * ((Real)1.0 - mu);
-                    small += (Real)0.5 * V * omc;
-                    mu = mu_new;
-                    T = at_surface ? c.tau : Tn;
-                }
-            }
-            if (done) {
-                // implicit-capture bookkeeping: the packet's 2^32 units are split
-                // exactly between its terminal sink and the two absorption sinks
+                // implicit capture: the packet's 2^32 units are split exactly
+                // between its terminal slot and the two absorption sinks
                 if (c.weighting == 0) {
-                    const uint64_t fw = to_fixed32<Real>(w);
                     const uint64_t fs = to_fixed32<Real>(abs_s);
                     acc.abs_surface += fs;
                     acc.abs_particle += (4294967296ull - fw) - fs;
                 }
+                acc.packets += 1;
+                acc.collisions += (uint32_t)n_sc + (coll ? 1u : 0u);
+                acc.surface += (uint32_t)n_surf + (surf ? 1u : 0u);
+                acc.exits += leave ? 1u : 0u;
+                acc.detected += detected ? 1u : 0u;
                 alive = false;
             }
             }  // alive
