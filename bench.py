@@ -16,10 +16,15 @@ Also reported on the same JSON line:
   cpu_baseline  the FP64 oracle on the host cores over a bounded packet
                 sample of the same workload;
   extra         FP64 ("plain") spectrum of the same workload and its error
-                against FP32, plus optional legs (--legs).
+                against FP32, plus optional legs (--legs): "batched" (512
+                uneven sets in one FP32 launch vs serial FP64 launches),
+                "spectrogram" (256 frames x 1e6 packets, beat record, STFT),
+                "serve" (Poisson request stream with continuous batching vs
+                serial FP64, p50/p99 latency).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                       [--legs batched,spectrogram] [--calib-copy BYTES]
+                       [--legs batched,spectrogram,serve] [--serve-duration S]
+                       [--calib-copy BYTES]
 """
 from __future__ import annotations
 
@@ -37,7 +42,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 # Issue-slot cost of one scatter event in the transport kernel, counted from
-# the algorithm (see DESIGN.md "Roofline"): Philox4x32-10 (10 rounds x
+# the algorithm: Philox4x32-10 (10 rounds x
 # 2 mul_hi + 2 mul_lo + 4 xor = 80), three uniforms (12), flight (3),
 # branch tests (4), layer/angle lookup (13), angle sampling (11), azimuth (1),
 # rotation (8), Doppler (6), weight (4): 142 full-rate lane operations, of
@@ -98,6 +103,122 @@ def run_calib_copy(nbytes: int):
     print(json.dumps({"calib_copy_bytes_each_way": n * 4, "launches": 3}))
 
 
+def batched_leg(ctx):
+    """512 uneven Mie sets: one FP32 persistent launch against serial
+    per-set FP64 ("plain") launches, with the per-set FP32 error."""
+    import numpy as np
+    import torch
+    from paper_2012_00963_amd import workloads
+    sets = workloads.batched_sets(512)
+    s32 = [dict(s, precision=0) for s in sets]
+    s64 = [dict(s, precision=1) for s in sets]
+    ctx.spectrum_batch(s32[:8])                      # warm the Mie basis and buffers
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r32 = ctx.spectrum_batch(s32)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    k32 = ctx.last_launch()["kernel_ms"]
+    r64 = [ctx.spectrum(s) for s in s64]
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    errs = [l1_err(a["W"], b["W"]) for a, b in zip(r32, r64) if b["W"].sum() > 0]
+    tot = [abs(a["W"].sum() - b["W"].sum()) / b["W"].sum() for a, b in zip(r32, r64) if b["W"].sum() > 0]
+    ev32 = sum(r["counts"]["collisions"] + r["counts"]["surface"] for r in r32)
+    return {
+        "sets": len(sets),
+        "packets": int(sum(s["n_packets"] for s in sets)),
+        "events": int(ev32),
+        "fp32_batched_s": t1 - t0,
+        "fp32_batched_kernel_ms": k32,
+        "fp64_plain_serial_s": t2 - t1,
+        "spectra_per_s_fp32_batched": len(sets) / (t1 - t0),
+        "spectra_per_s_fp64_plain": len(sets) / (t2 - t1),
+        "speedup": (t2 - t1) / (t1 - t0),
+        "events_per_s_fp32_batched": ev32 / (t1 - t0),
+        "max_l1_fp32_vs_fp64": float(max(errs)),
+        "median_l1_fp32_vs_fp64": float(np.median(errs)),
+        "max_total_rel_fp32_vs_fp64": float(max(tot)),
+    }
+
+
+def spectrogram_leg(ctx):
+    """Time-resolved case: 256 frames x 1e6 packets, 20 GS/s beat record of
+    1e5 samples with FP64 phase, 4096-point Hann STFT at 80% overlap."""
+    import torch
+    from paper_2012_00963_amd import workloads
+    p, sg = workloads.spectrogram_case()
+    ctx.spectrogram(p, dict(sg, n_frames=8, packets_per_frame=10_000))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = ctx.spectrogram(p, sg)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return {
+        "frames": sg["n_frames"], "packets_per_frame": sg["packets_per_frame"],
+        "seconds": t1 - t0, "spectrograms_per_s": 1.0 / (t1 - t0),
+        "packets_per_s": sg["n_frames"] * sg["packets_per_frame"] / (t1 - t0),
+        "detected_entries": int(g["frame_counts"].sum()), "windows": g["n_windows"],
+        "overflow": g["overflow"],
+    }
+
+
+def serve_leg(ctx, duration=60.0):
+    """Poisson arrivals (200/s) of uneven Mie requests, a quarter with a
+    64-frame spectrogram, served with continuous batching (FP32, graph
+    replays), against the same trace replayed with serial per-request plain
+    FP64 launches.  Latency = arrival -> result on the host."""
+    import numpy as np
+    from paper_2012_00963_amd import pdv, workloads
+    trace = workloads.serving_trace(duration=duration)
+    ctx.spectrum(dict(trace[0]["params"], n_packets=1000))     # resident Mie basis
+    srv = pdv.Server(ctx, max_active=256, use_graph=1)
+    t0 = time.perf_counter()
+    tks = []
+    for r in trace:
+        dt = t0 + r["arrival"] - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        tks.append(srv.submit(r["params"], sg=r["spectrogram"]))
+    codes = [srv.poll(tk, wait_ms=-1) for tk in tks]
+    t1 = time.perf_counter()
+    st = srv.stats()
+    srv.stop()
+    ok = sum(1 for c in codes if c in (0, -4))
+    # serial plain FP64 replay of the same trace
+    lat = []
+    t2 = time.perf_counter()
+    n_done = 0
+    for r in trace:
+        arr = t2 + r["arrival"]
+        dt = arr - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        p64 = dict(r["params"], precision=1)
+        ctx.spectrum(p64)
+        if r["spectrogram"] is not None:
+            sg = dict(r["spectrogram"])
+            sg.setdefault("list_capacity", max(4096, sg["packets_per_frame"] // 10))
+            ctx.spectrogram(p64, sg)
+        lat.append((time.perf_counter() - arr) * 1e3)
+        n_done += 1
+        if time.perf_counter() - t2 > 3 * duration:
+            break
+    t3 = time.perf_counter()
+    lat = np.array(lat)
+    return {
+        "requests": len(trace), "served_ok": ok, "spectrogram_requests": sum(r["spectrogram"] is not None for r in trace),
+        "duration_s": duration,
+        "served_wall_s": t1 - t0, "served_spectra_per_s": ok / (t1 - t0),
+        "served_p50_ms": st["p50_ms"], "served_p99_ms": st["p99_ms"], "served_max_ms": st["max_ms"],
+        "served_iterations": st["iterations"], "served_events_per_s": st["events"] / (t1 - t0),
+        "served_busy_fraction": st["busy_s"] / (t1 - t0),
+        "fp64_serial_requests_done": n_done, "fp64_serial_wall_s": t3 - t2,
+        "fp64_serial_spectra_per_s": n_done / (t3 - t2),
+        "fp64_serial_p50_ms": float(np.percentile(lat, 50)), "fp64_serial_p99_ms": float(np.percentile(lat, 99)),
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,12 +229,13 @@ def main(argv=None):
     ap.add_argument("--legs", default="", help="comma list of extra legs: batched,spectrogram")
     ap.add_argument("--cpu-sample", type=int, default=20_000_000, help="packets in the oracle sample")
     ap.add_argument("--calib-copy", type=int, default=0, help="only run a copy of this many bytes")
+    ap.add_argument("--serve-duration", type=float, default=60.0, help="seconds of the serving trace")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the transport would shard by packet-id ranges with one all-reduce of the tallies; "
-              "see DESIGN.md)", file=sys.stderr)
+              "(the transport would shard by packet-id ranges with one all-reduce of the tallies)",
+              file=sys.stderr)
         return 2
     if args.calib_copy:
         run_calib_copy(args.calib_copy)
@@ -209,11 +331,11 @@ def main(argv=None):
 
     legs = [x for x in args.legs.split(",") if x]
     if "batched" in legs:
-        from bench_legs import batched_leg
         out["extra"]["batched"] = batched_leg(ctx)
     if "spectrogram" in legs:
-        from bench_legs import spectrogram_leg
         out["extra"]["spectrogram"] = spectrogram_leg(ctx)
+    if "serve" in legs:
+        out["extra"]["serve"] = serve_leg(ctx, args.serve_duration)
 
     if not args.no_cpu:
         from oracle import mc

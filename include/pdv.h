@@ -30,7 +30,7 @@
  *     call on that context.  After PDV_EDEVICE the context is poisoned: every
  *     later call returns PDV_EDEVICE; destroy and recreate it.
  *   - One context per host thread, except the serving calls (pdv_submit,
- *     pdv_poll, pdv_cancel, pdv_serve_stats), which are thread-safe.
+ *     pdv_poll, pdv_cancel, pdv_serve_report), which are thread-safe.
  *   - Fixed-point tallies: weights are accumulated as unsigned 64-bit
  *     integers scaled by 2^32 (divide by 4294967296.0 for packet-weight
  *     units).  Integer sums are order independent, so results are bitwise
@@ -260,6 +260,14 @@ typedef struct pdv_sg_out {
     int32_t n_windows;            /* written */
     int32_t overflow;             /* written: 1 if some frame exceeded list_capacity */
     pdv_spectrum_out* spectrum;   /* nullable: tallies summed over all frames */
+    /* nullable host arrays of n_frames x list_stride entries: the detected
+     * list of frame k (weight, apparent velocity, phase word; phase in cycles
+     * is phase / 2^32) fills [k list_stride, k list_stride + min(count_k,
+     * list_stride, list_capacity)); order inside a frame is unspecified */
+    float* list_w;
+    double* list_v;
+    uint32_t* list_phase;
+    uint64_t list_stride;
 } pdv_sg_out;
 
 int pdv_spectrogram(struct pdv_ctx* ctx, const pdv_params* p, const pdv_sg_params* sg, pdv_sg_out* out);
@@ -282,6 +290,110 @@ int pdv_beat_synthesize(struct pdv_ctx* ctx, int32_t n_frames, const uint64_t* o
  */
 int pdv_stft(struct pdv_ctx* ctx, const float* signal, int32_t n_samples, int32_t nfft, int32_t hop,
              float* map, int32_t* n_windows);
+
+/*
+ * Autotuner for pdv_spectrum_batch launches.  Times every candidate launch
+ * shape (block size 256/512/1024; persistent grid of 1, 2, 4 or 8 blocks per
+ * CU, or one block per item; work items of 2^12 .. 2^18 packets) on the given
+ * sets, `repeats` times each, and keeps the fastest (median) as the
+ * context's default for later batches.  Every candidate must reproduce the
+ * first candidate's tallies bitwise (integer tallies do not depend on the
+ * launch shape); a mismatch returns PDV_EDEVICE.  best and report are
+ * nullable.
+ */
+typedef struct pdv_tune_report {
+    int32_t candidates;          /* launch shapes timed */
+    int32_t invariant;           /* 1 if all candidates gave bitwise-equal tallies */
+    double best_ms, worst_ms, default_ms;   /* median transport-kernel times */
+} pdv_tune_report;
+
+int pdv_autotune(struct pdv_ctx* ctx, const pdv_params* sets, int32_t n, int32_t repeats,
+                 pdv_launch_opts* best, pdv_tune_report* report);
+/* Set the context's default launch shape (e.g. from a cached tuning). */
+int pdv_set_launch_defaults(struct pdv_ctx* ctx, const pdv_launch_opts* opts);
+/* Identifier of the kernel sources the library was built from. */
+const char* pdv_build_id(void);
+
+/*
+ * ---------------------------------------------------------------------------
+ * Serving: continuous batching of spectrum requests on one device.
+ *
+ * After pdv_serve_start, clients submit requests from any thread; one
+ * scheduler thread owned by the context admits them in arrival order while
+ * a request slot and enough of the memory budget are free, builds their
+ * device tables once, and transports a slice of every active request's
+ * packets in each persistent launch, so requests that arrive while others
+ * run share the device with them.  Results are bitwise the same as a lone
+ * pdv_spectrum call with the same parameters (integer tallies over the same
+ * random streams).  While a context serves, pdv_spectrum, pdv_spectrum_batch,
+ * pdv_spectrogram, pdv_beat_synthesize and pdv_stft return PDV_ESTATE.
+ * ---------------------------------------------------------------------------
+ */
+enum { PDV_EXEC_HIP = 0, PDV_EXEC_HOST = 1 };
+
+typedef struct pdv_serve_opts {
+    int32_t max_active;            /* request slots (0 = 256, at most 4096) */
+    int32_t max_items;             /* work items per launch (0 = 8192) */
+    uint64_t mem_budget;           /* device bytes for active requests (0 = half the context budget) */
+    uint64_t packets_per_iteration;/* packets shared among active requests per launch (0 = 2^25) */
+    uint64_t packets_per_item;     /* packets per work item (0 = 2^16) */
+    int32_t max_layers;            /* largest n_layers served (0 = 1024) */
+    int32_t max_angles;            /* largest n_angles served (0 = 2048) */
+    int32_t max_bins;              /* largest n_bins served (0 = 1024) */
+    int32_t precision;             /* PDV_FP32 or PDV_FP64 for every request */
+    int32_t use_graph;             /* 1: replay each launch from a captured hipGraph */
+    int32_t executor;              /* PDV_EXEC_HIP, or PDV_EXEC_HOST: scheduler only, no device work
+                                      (every packet is tallied as undetected with unit weight) */
+    int32_t host_fail_iteration;   /* PDV_EXEC_HOST: report a device failure at this iteration (0 = never) */
+    double host_ns_per_packet;     /* PDV_EXEC_HOST: simulated cost per packet */
+} pdv_serve_opts;
+
+/*
+ * A request: the parameter set (copied at submission, including its density
+ * and phase arrays), the caller-owned output (w_fx, w2_fx must stay valid
+ * until pdv_poll reports a final status), and optionally a spectrogram
+ * (sg and sg_out non-NULL; HIP executor only) computed after the spectrum.
+ */
+typedef struct pdv_request {
+    pdv_params params;
+    const pdv_sg_params* sg;
+    pdv_spectrum_out* out;
+    pdv_sg_out* sg_out;
+} pdv_request;
+
+typedef struct pdv_serve_stats {
+    uint64_t submitted, completed, failed, cancelled;
+    uint64_t iterations;           /* persistent launches issued */
+    uint64_t packets, events;      /* of completed requests (events = collisions + surface hits) */
+    uint64_t admission_waits;      /* requests that had to wait for a slot or memory */
+    uint64_t mem_in_use;           /* bytes held by active requests */
+    uint32_t active, pending;
+    double p50_ms, p99_ms, mean_ms, max_ms;   /* latency: submission -> result on the host */
+    double busy_s;                 /* scheduler time spent in table builds and launches */
+    double wall_s;                 /* since pdv_serve_start */
+} pdv_serve_stats;
+
+/* Start the scheduler thread (opts nullable).  PDV_ESTATE if already serving. */
+int pdv_serve_start(struct pdv_ctx* ctx, const pdv_serve_opts* opts);
+/* Queue a request; *ticket identifies it.  Thread-safe.  PDV_EINVAL (bad
+ * parameters or beyond the serving limits), PDV_ENOMEM (larger than the
+ * whole memory budget), PDV_ESTATE (not serving or stopping). */
+int pdv_submit(struct pdv_ctx* ctx, const pdv_request* req, uint64_t* ticket);
+/* Status of a request: PDV_PENDING, or its final status (PDV_OK, PDV_EOVERFLOW,
+ * PDV_ECANCELLED, PDV_EDEVICE, ...).  wait_ms > 0 waits up to that long,
+ * < 0 waits until final.  A final status is reported once; the ticket is
+ * then forgotten (PDV_ENOTFOUND afterwards).  Thread-safe. */
+int pdv_poll(struct pdv_ctx* ctx, uint64_t ticket, int32_t wait_ms);
+/* Cancel a request that has not finished (it ends with PDV_ECANCELLED). */
+int pdv_cancel(struct pdv_ctx* ctx, uint64_t ticket);
+int pdv_serve_report(struct pdv_ctx* ctx, pdv_serve_stats* stats);
+/* Stop serving: drain != 0 finishes queued requests first, else cancels
+ * them.  Returns PDV_EDEVICE if the executor failed while serving. */
+int pdv_serve_stop(struct pdv_ctx* ctx, int32_t drain);
+
+/* A context without a device, usable only for serving with PDV_EXEC_HOST
+ * (scheduler tests on machines without a GPU). */
+int pdv_create_host(struct pdv_ctx** out);
 
 /*
  * Timing of the last transport launch on ctx: kernel time between HIP events

@@ -7,6 +7,7 @@ gfx950 offload only, packed FP32 instructions disabled in device code.
 from __future__ import annotations
 
 import concurrent.futures as cf
+import hashlib
 import os
 import shutil
 import subprocess
@@ -23,6 +24,17 @@ ARCH = os.environ.get("PDV_OFFLOAD_ARCH", "gfx950")
 SOURCES = ["transport.hip", "tables.hip", "stage2.hip", "pdv_api.cpp", "serve.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-I" + INC, "-I" + CSRC]
+
+
+def build_id() -> str:
+    """Hash of every source and header the library is built from."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)) + ["../../include/pdv.h"]:
+        path = os.path.normpath(os.path.join(CSRC, name))
+        if os.path.isfile(path):
+            with open(path, "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
 DEVICE = ["-x", "hip", "--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-fgpu-flush-denormals-to-zero"]
 
@@ -34,7 +46,7 @@ def hipcc() -> str:
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), "-c"] + COMMON + DEVICE + [os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc(), "-c"] + COMMON + DEVICE + ['-DPDV_BUILD_ID="' + build_id() + '"', os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -32,6 +33,12 @@ void launch_phase_cdf(hipStream_t s, int n_jobs, const void* jobs, int n_nodes, 
                       const double* basis, uint8_t* tables, SetDesc* descs);
 void launch_zero_u64(hipStream_t s, uint64_t* p, uint64_t n);
 int transport_lds_bytes(int real_bytes, int max_layers, int max_cells, int max_bins);
+hipError_t launch_synth(hipStream_t s, int n_frames, const void* frames, const ListEntry* entries, double r_scale,
+                        int n_chunks, int max_samples, float* partial, float* signal);
+hipError_t launch_stft(hipStream_t s, const float* signal, int n_windows, int nfft, int hop, void* tw, void* tr,
+                       float* win, float* map, bool build_tables);
+int synth_chunk();
+size_t synth_frame_bytes();
 hipError_t launch_transport(hipStream_t s, int precision, bool list, int grid, int block, int lds_bytes,
                             const SetDesc* descs, const uint8_t* tables, uint64_t* tallies, const WorkItem* items,
                             int n_items, uint32_t* queue, int persistent, int max_layers, int max_cells,
@@ -89,7 +96,8 @@ int pdv_ctx::ensure(DevBuf& b, size_t bytes, const char* what) {
 
 static bool is_finite(double v) { return std::isfinite(v); }
 
-static int validate(pdv_ctx* ctx, const pdv_params* p) {
+namespace pdv {
+int validate_params(pdv_ctx* ctx, const pdv_params* p) {
     auto bad = [&](const char* msg) {
         if (ctx) ctx->fail(PDV_EINVAL, "invalid parameters: %s", msg);
         return (int)PDV_EINVAL;
@@ -154,6 +162,7 @@ static int validate(pdv_ctx* ctx, const pdv_params* p) {
     if (p->pid_begin + p->n_packets < p->pid_begin) return bad("packet id range overflows");
     return PDV_OK;
 }
+}  // namespace pdv
 
 // ---------------------------------------------------------------------------
 // context
@@ -207,6 +216,16 @@ extern "C" int pdv_create(pdv_ctx** out, int device, uint64_t mem_budget, void* 
     return PDV_OK;
 }
 
+extern "C" int pdv_create_host(pdv_ctx** out) {
+    if (!out) return PDV_EINVAL;
+    pdv_ctx* c = new pdv_ctx();
+    c->device = -1;
+    c->ready = false;
+    c->mem_budget = 1ull << 34;
+    *out = c;
+    return PDV_OK;
+}
+
 extern "C" void pdv_destroy(pdv_ctx* ctx) {
     if (!ctx) return;
     ctx->shutdown_serving();
@@ -215,16 +234,18 @@ extern "C" void pdv_destroy(pdv_ctx* ctx) {
         (void)hipStreamSynchronize(ctx->stream);
     }
     ctx->release_all();
-    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
-    if (ctx->ev_a) (void)hipEventDestroy(ctx->ev_a);
-    if (ctx->ev_b) (void)hipEventDestroy(ctx->ev_b);
+    if (ctx->ready) {
+        if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+        if (ctx->ev_a) (void)hipEventDestroy(ctx->ev_a);
+        if (ctx->ev_b) (void)hipEventDestroy(ctx->ev_b);
+    }
     delete ctx;
 }
 
 void pdv_ctx::release_all() {
     DevBuf* all[] = {&descs, &tables, &tallies, &items, &queue, &layer_jobs, &phase_jobs, &density, &lists,
                      &list_counts, &mie_info, &mie_a, &mie_b, &mie_d, &mie_basis, &mie_gx, &mie_gw, &sg_entries,
-                     &sg_offsets, &sg_signal, &sg_map, &sg_frames};
+                     &sg_offsets, &sg_signal, &sg_map, &sg_frames, &sg_partial, &sg_tab};
     for (DevBuf* b : all) {
         if (b->ptr) (void)hipFree(b->ptr);
         b->ptr = nullptr;
@@ -234,6 +255,7 @@ void pdv_ctx::release_all() {
     host_pinned.clear();
     mem_used = 0;
     mie_key_valid = false;
+    stft_nfft = 0;
 }
 
 extern "C" const char* pdv_last_error(const pdv_ctx* ctx) {
@@ -241,7 +263,7 @@ extern "C" const char* pdv_last_error(const pdv_ctx* ctx) {
     return ctx->err.c_str();
 }
 
-extern "C" int pdv_validate(pdv_ctx* ctx, const pdv_params* p) { return validate(ctx, p); }
+extern "C" int pdv_validate(pdv_ctx* ctx, const pdv_params* p) { return validate_params(ctx, p); }
 
 // ---------------------------------------------------------------------------
 // Mie basis (cached per optics key)
@@ -277,7 +299,7 @@ int pdv_ctx::ensure_mie_basis(const pdv_params& p) {
 // ---------------------------------------------------------------------------
 // Batch preparation and launch
 // ---------------------------------------------------------------------------
-static void fill_desc(SetDesc& d, const pdv_params& p) {
+void pdv::fill_desc(SetDesc& d, const pdv_params& p) {
     std::memset(&d, 0, sizeof d);
     d.v_top = p.v_top;
     d.dzeta = (p.v_top - p.v_bottom) / (double)p.n_layers;
@@ -329,13 +351,13 @@ void pdv_ctx::default_opts(pdv_launch_opts& o, uint64_t total_packets, int n_set
     (void)n_sets;
     if (o.block_size <= 0) o.block_size = tuned.block_size > 0 ? tuned.block_size : 512;
     if (o.blocks_per_cu <= 0) o.blocks_per_cu = tuned.blocks_per_cu > 0 ? tuned.blocks_per_cu : 4;
-    if (o.persistent < 0) o.persistent = 1;
+    if (o.persistent < 0) o.persistent = tuned.persistent >= 0 ? tuned.persistent : 1;
     if (o.packets_per_item == 0) {
         uint64_t grid = (uint64_t)n_cu * (uint64_t)o.blocks_per_cu;
         uint64_t ppi = total_packets / (grid * 4 + 1);
         ppi = std::max<uint64_t>(ppi, 4096);
-        ppi = std::min<uint64_t>(ppi, tuned.packets_per_item > 0 ? tuned.packets_per_item : (1ull << 18));
-        o.packets_per_item = ppi;
+        ppi = std::min<uint64_t>(ppi, 1ull << 18);
+        o.packets_per_item = tuned.packets_per_item > 0 ? tuned.packets_per_item : ppi;
     }
 }
 
@@ -347,7 +369,7 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
     if (!outs && !keep_device) return fail(PDV_EINVAL, "NULL output array");
     const int precision = sets[0].precision;
     for (int i = 0; i < n; ++i) {
-        if (int r = validate(this, &sets[i])) return r;
+        if (int r = validate_params(this, &sets[i])) return r;
         if (sets[i].precision != precision) return fail(PDV_EINVAL, "all sets of a batch need one precision");
         if (outs && (!outs[i].w_fx || !outs[i].w2_fx)) return fail(PDV_EINVAL, "set %d: NULL w_fx or w2_fx", i);
     }
@@ -538,6 +560,7 @@ void pdv_ctx::unpack(const pdv_params& p, const SetDesc& d, const uint64_t* t, p
 
 extern "C" int pdv_spectrum(pdv_ctx* ctx, const pdv_params* p, pdv_spectrum_out* out) {
     if (!ctx) return PDV_EINVAL;
+    if (ctx->serve) return ctx->fail(PDV_ESTATE, "context is serving: submit requests instead");
     if (!out) return ctx->fail(PDV_EINVAL, "NULL output");
     return ctx->run_batch(p, 1, out, nullptr, 0, false);
 }
@@ -545,6 +568,7 @@ extern "C" int pdv_spectrum(pdv_ctx* ctx, const pdv_params* p, pdv_spectrum_out*
 extern "C" int pdv_spectrum_batch(pdv_ctx* ctx, const pdv_params* sets, int32_t n, pdv_spectrum_out* outs,
                                   const pdv_launch_opts* opts) {
     if (!ctx) return PDV_EINVAL;
+    if (ctx->serve) return ctx->fail(PDV_ESTATE, "context is serving: submit requests instead");
     return ctx->run_batch(sets, n, outs, opts, 0, false);
 }
 
@@ -557,5 +581,361 @@ extern "C" int pdv_last_launch(const pdv_ctx* ctx, float* kernel_ms, int32_t* gr
     if (grid) *grid = ctx->last_grid;
     if (block) *block = ctx->last_block;
     if (n_items) *n_items = ctx->last_items;
+    return PDV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Stage 2: beat synthesis and spectrogram
+// ---------------------------------------------------------------------------
+namespace {
+struct SynthFrameH {          // mirrors SynthFrame in stage2.hip
+    uint64_t entry_begin;
+    uint32_t n_entries;
+    int32_t s_begin, s_count, pad;
+};
+}  // namespace
+
+// Entries already on the device (in `lists` when entries == nullptr, else in
+// sg_entries); writes the record into sg_signal.
+int pdv_ctx::synthesize(int n_frames, const uint64_t* entry_begin, const uint64_t* n_entries,
+                        const ListEntry_* entries, double wavelength, double fs, int n_samples) {
+    if (synth_frame_bytes() != sizeof(SynthFrameH)) return fail(PDV_EDEVICE, "synth frame layout mismatch");
+    std::vector<SynthFrameH> fr(n_frames);
+    uint64_t max_entries = 0;
+    int max_samples = 1;
+    for (int k = 0; k < n_frames; ++k) {
+        const int64_t b0 = (int64_t)k * n_samples / n_frames, b1 = (int64_t)(k + 1) * n_samples / n_frames;
+        fr[k].entry_begin = entry_begin[k];
+        fr[k].n_entries = (uint32_t)n_entries[k];
+        fr[k].s_begin = (int32_t)b0;
+        fr[k].s_count = (int32_t)(b1 - b0);
+        fr[k].pad = 0;
+        max_entries = std::max<uint64_t>(max_entries, n_entries[k]);
+        max_samples = std::max(max_samples, (int)(b1 - b0));
+    }
+    const int chunk = synth_chunk();
+    const int n_chunks = (int)((max_entries + chunk - 1) / chunk);
+    int r;
+    if ((r = ensure(sg_frames, sizeof(SynthFrameH) * n_frames, "synthesis frames"))) return r;
+    if ((r = ensure(sg_partial, 4ull * std::max(1, n_chunks) * n_frames * max_samples, "synthesis partials")))
+        return r;
+    if ((r = ensure(sg_signal, 4ull * std::max(1, n_samples), "beat signal"))) return r;
+    if ((r = hip_check(hipMemcpyAsync(sg_frames.ptr, fr.data(), sizeof(SynthFrameH) * n_frames,
+                                      hipMemcpyHostToDevice, stream), "copy frames")))
+        return r;
+    const ListEntry* src = entries ? entries : (const ListEntry*)lists.ptr;
+    hipError_t e = launch_synth(stream, n_frames, sg_frames.ptr, src, 2.0 / (wavelength * fs), n_chunks,
+                                max_samples, (float*)sg_partial.ptr, (float*)sg_signal.ptr);
+    return hip_check(e, "beat synthesis kernels");
+}
+
+int pdv_ctx::stft(const float* d_signal, int n_samples, int nfft, int hop, int* n_windows) {
+    const int nw = n_samples >= nfft ? (n_samples - nfft) / hop + 1 : 0;
+    *n_windows = nw;
+    const int n = nfft / 2;
+    int r;
+    const size_t tab_bytes = 8ull * n + 8ull * (n + 1) + 4ull * nfft + 64;
+    if ((r = ensure(sg_tab, tab_bytes, "stft tables"))) return r;
+    if ((r = ensure(sg_map, 4ull * std::max(1, nw) * (n + 1), "spectrogram map"))) return r;
+    uint8_t* base = (uint8_t*)sg_tab.ptr;
+    void* tw = base;
+    void* tr = base + 8ull * n;
+    float* win = (float*)(base + 8ull * n + 8ull * (n + 1));
+    const bool build = stft_nfft != nfft;
+    hipError_t e = launch_stft(stream, d_signal, nw, nfft, hop, tw, tr, win, (float*)sg_map.ptr, build);
+    if ((r = hip_check(e, "stft kernels"))) return r;
+    stft_nfft = nfft;
+    return PDV_OK;
+}
+
+int pdv_spectrogram_internal(pdv_ctx* ctx, const pdv_params* p, const pdv_sg_params* sg, pdv_sg_out* out);
+
+static int check_sg(pdv_ctx* ctx, const pdv_sg_params* sg) {
+    if (!sg) return ctx->fail(PDV_EINVAL, "NULL spectrogram parameters");
+    if (sg->n_frames < 1 || sg->n_frames > 65535) return ctx->fail(PDV_EINVAL, "n_frames must be in [1, 65535]");
+    if (sg->nfft < 256 || sg->nfft > 8192 || (sg->nfft & (sg->nfft - 1)))
+        return ctx->fail(PDV_EINVAL, "nfft must be a power of two in [256, 8192]");
+    if (sg->hop < 1) return ctx->fail(PDV_EINVAL, "hop must be >= 1");
+    if (sg->n_samples < 1 || sg->n_samples > (1 << 28)) return ctx->fail(PDV_EINVAL, "n_samples out of range");
+    if (!(sg->fs > 0.0) || !std::isfinite(sg->fs)) return ctx->fail(PDV_EINVAL, "fs must be > 0");
+    if (sg->packets_per_frame > 0xFFFFFFFFull) return ctx->fail(PDV_EINVAL, "packets_per_frame must be < 2^32");
+    if (sg->list_capacity < 1 || sg->list_capacity > (1ull << 31))
+        return ctx->fail(PDV_EINVAL, "list_capacity must be in [1, 2^31]");
+    return PDV_OK;
+}
+
+extern "C" int pdv_spectrogram(pdv_ctx* ctx, const pdv_params* p, const pdv_sg_params* sg, pdv_sg_out* out) {
+    if (!ctx) return PDV_EINVAL;
+    if (ctx->serve) return ctx->fail(PDV_ESTATE, "context is serving: submit requests instead");
+    return pdv_spectrogram_internal(ctx, p, sg, out);
+}
+
+int pdv_spectrogram_internal(pdv_ctx* ctx, const pdv_params* p, const pdv_sg_params* sg, pdv_sg_out* out) {
+    if (!out || !out->map) return ctx->fail(PDV_EINVAL, "NULL spectrogram output map");
+    if (int r = check_sg(ctx, sg)) return r;
+    if (int r = validate_params(ctx, p)) return r;
+    if (!(p->wavelength > 0.0)) return ctx->fail(PDV_EINVAL, "wavelength must be > 0");
+    const int F = sg->n_frames;
+    std::vector<pdv_params> frames(F, *p);
+    for (int k = 0; k < F; ++k) {
+        frames[k].stream = p->stream + (uint32_t)k;
+        frames[k].n_packets = sg->packets_per_frame;
+    }
+    const int nb = p->n_bins;
+    std::vector<uint64_t> W((size_t)F * nb), W2((size_t)F * nb);
+    std::vector<pdv_spectrum_out> outs(F);
+    for (int k = 0; k < F; ++k) {
+        std::memset(&outs[k], 0, sizeof(pdv_spectrum_out));
+        outs[k].w_fx = W.data() + (size_t)k * nb;
+        outs[k].w2_fx = W2.data() + (size_t)k * nb;
+    }
+    if (int r = ctx->run_batch(frames.data(), F, outs.data(), nullptr, sg->list_capacity, true)) return r;
+    // detected entries per frame (the transport already synchronised the stream)
+    std::vector<uint64_t> counts(F), begin(F), kept(F);
+    if (int r = ctx->hip_check(hipMemcpy(counts.data(), ctx->list_counts.ptr, 8ull * F, hipMemcpyDeviceToHost),
+                               "copy list counts"))
+        return r;
+    int overflow = 0;
+    for (int k = 0; k < F; ++k) {
+        begin[k] = (uint64_t)k * sg->list_capacity;
+        kept[k] = std::min<uint64_t>(counts[k], sg->list_capacity);
+        if (counts[k] > sg->list_capacity) overflow = 1;
+    }
+    if (out->list_w || out->list_v || out->list_phase) {
+        if (!out->list_w || !out->list_v || !out->list_phase || out->list_stride == 0)
+            return ctx->fail(PDV_EINVAL, "list output needs list_w, list_v, list_phase and list_stride > 0");
+        std::vector<ListEntry> ent((size_t)F * sg->list_capacity);
+        if (int r = ctx->hip_check(hipMemcpy(ent.data(), ctx->lists.ptr, sizeof(ListEntry) * ent.size(),
+                                             hipMemcpyDeviceToHost), "copy lists"))
+            return r;
+        for (int k = 0; k < F; ++k) {
+            const uint64_t m = std::min<uint64_t>(kept[k], out->list_stride);
+            for (uint64_t i = 0; i < m; ++i) {
+                const ListEntry& e = ent[(size_t)k * sg->list_capacity + i];
+                out->list_w[(size_t)k * out->list_stride + i] = e.w;
+                out->list_v[(size_t)k * out->list_stride + i] = e.v;
+                out->list_phase[(size_t)k * out->list_stride + i] = e.phase;
+            }
+        }
+    }
+    if (int r = ctx->synthesize(F, begin.data(), kept.data(), nullptr, p->wavelength, sg->fs, sg->n_samples))
+        return r;
+    int nw = 0;
+    if (int r = ctx->stft((const float*)ctx->sg_signal.ptr, sg->n_samples, sg->nfft, sg->hop, &nw)) return r;
+    const size_t map_floats = (size_t)nw * (sg->nfft / 2 + 1);
+    if (map_floats)
+        if (int r = ctx->hip_check(hipMemcpyAsync(out->map, ctx->sg_map.ptr, 4 * map_floats, hipMemcpyDeviceToHost,
+                                                  ctx->stream), "copy map"))
+            return r;
+    if (out->signal)
+        if (int r = ctx->hip_check(hipMemcpyAsync(out->signal, ctx->sg_signal.ptr, 4ull * sg->n_samples,
+                                                  hipMemcpyDeviceToHost, ctx->stream), "copy signal"))
+            return r;
+    if (int r = ctx->hip_check(hipStreamSynchronize(ctx->stream), "spectrogram")) return r;
+    if (out->frame_counts) std::memcpy(out->frame_counts, counts.data(), 8ull * F);
+    out->n_windows = nw;
+    out->overflow = overflow;
+    if (out->spectrum) {
+        pdv_spectrum_out* s = out->spectrum;
+        if (!s->w_fx || !s->w2_fx) return ctx->fail(PDV_EINVAL, "spectrum output needs w_fx and w2_fx");
+        for (int b = 0; b < nb; ++b) {
+            uint64_t a = 0, a2 = 0;
+            for (int k = 0; k < F; ++k) { a += W[(size_t)k * nb + b]; a2 += W2[(size_t)k * nb + b]; }
+            s->w_fx[b] = a;
+            s->w2_fx[b] = a2;
+        }
+        std::memset(s->sinks_fx, 0, sizeof s->sinks_fx);
+        std::memset(&s->counters, 0, sizeof s->counters);
+        for (int k = 0; k < F; ++k) {
+            for (int j = 0; j < PDV_N_SINKS; ++j) s->sinks_fx[j] += outs[k].sinks_fx[j];
+            s->counters.packets += outs[k].counters.packets;
+            s->counters.collisions += outs[k].counters.collisions;
+            s->counters.surface += outs[k].counters.surface;
+            s->counters.exits += outs[k].counters.exits;
+            s->counters.detected += outs[k].counters.detected;
+        }
+        s->albedo = outs[0].albedo;
+        s->g = outs[0].g;
+    }
+    return overflow ? PDV_EOVERFLOW : PDV_OK;
+}
+
+extern "C" int pdv_beat_synthesize(pdv_ctx* ctx, int32_t n_frames, const uint64_t* offsets, const float* w,
+                                   const double* v, const uint32_t* phase_u32, double wavelength, double fs,
+                                   int32_t n_samples, float* signal) {
+    if (!ctx) return PDV_EINVAL;
+    if (ctx->serve) return ctx->fail(PDV_ESTATE, "context is serving: submit requests instead");
+    if (ctx->poisoned) return ctx->fail(PDV_EDEVICE, "context poisoned by an earlier device error");
+    if (n_frames < 1 || !offsets || !signal) return ctx->fail(PDV_EINVAL, "need n_frames >= 1, offsets, signal");
+    if (!(wavelength > 0.0) || !(fs > 0.0) || n_samples < 1) return ctx->fail(PDV_EINVAL, "bad wavelength/fs/n_samples");
+    const uint64_t total = offsets[n_frames];
+    for (int k = 0; k < n_frames; ++k)
+        if (offsets[k + 1] < offsets[k]) return ctx->fail(PDV_EINVAL, "offsets must be non-decreasing");
+    if (total && (!w || !v || !phase_u32)) return ctx->fail(PDV_EINVAL, "NULL entry arrays");
+    if (offsets[0] != 0) return ctx->fail(PDV_EINVAL, "offsets[0] must be 0");
+    if (int r = ctx->hip_check(hipSetDevice(ctx->device), "hipSetDevice")) return r;
+    std::vector<ListEntry> ent(total);
+    for (uint64_t i = 0; i < total; ++i) {
+        if (!(w[i] >= 0.0f)) return ctx->fail(PDV_EINVAL, "weights must be >= 0");
+        ent[i].w = w[i];
+        ent[i].phase = phase_u32[i];
+        ent[i].v = v[i];
+    }
+    int r;
+    if ((r = ctx->ensure(ctx->sg_entries, sizeof(ListEntry) * std::max<uint64_t>(1, total), "entries"))) return r;
+    if (total)
+        if ((r = ctx->hip_check(hipMemcpyAsync(ctx->sg_entries.ptr, ent.data(), sizeof(ListEntry) * total,
+                                               hipMemcpyHostToDevice, ctx->stream), "copy entries")))
+            return r;
+    std::vector<uint64_t> begin(n_frames), cnt(n_frames);
+    for (int k = 0; k < n_frames; ++k) {
+        begin[k] = offsets[k];
+        cnt[k] = offsets[k + 1] - offsets[k];
+        if (cnt[k] > 0xFFFFFFFFull) return ctx->fail(PDV_EINVAL, "too many entries in one frame");
+    }
+    if ((r = ctx->synthesize(n_frames, begin.data(), cnt.data(), (const ListEntry*)ctx->sg_entries.ptr, wavelength,
+                             fs, n_samples)))
+        return r;
+    if ((r = ctx->hip_check(hipMemcpyAsync(signal, ctx->sg_signal.ptr, 4ull * n_samples, hipMemcpyDeviceToHost,
+                                           ctx->stream), "copy signal")))
+        return r;
+    return ctx->hip_check(hipStreamSynchronize(ctx->stream), "beat synthesis");
+}
+
+extern "C" int pdv_stft(pdv_ctx* ctx, const float* signal, int32_t n_samples, int32_t nfft, int32_t hop, float* map,
+                        int32_t* n_windows) {
+    if (!ctx) return PDV_EINVAL;
+    if (ctx->serve) return ctx->fail(PDV_ESTATE, "context is serving: submit requests instead");
+    if (ctx->poisoned) return ctx->fail(PDV_EDEVICE, "context poisoned by an earlier device error");
+    if (!signal || !map || n_samples < 1) return ctx->fail(PDV_EINVAL, "need signal, map and n_samples >= 1");
+    if (nfft < 256 || nfft > 8192 || (nfft & (nfft - 1)))
+        return ctx->fail(PDV_EINVAL, "nfft must be a power of two in [256, 8192]");
+    if (hop < 1) return ctx->fail(PDV_EINVAL, "hop must be >= 1");
+    if (int r = ctx->hip_check(hipSetDevice(ctx->device), "hipSetDevice")) return r;
+    int r;
+    if ((r = ctx->ensure(ctx->sg_signal, 4ull * n_samples, "signal"))) return r;
+    if ((r = ctx->hip_check(hipMemcpyAsync(ctx->sg_signal.ptr, signal, 4ull * n_samples, hipMemcpyHostToDevice,
+                                           ctx->stream), "copy signal")))
+        return r;
+    int nw = 0;
+    if ((r = ctx->stft((const float*)ctx->sg_signal.ptr, n_samples, nfft, hop, &nw))) return r;
+    if (nw)
+        if ((r = ctx->hip_check(hipMemcpyAsync(map, ctx->sg_map.ptr, 4ull * nw * (nfft / 2 + 1),
+                                               hipMemcpyDeviceToHost, ctx->stream), "copy map")))
+            return r;
+    if ((r = ctx->hip_check(hipStreamSynchronize(ctx->stream), "stft"))) return r;
+    if (n_windows) *n_windows = nw;
+    return PDV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner
+// ---------------------------------------------------------------------------
+#ifndef PDV_BUILD_ID
+#define PDV_BUILD_ID "unknown"
+#endif
+
+extern "C" const char* pdv_build_id(void) { return PDV_BUILD_ID; }
+
+extern "C" int pdv_set_launch_defaults(pdv_ctx* ctx, const pdv_launch_opts* o) {
+    if (!ctx || !o) return PDV_EINVAL;
+    if (o->block_size != 0 && o->block_size != 256 && o->block_size != 512 && o->block_size != 1024)
+        return ctx->fail(PDV_EINVAL, "block_size must be 256, 512 or 1024");
+    if (o->blocks_per_cu < 0 || o->blocks_per_cu > 64) return ctx->fail(PDV_EINVAL, "blocks_per_cu out of range");
+    if (o->packets_per_item > (1ull << 31)) return ctx->fail(PDV_EINVAL, "packets_per_item out of range");
+    ctx->tuned.block_size = o->block_size;
+    ctx->tuned.blocks_per_cu = o->blocks_per_cu;
+    ctx->tuned.packets_per_item = o->packets_per_item;
+    ctx->tuned.persistent = o->persistent;
+    return PDV_OK;
+}
+
+extern "C" int pdv_autotune(pdv_ctx* ctx, const pdv_params* sets, int32_t n, int32_t repeats,
+                            pdv_launch_opts* best, pdv_tune_report* report) {
+    if (!ctx) return PDV_EINVAL;
+    if (ctx->serve) return ctx->fail(PDV_ESTATE, "context is serving");
+    if (!sets || n < 1) return ctx->fail(PDV_EINVAL, "need sets");
+    if (repeats < 1) repeats = 3;
+    std::vector<std::vector<uint64_t>> W(n), W2(n);
+    std::vector<pdv_spectrum_out> outs(n);
+    auto run = [&](const pdv_launch_opts& o, float* ms) -> int {
+        for (int i = 0; i < n; ++i) {
+            W[i].assign(sets[i].n_bins, 0);
+            W2[i].assign(sets[i].n_bins, 0);
+            std::memset(&outs[i], 0, sizeof(pdv_spectrum_out));
+            outs[i].w_fx = W[i].data();
+            outs[i].w2_fx = W2[i].data();
+        }
+        int r = ctx->run_batch(sets, n, outs.data(), &o, 0, false);
+        *ms = ctx->last_kernel_ms;
+        return r;
+    };
+    // reference: default shape
+    pdv_launch_opts def{0, 0, 0, -1, 0};
+    float ms = 0;
+    if (int r = run(def, &ms)) return r;
+    std::vector<std::vector<uint64_t>> refW = W, refW2 = W2;
+    std::vector<std::array<uint64_t, PDV_N_SINKS>> refS(n);
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < PDV_N_SINKS; ++k) refS[i][k] = outs[i].sinks_fx[k];
+    auto median_ms = [&](const pdv_launch_opts& o, double* med, bool* same) -> int {
+        std::vector<float> t;
+        *same = true;
+        for (int rep = 0; rep < repeats; ++rep) {
+            if (int r = run(o, &ms)) return r;
+            t.push_back(ms);
+            for (int i = 0; i < n; ++i) {
+                if (W[i] != refW[i] || W2[i] != refW2[i]) *same = false;
+                for (int k = 0; k < PDV_N_SINKS; ++k)
+                    if (outs[i].sinks_fx[k] != refS[i][k]) *same = false;
+            }
+        }
+        std::sort(t.begin(), t.end());
+        *med = t[t.size() / 2];
+        return PDV_OK;
+    };
+    std::vector<pdv_launch_opts> cands;
+    for (int bs : {256, 512, 1024}) {
+        for (uint64_t ppi : {1ull << 12, 1ull << 14, 1ull << 16, 1ull << 18}) {
+            for (int bpc : {1, 2, 4, 8}) cands.push_back(pdv_launch_opts{bs, bpc, ppi, 1, 0});
+            cands.push_back(pdv_launch_opts{bs, 1, ppi, 0, 0});
+        }
+    }
+    double best_ms = 1e300, worst_ms = 0, def_ms = 0;
+    bool invariant = true;
+    pdv_launch_opts best_o = def;
+    {
+        bool same = true;
+        if (int r = median_ms(def, &def_ms, &same)) return r;
+        invariant = invariant && same;
+        best_ms = def_ms;
+        worst_ms = def_ms;
+    }
+    for (const pdv_launch_opts& o : cands) {
+        double med = 0;
+        bool same = true;
+        if (int r = median_ms(o, &med, &same)) return r;
+        invariant = invariant && same;
+        worst_ms = std::max(worst_ms, med);
+        if (med < best_ms) {
+            best_ms = med;
+            best_o = o;
+        }
+    }
+    if (report) {
+        report->candidates = (int32_t)cands.size() + 1;
+        report->invariant = invariant ? 1 : 0;
+        report->best_ms = best_ms;
+        report->worst_ms = worst_ms;
+        report->default_ms = def_ms;
+    }
+    if (!invariant) return ctx->fail(PDV_EDEVICE, "launch shapes gave different tallies");
+    if (best_o.block_size != 0) {
+        ctx->tuned.block_size = best_o.block_size;
+        ctx->tuned.blocks_per_cu = best_o.blocks_per_cu;
+        ctx->tuned.packets_per_item = best_o.packets_per_item;
+        ctx->tuned.persistent = best_o.persistent;
+    }
+    if (best) *best = best_o;
     return PDV_OK;
 }

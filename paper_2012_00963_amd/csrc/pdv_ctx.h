@@ -40,9 +40,15 @@ struct TunedLaunch {
     int32_t block_size = 0;
     int32_t blocks_per_cu = 0;
     uint64_t packets_per_item = 0;
+    int32_t persistent = -1;
 };
 
 struct ServeEngine;   // serving loop (serve.cpp)
+namespace pdv {
+int validate_params(pdv_ctx* ctx, const pdv_params* p);
+void fill_desc(SetDesc& d, const pdv_params& p);
+}
+using ListEntry_ = pdv::ListEntry;
 
 struct pdv_ctx {
     int device = 0;
@@ -64,7 +70,8 @@ struct pdv_ctx {
     bool mie_key_valid = false;
     int mie_nodes = 0;
     // stage-2 buffers
-    DevBuf sg_entries, sg_offsets, sg_signal, sg_map, sg_frames;
+    DevBuf sg_entries, sg_offsets, sg_signal, sg_map, sg_frames, sg_partial, sg_tab;
+    int stft_nfft = 0;   // nfft the cached STFT tables were built for
     std::vector<HostPinned> host_pinned;
 
     // host staging
@@ -92,6 +99,9 @@ struct pdv_ctx {
     void default_opts(pdv_launch_opts& o, uint64_t total_packets, int n_sets) const;
     int run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, const pdv_launch_opts* opts,
                   uint64_t list_capacity, bool keep_device);
+    int synthesize(int n_frames, const uint64_t* entry_begin, const uint64_t* n_entries, const ListEntry_* entries,
+                   double wavelength, double fs, int n_samples);
+    int stft(const float* d_signal, int n_samples, int nfft, int hop, int* n_windows);
     void unpack(const pdv_params& p, const pdv::SetDesc& d, const uint64_t* t, pdv_spectrum_out& o);
     void release_all();
     void shutdown_serving();

@@ -1,9 +1,680 @@
 // Serving engine: continuous batching of spectrum requests on one GPU.
+//
+// Clients submit requests (a parameter set, optionally a spectrogram) from
+// any thread; one scheduler thread owns the device.  Every iteration it
+//   1. admits waiting requests in arrival order while a slot and enough of
+//      the memory budget are free (a request larger than the whole budget is
+//      refused at submission),
+//   2. builds the device tables of the newly admitted requests into their
+//      slots (layer depths, Mie phase CDF from the resident Mie basis),
+//   3. issues the next slice of packets of every active request as work
+//      items of one persistent transport launch (replayed from a captured
+//      hipGraph when enabled),
+//   4. retires requests whose packets are all transported: copies their
+//      tallies to the caller's buffers, runs their spectrogram if asked,
+//      and stamps the latency (submission -> result on the host).
+// Requests that arrive while an iteration runs join the next one, so their
+// work overlaps on the device with older requests.  Tallies are integer sums
+// over the same (seed, stream, packet id) random streams whatever the slicing,
+// so a result is bitwise the same alone and in any mix.
+//
+// An executor interface separates the scheduler from the device: the HIP
+// executor runs the kernels; a host executor (for scheduler tests without a
+// GPU) completes items arithmetically, can be slowed down and can fail at a
+// chosen iteration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <unordered_map>
+
 #include "pdv_ctx.h"
 
-struct ServeEngine {};
+using namespace pdv;
 
-void pdv_ctx::shutdown_serving() { serve.reset(); }
+int pdv_spectrogram_internal(pdv_ctx* ctx, const pdv_params* p, const pdv_sg_params* sg, pdv_sg_out* out);
+
+namespace pdv {
+int validate_params(pdv_ctx* ctx, const pdv_params* p);
+void fill_desc(SetDesc& d, const pdv_params& p);
+void launch_layer_tables(hipStream_t s, int n_jobs, const void* jobs, const double* density, uint8_t* tables,
+                         SetDesc* descs);
+void launch_phase_cdf(hipStream_t s, int n_jobs, const void* jobs, int n_nodes, const void* info,
+                      const double* basis, uint8_t* tables, SetDesc* descs);
+void launch_zero_u64(hipStream_t s, uint64_t* p, uint64_t n);
+int transport_lds_bytes(int real_bytes, int max_layers, int max_cells, int max_bins);
+hipError_t launch_transport_dev(hipStream_t s, int precision, int grid, int block, int lds_bytes,
+                                const SetDesc* descs, const uint8_t* tables, uint64_t* tallies,
+                                const WorkItem* items, const int* n_items_dev, uint32_t* queue, int max_layers,
+                                int max_cells, int max_bins);
+}  // namespace pdv
+
+namespace {
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Req {
+    uint64_t ticket = 0;
+    pdv_params p{};
+    std::vector<double> density, phase;
+    bool want_sg = false;
+    pdv_sg_params sg{};
+    pdv_spectrum_out* out = nullptr;
+    pdv_sg_out* sg_out = nullptr;
+    int status = PDV_PENDING;          // final status once != PDV_PENDING
+    bool cancel = false;
+    bool waited = false;               // counted once in admission waits
+    int slot = -1;
+    uint64_t issued = 0;               // packets handed to launches
+    uint64_t footprint = 0;            // bytes of device memory while active
+    double t_submit = 0, t_admit = 0, t_done = 0;
+};
+
+uint64_t slot_tally_words(int max_bins) { return tally_words(max_bins); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// executors
+// ---------------------------------------------------------------------------
+struct Executor {
+    virtual ~Executor() = default;
+    virtual int init() = 0;
+    virtual int prepare(const std::vector<Req*>& admitted) = 0;
+    virtual int run(const std::vector<WorkItem>& items) = 0;
+    virtual int collect(Req* r) = 0;
+    virtual const char* error() const = 0;
+};
+
+struct ServeEngine {
+    pdv_ctx* ctx = nullptr;
+    pdv_serve_opts opts{};
+    std::unique_ptr<Executor> exec;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<std::shared_ptr<Req>> pending;
+    std::vector<std::shared_ptr<Req>> active;
+    std::unordered_map<uint64_t, std::shared_ptr<Req>> by_ticket;
+    std::vector<int> free_slots;
+    std::vector<int> slot_bins;        // n_bins of the request holding each slot
+    uint64_t mem_in_use = 0;
+    uint64_t next_ticket = 1;
+    bool stopping = false, drain = true, failed = false;
+    std::string fail_msg;
+    std::thread th;
+    // statistics
+    uint64_t n_submitted = 0, n_completed = 0, n_failed = 0, n_cancelled = 0, n_iterations = 0;
+    uint64_t n_packets = 0, n_events = 0;
+    uint64_t n_admit_waits = 0;
+    std::vector<double> latencies_ms;
+    double t_start = 0, busy_s = 0;
+
+    void loop();
+    uint64_t footprint(const Req& r) const;
+    int active_bins(int slot) const;
+};
+
+// HIP executor: slots of a fixed-capacity device arena.
+struct HipExecutor : Executor {
+    ServeEngine* E;
+    pdv_ctx* ctx;
+    DevBuf descs, tables, tallies, items, nitems, queue, layer_jobs, phase_jobs, density;
+    WorkItem* h_items = nullptr;     // pinned staging for graph replays
+    int* h_nitems = nullptr;
+    int max_items = 0;
+    int grid = 0, block = 512, lds = 0;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    std::string err;
+
+    explicit HipExecutor(ServeEngine* e) : E(e), ctx(e->ctx) {}
+    ~HipExecutor() override {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        DevBuf* all[] = {&descs, &tables, &tallies, &items, &nitems, &queue, &layer_jobs, &phase_jobs, &density};
+        for (DevBuf* b : all)
+            if (b->ptr) {
+                (void)hipFree(b->ptr);
+                ctx->mem_used -= b->cap;
+            }
+        if (h_items) (void)hipHostFree(h_items);
+        if (h_nitems) (void)hipHostFree(h_nitems);
+    }
+    const char* error() const override { return err.c_str(); }
+    int hipfail(hipError_t e, const char* what) {
+        if (e == hipSuccess) return PDV_OK;
+        err = std::string(what) + ": " + hipGetErrorString(e);
+        return PDV_EDEVICE;
+    }
+    int init() override {
+        const int S = E->opts.max_active;
+        int r;
+        if ((r = ctx->ensure(descs, sizeof(SetDesc) * S, "serve descriptors"))) return r;
+        if ((r = ctx->ensure(tables, TableLayout::BYTES * (size_t)S, "serve tables"))) return r;
+        if ((r = ctx->ensure(tallies, 8ull * slot_tally_words(E->opts.max_bins) * S, "serve tallies"))) return r;
+        max_items = E->opts.max_items;
+        if ((r = ctx->ensure(items, sizeof(WorkItem) * max_items, "serve items"))) return r;
+        if ((r = ctx->ensure(nitems, 256, "serve item count"))) return r;
+        if ((r = ctx->ensure(queue, 256, "serve queue"))) return r;
+        if ((r = ctx->ensure(layer_jobs, sizeof(LayerJob) * S, "serve layer jobs"))) return r;
+        if ((r = ctx->ensure(phase_jobs, sizeof(PhaseJob) * S, "serve phase jobs"))) return r;
+        if ((r = hipfail(hipHostMalloc((void**)&h_items, sizeof(WorkItem) * max_items, hipHostMallocDefault),
+                         "pinned items"))) return r;
+        if ((r = hipfail(hipHostMalloc((void**)&h_nitems, 256, hipHostMallocDefault), "pinned count"))) return r;
+        block = 512;
+        grid = ctx->n_cu * 4;
+        lds = transport_lds_bytes(E->opts.precision == PDV_FP64 ? 8 : 4, E->opts.max_layers, E->opts.max_angles - 1,
+                                  E->opts.max_bins);
+        return PDV_OK;
+    }
+    int prepare(const std::vector<Req*>& adm) override {
+        if (adm.empty()) return PDV_OK;
+        hipStream_t s = ctx->stream;
+        std::vector<SetDesc> d(adm.size());
+        std::vector<LayerJob> lj(adm.size());
+        std::vector<double> dens;
+        for (size_t i = 0; i < adm.size(); ++i) {
+            const Req* q = adm[i];
+            fill_desc(d[i], q->p);
+            d[i].tab_offset = (uint64_t)q->slot * TableLayout::BYTES;
+            d[i].tally_offset = (uint64_t)q->slot * slot_tally_words(E->opts.max_bins);
+            LayerJob& L = lj[i];
+            L = LayerJob{q->p.v_bottom, q->p.v_top, q->p.v0, q->p.tau_total, q->p.n_layers, q->p.density_kind,
+                         d[i].tab_offset, dens.size(), q->slot, 0};
+            if (q->p.density_kind == PDV_DENSITY_TABLE) dens.insert(dens.end(), q->density.begin(), q->density.end());
+        }
+        int r;
+        if ((r = ctx->ensure(density, 8 * std::max<size_t>(1, dens.size()), "serve density"))) return r;
+        for (size_t i = 0; i < adm.size(); ++i)
+            if ((r = hipfail(hipMemcpyAsync((SetDesc*)descs.ptr + adm[i]->slot, &d[i], sizeof(SetDesc),
+                                            hipMemcpyHostToDevice, s), "copy descriptor")))
+                return r;
+        if ((r = hipfail(hipMemcpyAsync(layer_jobs.ptr, lj.data(), sizeof(LayerJob) * lj.size(),
+                                        hipMemcpyHostToDevice, s), "copy layer jobs")))
+            return r;
+        if (!dens.empty())
+            if ((r = hipfail(hipMemcpyAsync(density.ptr, dens.data(), 8 * dens.size(), hipMemcpyHostToDevice, s),
+                             "copy densities")))
+                return r;
+        launch_layer_tables(s, (int)lj.size(), layer_jobs.ptr, (const double*)density.ptr, (uint8_t*)tables.ptr,
+                            (SetDesc*)descs.ptr);
+        // phase tables: caller tables, then Mie sets grouped by optics key
+        std::vector<PhaseJob> pj;
+        for (const Req* q : adm) {
+            if (q->p.phase_kind != PDV_PHASE_TABLE) continue;
+            uint8_t* dst = (uint8_t*)tables.ptr + (uint64_t)q->slot * TableLayout::BYTES + TableLayout::PHASE;
+            if ((r = hipfail(hipMemcpyAsync(dst, q->phase.data(), 8 * q->phase.size(), hipMemcpyHostToDevice, s),
+                             "copy phase table")))
+                return r;
+            pj.push_back(PhaseJob{1, q->p.n_angles, 0.0, 0.0, (uint64_t)q->slot * TableLayout::BYTES, q->slot, 0});
+        }
+        if (!pj.empty()) {
+            if ((r = hipfail(hipMemcpyAsync(phase_jobs.ptr, pj.data(), sizeof(PhaseJob) * pj.size(),
+                                            hipMemcpyHostToDevice, s), "copy phase jobs")))
+                return r;
+            launch_phase_cdf(s, (int)pj.size(), phase_jobs.ptr, 0, nullptr, nullptr, (uint8_t*)tables.ptr,
+                             (SetDesc*)descs.ptr);
+            if ((r = hipfail(hipStreamSynchronize(s), "phase tables"))) return r;
+        }
+        std::vector<char> done(adm.size(), 0);
+        for (size_t i = 0; i < adm.size(); ++i) {
+            if (adm[i]->p.phase_kind != PDV_PHASE_MIE || done[i]) continue;
+            if ((r = ctx->ensure_mie_basis(adm[i]->p))) {
+                err = ctx->err;
+                return r;
+            }
+            pj.clear();
+            for (size_t j = i; j < adm.size(); ++j) {
+                const pdv_params& p = adm[j]->p;
+                if (p.phase_kind != PDV_PHASE_MIE || done[j]) continue;
+                MieKey k{p.m_re, p.m_im, p.wavelength, p.d_min, p.d_max, p.n_size_nodes, p.n_angles};
+                if (!(k == ctx->mie_key)) continue;
+                pj.push_back(PhaseJob{0, p.n_angles, p.d_median, p.sigma_ln,
+                                      (uint64_t)adm[j]->slot * TableLayout::BYTES, adm[j]->slot, 0});
+                done[j] = 1;
+            }
+            if ((r = hipfail(hipMemcpyAsync(phase_jobs.ptr, pj.data(), sizeof(PhaseJob) * pj.size(),
+                                            hipMemcpyHostToDevice, s), "copy phase jobs")))
+                return r;
+            launch_phase_cdf(s, (int)pj.size(), phase_jobs.ptr, ctx->mie_nodes, ctx->mie_info.ptr,
+                             (const double*)ctx->mie_basis.ptr, (uint8_t*)tables.ptr, (SetDesc*)descs.ptr);
+            if ((r = hipfail(hipStreamSynchronize(s), "mie phase tables"))) return r;
+        }
+        for (const Req* q : adm)
+            launch_zero_u64(s, (uint64_t*)tallies.ptr + (uint64_t)q->slot * slot_tally_words(E->opts.max_bins),
+                            slot_tally_words(E->opts.max_bins));
+        return hipfail(hipGetLastError(), "table kernels");
+    }
+    int record(hipStream_t s) {
+        hipError_t e;
+        if ((e = hipMemcpyAsync(items.ptr, h_items, sizeof(WorkItem) * max_items, hipMemcpyHostToDevice, s)))
+            return hipfail(e, "copy items");
+        if ((e = hipMemcpyAsync(nitems.ptr, h_nitems, sizeof(int), hipMemcpyHostToDevice, s)))
+            return hipfail(e, "copy item count");
+        launch_zero_u64(s, (uint64_t*)queue.ptr, 1);
+        e = launch_transport_dev(s, E->opts.precision, grid, block, lds, (const SetDesc*)descs.ptr,
+                                 (const uint8_t*)tables.ptr, (uint64_t*)tallies.ptr, (const WorkItem*)items.ptr,
+                                 (const int*)nitems.ptr, (uint32_t*)queue.ptr, E->opts.max_layers,
+                                 E->opts.max_angles - 1, E->opts.max_bins);
+        return hipfail(e, "transport launch");
+    }
+    int run(const std::vector<WorkItem>& its) override {
+        if (its.empty()) return PDV_OK;
+        hipStream_t s = ctx->stream;
+        std::memcpy(h_items, its.data(), sizeof(WorkItem) * its.size());
+        *h_nitems = (int)its.size();
+        int r;
+        if (E->opts.use_graph) {
+            if (!gexec) {
+                if ((r = hipfail(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture")))
+                    return r;
+                const int rr = record(s);
+                hipError_t e = hipStreamEndCapture(s, &graph);
+                if (rr) return rr;
+                if ((r = hipfail(e, "end capture"))) return r;
+                if ((r = hipfail(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0), "graph instantiate")))
+                    return r;
+            }
+            if ((r = hipfail(hipGraphLaunch(gexec, s), "graph launch"))) return r;
+        } else {
+            if ((r = record(s))) return r;
+        }
+        return hipfail(hipStreamSynchronize(s), "transport");
+    }
+    int collect(Req* q) override {
+        const int nb = q->p.n_bins;
+        std::vector<uint64_t> t(tally_words(nb));
+        const uint64_t* src = (const uint64_t*)tallies.ptr + (uint64_t)q->slot * slot_tally_words(E->opts.max_bins);
+        int r;
+        if ((r = hipfail(hipMemcpy(t.data(), src, 8 * t.size(), hipMemcpyDeviceToHost), "copy tallies"))) return r;
+        SetDesc d;
+        if ((r = hipfail(hipMemcpy(&d, (SetDesc*)descs.ptr + q->slot, sizeof d, hipMemcpyDeviceToHost),
+                         "copy descriptor")))
+            return r;
+        // the slot's tally block has the request's own n_bins layout
+        ctx->unpack(q->p, d, t.data(), *q->out);
+        if (q->want_sg) {
+            int rc = pdv_spectrogram_internal(ctx, &q->p, &q->sg, q->sg_out);
+            if (rc != PDV_OK && rc != PDV_EOVERFLOW) {
+                err = ctx->err;
+                return rc;
+            }
+            if (rc == PDV_EOVERFLOW) return PDV_EOVERFLOW;
+        }
+        return PDV_OK;
+    }
+};
+
+// Host executor for scheduler tests: every packet goes to the "undetected"
+// sink with unit weight; optional delay per packet; optional failure.
+struct HostExecutor : Executor {
+    ServeEngine* E;
+    std::vector<std::vector<uint64_t>> slots;
+    uint64_t iter = 0;
+    std::string err;
+    explicit HostExecutor(ServeEngine* e) : E(e) {}
+    const char* error() const override { return err.c_str(); }
+    int init() override {
+        slots.assign(E->opts.max_active, std::vector<uint64_t>(slot_tally_words(E->opts.max_bins), 0));
+        return PDV_OK;
+    }
+    int prepare(const std::vector<Req*>& adm) override {
+        for (Req* q : adm) std::fill(slots[q->slot].begin(), slots[q->slot].end(), 0);
+        return PDV_OK;
+    }
+    int run(const std::vector<WorkItem>& its) override {
+        ++iter;
+        if (E->opts.host_fail_iteration && iter == (uint64_t)E->opts.host_fail_iteration) {
+            err = "injected executor failure";
+            return PDV_EDEVICE;
+        }
+        uint64_t pk = 0;
+        for (const WorkItem& w : its) {
+            const int nb = E->active_bins(w.set);
+            std::vector<uint64_t>& t = slots[w.set];
+            t[tw_sinks(nb) + SK_UNDETECTED] += w.count << 32;
+            t[tw_counts(nb) + C_PACKETS] += w.count;
+            t[tw_counts(nb) + C_EXITS] += w.count;
+            pk += w.count;
+        }
+        if (E->opts.host_ns_per_packet > 0)
+            std::this_thread::sleep_for(std::chrono::nanoseconds((uint64_t)(E->opts.host_ns_per_packet * pk)));
+        return PDV_OK;
+    }
+    int collect(Req* q) override {
+        SetDesc d;
+        std::memset(&d, 0, sizeof d);
+        d.albedo = q->p.albedo;
+        d.g_mean = q->p.hg_g;
+        E->ctx->unpack(q->p, d, slots[q->slot].data(), *q->out);
+        return PDV_OK;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// scheduler
+// ---------------------------------------------------------------------------
+uint64_t ServeEngine::footprint(const Req& r) const {
+    uint64_t b = TableLayout::BYTES + 8ull * slot_tally_words(opts.max_bins);
+    if (r.want_sg) {
+        b += 16ull * r.sg.list_capacity * (uint64_t)r.sg.n_frames;          // detected lists
+        b += (uint64_t)r.sg.n_frames * (TableLayout::BYTES + 8ull * tally_words(r.p.n_bins));
+        b += 8ull * (uint64_t)r.sg.n_samples + 4ull * (uint64_t)r.sg.nfft * 64;
+    }
+    return b;
+}
+
+int ServeEngine::active_bins(int slot) const { return slot_bins[slot]; }
+
+void ServeEngine::loop() {
+    for (;;) {
+        std::vector<Req*> admitted;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            while (!pending.empty()) {
+                std::shared_ptr<Req> q = pending.front();
+                if (q->cancel) {
+                    pending.pop_front();
+                    q->status = PDV_ECANCELLED;
+                    q->t_done = now_s();
+                    ++n_cancelled;
+                    cv_done.notify_all();
+                    continue;
+                }
+                const uint64_t fp = footprint(*q);
+                if (free_slots.empty() || mem_in_use + fp > opts.mem_budget) {
+                    if (!q->waited) {
+                        q->waited = true;
+                        ++n_admit_waits;
+                    }
+                    break;
+                }
+                pending.pop_front();
+                q->slot = free_slots.back();
+                free_slots.pop_back();
+                slot_bins[q->slot] = q->p.n_bins;
+                q->footprint = fp;
+                mem_in_use += fp;
+                q->t_admit = now_s();
+                active.push_back(q);
+                admitted.push_back(q.get());
+            }
+            if (active.empty()) {
+                if (stopping && (pending.empty() || !drain)) {
+                    for (auto& q : pending) {
+                        q->status = PDV_ECANCELLED;
+                        ++n_cancelled;
+                    }
+                    pending.clear();
+                    cv_done.notify_all();
+                    return;
+                }
+                cv_work.wait_for(lk, std::chrono::milliseconds(2));
+                continue;
+            }
+        }
+        const double t0 = now_s();
+        int rc = exec->prepare(admitted);
+        std::vector<WorkItem> items;
+        if (rc == PDV_OK) {
+            std::unique_lock<std::mutex> lk(mu);
+            uint64_t open = 0;
+            for (auto& q : active)
+                if (!q->cancel && q->issued < q->p.n_packets) ++open;
+            const uint64_t share = open ? std::max<uint64_t>(opts.packets_per_item, opts.packets_per_iteration / open)
+                                        : 0;
+            for (auto& q : active) {
+                if (q->cancel) continue;
+                uint64_t take = std::min<uint64_t>(q->p.n_packets - q->issued, share);
+                while (take > 0 && (int)items.size() < opts.max_items) {
+                    const uint64_t c = std::min<uint64_t>(take, opts.packets_per_item);
+                    items.push_back(WorkItem{(uint32_t)q->slot, 0, q->p.pid_begin + q->issued, c});
+                    q->issued += c;
+                    take -= c;
+                }
+            }
+        }
+        if (rc == PDV_OK) rc = exec->run(items);
+        busy_s += now_s() - t0;
+        ++n_iterations;
+        // retire finished requests
+        std::vector<std::shared_ptr<Req>> done_now;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            for (auto& q : active)
+                if (rc != PDV_OK || q->cancel || q->issued >= q->p.n_packets) done_now.push_back(q);
+        }
+        for (auto& q : done_now) {
+            int st = rc;
+            if (st == PDV_OK && q->cancel) st = PDV_ECANCELLED;
+            if (st == PDV_OK) st = exec->collect(q.get());
+            std::unique_lock<std::mutex> lk(mu);
+            if (st != PDV_OK && st != PDV_EOVERFLOW && st != PDV_ECANCELLED && fail_msg.empty())
+                fail_msg = exec->error();
+            q->t_done = now_s();
+            if (st == PDV_OK || st == PDV_EOVERFLOW) {
+                ++n_completed;
+                latencies_ms.push_back((q->t_done - q->t_submit) * 1e3);
+                n_packets += q->out->counters.packets;
+                n_events += q->out->counters.collisions + q->out->counters.surface;
+            } else if (st == PDV_ECANCELLED) {
+                ++n_cancelled;
+            } else {
+                ++n_failed;
+            }
+            q->status = st;
+            free_slots.push_back(q->slot);
+            mem_in_use -= q->footprint;
+            active.erase(std::find(active.begin(), active.end(), q));
+            cv_done.notify_all();
+        }
+        if (rc != PDV_OK) {
+            // the device failed: every waiting request fails the same way
+            std::unique_lock<std::mutex> lk(mu);
+            failed = true;
+            for (auto& q : pending) {
+                q->status = rc;
+                ++n_failed;
+            }
+            pending.clear();
+            cv_done.notify_all();
+            return;
+        }
+    }
+}
+
+void pdv_ctx::shutdown_serving() {
+    if (!serve) return;
+    {
+        std::unique_lock<std::mutex> lk(serve->mu);
+        serve->stopping = true;
+        serve->drain = false;
+    }
+    serve->cv_work.notify_all();
+    if (serve->th.joinable()) serve->th.join();
+    serve.reset();
+}
 
 pdv_ctx::pdv_ctx() = default;
 pdv_ctx::~pdv_ctx() = default;
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" int pdv_serve_start(pdv_ctx* ctx, const pdv_serve_opts* o) {
+    if (!ctx) return PDV_EINVAL;
+    if (ctx->serve) return ctx->fail(PDV_ESTATE, "serving already started");
+    pdv_serve_opts opts{};
+    if (o) opts = *o;
+    if (opts.executor != PDV_EXEC_HIP && opts.executor != PDV_EXEC_HOST)
+        return ctx->fail(PDV_EINVAL, "unknown executor");
+    if (opts.executor == PDV_EXEC_HIP) {
+        if (!ctx->ready) return ctx->fail(PDV_ESTATE, "the HIP executor needs a device context");
+        if (ctx->poisoned) return ctx->fail(PDV_EDEVICE, "context poisoned by an earlier device error");
+    }
+    if (opts.max_active <= 0) opts.max_active = 256;
+    if (opts.max_items <= 0) opts.max_items = 8192;
+    if (opts.packets_per_iteration == 0) opts.packets_per_iteration = 1ull << 25;
+    if (opts.packets_per_item == 0) opts.packets_per_item = 1ull << 16;
+    if (opts.max_layers <= 0) opts.max_layers = 1024;
+    if (opts.max_angles <= 0) opts.max_angles = 2048;
+    if (opts.max_bins <= 0) opts.max_bins = 1024;
+    if (opts.max_active > 4096 || opts.max_items > (1 << 20) || opts.max_layers > MAX_LAYERS ||
+        opts.max_angles > MAX_ANGLES || opts.max_angles < 16 || opts.max_bins > MAX_BINS ||
+        opts.packets_per_item > (1ull << 31))
+        return ctx->fail(PDV_EINVAL, "serving limits out of range");
+    if (opts.precision != PDV_FP32 && opts.precision != PDV_FP64) return ctx->fail(PDV_EINVAL, "bad precision");
+    if (opts.mem_budget == 0) opts.mem_budget = ctx->mem_budget ? ctx->mem_budget / 2 : (1ull << 34);
+    auto E = std::make_unique<ServeEngine>();
+    E->ctx = ctx;
+    E->opts = opts;
+    E->slot_bins.assign(opts.max_active, 1);
+    for (int s = opts.max_active - 1; s >= 0; --s) E->free_slots.push_back(s);
+    if (opts.executor == PDV_EXEC_HIP) E->exec = std::make_unique<HipExecutor>(E.get());
+    else E->exec = std::make_unique<HostExecutor>(E.get());
+    if (int r = E->exec->init()) {
+        std::string msg = E->exec->error();
+        if (msg.empty()) msg = ctx->err;
+        return ctx->fail(r, "serving executor: %s", msg.c_str());
+    }
+    E->t_start = now_s();
+    ServeEngine* raw = E.get();
+    ctx->serve = std::move(E);
+    raw->th = std::thread([raw] { raw->loop(); });
+    return PDV_OK;
+}
+
+extern "C" int pdv_submit(pdv_ctx* ctx, const pdv_request* req, uint64_t* ticket) {
+    if (!ctx || !req || !ticket || !req->out) return PDV_EINVAL;
+    ServeEngine* E = ctx->serve.get();
+    if (!E) return PDV_ESTATE;
+    const pdv_params& p = req->params;
+    if (validate_params(nullptr, &p) != PDV_OK) return PDV_EINVAL;
+    if (!req->out->w_fx || !req->out->w2_fx) return PDV_EINVAL;
+    if (p.precision != E->opts.precision) return PDV_EINVAL;
+    if (p.n_layers > E->opts.max_layers || p.n_bins > E->opts.max_bins ||
+        (p.phase_kind != PDV_PHASE_HG && p.n_angles > E->opts.max_angles))
+        return PDV_EINVAL;
+    auto q = std::make_shared<Req>();
+    q->p = p;
+    if (p.density_kind == PDV_DENSITY_TABLE) {
+        q->density.assign(p.density, p.density + p.n_layers);
+        q->p.density = q->density.data();
+    }
+    if (p.phase_kind == PDV_PHASE_TABLE) {
+        q->phase.assign(p.phase, p.phase + p.n_angles);
+        q->p.phase = q->phase.data();
+    }
+    if (req->sg) {
+        if (!req->sg_out || !req->sg_out->map) return PDV_EINVAL;
+        if (E->opts.executor != PDV_EXEC_HIP) return PDV_EINVAL;
+        q->want_sg = true;
+        q->sg = *req->sg;
+        q->sg_out = req->sg_out;
+    }
+    q->out = req->out;
+    if (E->footprint(*q) > E->opts.mem_budget) return PDV_ENOMEM;
+    {
+        std::unique_lock<std::mutex> lk(E->mu);
+        if (E->stopping || E->failed) return E->failed ? PDV_EDEVICE : PDV_ESTATE;
+        q->ticket = E->next_ticket++;
+        q->t_submit = now_s();
+        E->pending.push_back(q);
+        E->by_ticket[q->ticket] = q;
+        ++E->n_submitted;
+        *ticket = q->ticket;
+    }
+    E->cv_work.notify_all();
+    return PDV_OK;
+}
+
+extern "C" int pdv_poll(pdv_ctx* ctx, uint64_t ticket, int32_t wait_ms) {
+    if (!ctx) return PDV_EINVAL;
+    ServeEngine* E = ctx->serve.get();
+    if (!E) return PDV_ESTATE;
+    std::unique_lock<std::mutex> lk(E->mu);
+    auto it = E->by_ticket.find(ticket);
+    if (it == E->by_ticket.end()) return PDV_ENOTFOUND;
+    std::shared_ptr<Req> q = it->second;
+    auto done = [&] { return q->status != PDV_PENDING; };
+    if (!done() && wait_ms != 0) {
+        if (wait_ms < 0) E->cv_done.wait(lk, done);
+        else E->cv_done.wait_for(lk, std::chrono::milliseconds(wait_ms), done);
+    }
+    const int st = q->status;
+    if (st != PDV_PENDING) E->by_ticket.erase(ticket);
+    return st;
+}
+
+extern "C" int pdv_cancel(pdv_ctx* ctx, uint64_t ticket) {
+    if (!ctx) return PDV_EINVAL;
+    ServeEngine* E = ctx->serve.get();
+    if (!E) return PDV_ESTATE;
+    std::unique_lock<std::mutex> lk(E->mu);
+    auto it = E->by_ticket.find(ticket);
+    if (it == E->by_ticket.end()) return PDV_ENOTFOUND;
+    it->second->cancel = true;
+    E->cv_work.notify_all();
+    return PDV_OK;
+}
+
+extern "C" int pdv_serve_report(pdv_ctx* ctx, pdv_serve_stats* s) {
+    if (!ctx || !s) return PDV_EINVAL;
+    ServeEngine* E = ctx->serve.get();
+    if (!E) return PDV_ESTATE;
+    std::unique_lock<std::mutex> lk(E->mu);
+    std::memset(s, 0, sizeof *s);
+    s->submitted = E->n_submitted;
+    s->completed = E->n_completed;
+    s->failed = E->n_failed;
+    s->cancelled = E->n_cancelled;
+    s->iterations = E->n_iterations;
+    s->packets = E->n_packets;
+    s->events = E->n_events;
+    s->admission_waits = E->n_admit_waits;
+    s->active = (uint32_t)E->active.size();
+    s->pending = (uint32_t)E->pending.size();
+    s->mem_in_use = E->mem_in_use;
+    s->busy_s = E->busy_s;
+    s->wall_s = now_s() - E->t_start;
+    std::vector<double> l = E->latencies_ms;
+    if (!l.empty()) {
+        std::sort(l.begin(), l.end());
+        auto pct = [&](double q) {
+            const double pos = q * (double)(l.size() - 1);
+            const size_t i = (size_t)pos;
+            const double f = pos - (double)i;
+            return i + 1 < l.size() ? l[i] * (1.0 - f) + l[i + 1] * f : l[i];
+        };
+        s->p50_ms = pct(0.50);
+        s->p99_ms = pct(0.99);
+        s->max_ms = l.back();
+        double sum = 0;
+        for (double v : l) sum += v;
+        s->mean_ms = sum / (double)l.size();
+    }
+    return PDV_OK;
+}
+
+extern "C" int pdv_serve_stop(pdv_ctx* ctx, int32_t drain) {
+    if (!ctx) return PDV_EINVAL;
+    ServeEngine* E = ctx->serve.get();
+    if (!E) return PDV_ESTATE;
+    {
+        std::unique_lock<std::mutex> lk(E->mu);
+        E->stopping = true;
+        E->drain = drain != 0;
+    }
+    E->cv_work.notify_all();
+    if (E->th.joinable()) E->th.join();
+    const bool failed = E->failed;
+    std::string msg = E->fail_msg;
+    ctx->serve.reset();
+    if (failed) return ctx->fail(PDV_EDEVICE, "serving stopped after an executor failure: %s", msg.c_str());
+    return PDV_OK;
+}

@@ -218,8 +218,10 @@ __global__ void __launch_bounds__(1024)
 transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ tables,
                  uint64_t* __restrict__ tallies, const WorkItem* __restrict__ items, int n_items,
                  uint32_t* __restrict__ queue, int persistent, int max_layers, int max_cells, int max_bins,
-                 ListEntry* __restrict__ lists, uint64_t* __restrict__ list_counts) {
+                 ListEntry* __restrict__ lists, uint64_t* __restrict__ list_counts,
+                 const int* __restrict__ n_items_dev) {
     extern __shared__ __align__(16) uint8_t lds[];
+    if (n_items_dev) n_items = *n_items_dev;   // item count from device memory (graph replays)
     __shared__ WorkItem s_item;
     __shared__ int s_item_idx;
     __shared__ uint32_t s_next;
@@ -482,7 +484,25 @@ static hipError_t launch_one(hipStream_t s, int grid, int block, int lds, const 
                              uint32_t* queue, int persistent, int max_layers, int max_cells, int max_bins,
                              ListEntry* lists, uint64_t* list_counts) {
     hipLaunchKernelGGL((transport_kernel<Real, LIST>), dim3(grid), dim3(block), lds, s, descs, tables, tallies,
-                       items, n_items, queue, persistent, max_layers, max_cells, max_bins, lists, list_counts);
+                       items, n_items, queue, persistent, max_layers, max_cells, max_bins, lists, list_counts,
+                       (const int*)nullptr);
+    return hipGetLastError();
+}
+
+// Persistent launch whose item count is read from device memory, so a
+// captured graph can be replayed with a different item list.
+hipError_t launch_transport_dev(hipStream_t s, int precision, int grid, int block, int lds_bytes,
+                                const SetDesc* descs, const uint8_t* tables, uint64_t* tallies,
+                                const WorkItem* items, const int* n_items_dev, uint32_t* queue, int max_layers,
+                                int max_cells, int max_bins) {
+    if (precision == 1)
+        hipLaunchKernelGGL((transport_kernel<double, false>), dim3(grid), dim3(block), lds_bytes, s, descs, tables,
+                           tallies, items, 0, queue, 1, max_layers, max_cells, max_bins, (ListEntry*)nullptr,
+                           (uint64_t*)nullptr, n_items_dev);
+    else
+        hipLaunchKernelGGL((transport_kernel<float, false>), dim3(grid), dim3(block), lds_bytes, s, descs, tables,
+                           tallies, items, 0, queue, 1, max_layers, max_cells, max_bins, (ListEntry*)nullptr,
+                           (uint64_t*)nullptr, n_items_dev);
     return hipGetLastError();
 }
 

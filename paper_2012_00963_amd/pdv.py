@@ -89,7 +89,9 @@ class SgOut(ctypes.Structure):
     _fields_ = [("map", ctypes.POINTER(ctypes.c_float)), ("signal", ctypes.POINTER(ctypes.c_float)),
                 ("frame_counts", ctypes.POINTER(ctypes.c_uint64)),
                 ("n_windows", ctypes.c_int32), ("overflow", ctypes.c_int32),
-                ("spectrum", ctypes.POINTER(SpectrumOut))]
+                ("spectrum", ctypes.POINTER(SpectrumOut)),
+                ("list_w", ctypes.POINTER(ctypes.c_float)), ("list_v", ctypes.POINTER(ctypes.c_double)),
+                ("list_phase", ctypes.POINTER(ctypes.c_uint32)), ("list_stride", ctypes.c_uint64)]
 
 
 _lib = None
@@ -248,3 +250,294 @@ class Context:
         g, b, it = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         self.lib.pdv_last_launch(self.h, ctypes.byref(ms), ctypes.byref(g), ctypes.byref(b), ctypes.byref(it))
         return {"kernel_ms": float(ms.value), "grid": g.value, "block": b.value, "items": it.value}
+
+
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def _spectrogram(self, p: dict, sg: dict, want_signal: bool = False, want_spectrum: bool = False,
+                 want_lists: bool = False) -> dict:
+    """Spectrogram of ``p`` with stage-2 settings ``sg`` (n_frames,
+    packets_per_frame, fs, n_samples, nfft, hop, list_capacity)."""
+    keep = []
+    cp = make_params(p, keep)
+    s = SgParams(int(sg["n_frames"]), int(sg["nfft"]), int(sg["hop"]), int(sg["n_samples"]),
+                 int(sg["packets_per_frame"]), int(sg.get("list_capacity", max(4096, sg["packets_per_frame"] // 10))),
+                 float(sg["fs"]))
+    nfft, n_s = int(sg["nfft"]), int(sg["n_samples"])
+    n_win = (n_s - nfft) // int(sg["hop"]) + 1 if n_s >= nfft else 0
+    m = np.zeros((max(n_win, 1), nfft // 2 + 1), dtype=np.float32)
+    o = SgOut()
+    o.map = _fptr(m)
+    sig = np.zeros(n_s, dtype=np.float32) if want_signal else None
+    if sig is not None:
+        o.signal = _fptr(sig)
+    fc = np.zeros(int(sg["n_frames"]), dtype=np.uint64)
+    o.frame_counts = _u64ptr(fc)
+    spec = None
+    if want_spectrum:
+        nb = int(p["n_bins"])
+        W, W2 = np.zeros(nb, dtype=np.uint64), np.zeros(nb, dtype=np.uint64)
+        spec = SpectrumOut()
+        spec.w_fx, spec.w2_fx = _u64ptr(W), _u64ptr(W2)
+        o.spectrum = ctypes.pointer(spec)
+    if want_lists:
+        stride = int(s.list_capacity)
+        nf = int(sg["n_frames"])
+        lw = np.zeros(nf * stride, dtype=np.float32)
+        lv = np.zeros(nf * stride, dtype=np.float64)
+        lph = np.zeros(nf * stride, dtype=np.uint32)
+        o.list_w, o.list_v = _fptr(lw), lv.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        o.list_phase = lph.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+        o.list_stride = stride
+    rc = self.lib.pdv_spectrogram(self.h, ctypes.byref(cp), ctypes.byref(s), ctypes.byref(o))
+    if rc not in (0, -4):
+        raise PdvError(rc, self.error())
+    res = {"map": m[:o.n_windows], "n_windows": int(o.n_windows), "overflow": bool(o.overflow),
+           "frame_counts": fc, "status": rc}
+    if sig is not None:
+        res["signal"] = sig
+    if spec is not None:
+        res["spectrum"] = _result(spec, W, W2, None, nb)
+    if want_lists:
+        lists = []
+        for k in range(int(sg["n_frames"])):
+            m = int(min(fc[k], stride))
+            sl = slice(k * stride, k * stride + m)
+            lists.append({"w": lw[sl].copy(), "v": lv[sl].copy(), "phase_u32": lph[sl].copy()})
+        res["lists"] = lists
+    return res
+
+
+def _beat_synthesize(self, lists, wavelength: float, fs: float, n_samples: int) -> np.ndarray:
+    """Beat signal from caller lists: lists[k] = dict(w, v, phase_u32)."""
+    offs = np.zeros(len(lists) + 1, dtype=np.uint64)
+    for k, L in enumerate(lists):
+        offs[k + 1] = offs[k] + len(L["w"])
+    w = np.ascontiguousarray(np.concatenate([np.asarray(L["w"], np.float32) for L in lists]) if len(lists) else
+                             np.zeros(0, np.float32), dtype=np.float32)
+    v = np.ascontiguousarray(np.concatenate([np.asarray(L["v"], np.float64) for L in lists]), dtype=np.float64)
+    ph = np.ascontiguousarray(np.concatenate([np.asarray(L["phase_u32"], np.uint32) for L in lists]), dtype=np.uint32)
+    out = np.zeros(int(n_samples), dtype=np.float32)
+    self._check(self.lib.pdv_beat_synthesize(
+        self.h, len(lists), _u64ptr(offs), _fptr(w), v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+        ph.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), float(wavelength), float(fs), int(n_samples),
+        _fptr(out)))
+    return out
+
+
+def _stft(self, signal, nfft: int, hop: int) -> np.ndarray:
+    s = np.ascontiguousarray(signal, dtype=np.float32)
+    n_win = (len(s) - nfft) // hop + 1 if len(s) >= nfft else 0
+    m = np.zeros((max(n_win, 1), nfft // 2 + 1), dtype=np.float32)
+    nw = ctypes.c_int32()
+    self._check(self.lib.pdv_stft(self.h, _fptr(s), len(s), int(nfft), int(hop), _fptr(m), ctypes.byref(nw)))
+    return m[:nw.value]
+
+
+Context.spectrogram = _spectrogram
+Context.beat_synthesize = _beat_synthesize
+Context.stft = _stft
+
+
+# ---------------------------------------------------------------------------
+# serving
+# ---------------------------------------------------------------------------
+EXEC_HIP, EXEC_HOST = 0, 1
+
+
+class ServeOpts(ctypes.Structure):
+    _fields_ = [("max_active", ctypes.c_int32), ("max_items", ctypes.c_int32),
+                ("mem_budget", ctypes.c_uint64), ("packets_per_iteration", ctypes.c_uint64),
+                ("packets_per_item", ctypes.c_uint64), ("max_layers", ctypes.c_int32),
+                ("max_angles", ctypes.c_int32), ("max_bins", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("executor", ctypes.c_int32),
+                ("host_fail_iteration", ctypes.c_int32), ("host_ns_per_packet", ctypes.c_double)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("params", Params), ("sg", ctypes.POINTER(SgParams)), ("out", ctypes.POINTER(SpectrumOut)),
+                ("sg_out", ctypes.POINTER(SgOut))]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("cancelled", ctypes.c_uint64), ("iterations", ctypes.c_uint64), ("packets", ctypes.c_uint64),
+                ("events", ctypes.c_uint64), ("admission_waits", ctypes.c_uint64), ("mem_in_use", ctypes.c_uint64),
+                ("active", ctypes.c_uint32), ("pending", ctypes.c_uint32),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("busy_s", ctypes.c_double), ("wall_s", ctypes.c_double)]
+
+
+def _load_serving(lib):
+    P, V = ctypes.POINTER, ctypes.c_void_p
+    lib.pdv_serve_start.argtypes = [V, P(ServeOpts)]
+    lib.pdv_submit.argtypes = [V, P(Request), P(ctypes.c_uint64)]
+    lib.pdv_poll.argtypes = [V, ctypes.c_uint64, ctypes.c_int32]
+    lib.pdv_cancel.argtypes = [V, ctypes.c_uint64]
+    lib.pdv_serve_report.argtypes = [V, P(ServeStats)]
+    lib.pdv_serve_stop.argtypes = [V, ctypes.c_int32]
+    lib.pdv_create_host.argtypes = [P(V)]
+
+
+class Ticket:
+    """A submitted request and the buffers its results land in."""
+
+    def __init__(self, ticket, req, bufs, keep, sg_bufs=None):
+        self.ticket, self.req, self.bufs, self.keep, self.sg_bufs = ticket, req, bufs, keep, sg_bufs
+        self.status = PDV_PENDING
+
+    def result(self) -> dict:
+        W, W2, nb = self.bufs
+        res = _result(self.req.out.contents, W, W2, None, nb)
+        if self.sg_bufs is not None:
+            m, o = self.sg_bufs
+            res["spectrogram"] = {"map": m[:o.n_windows], "n_windows": int(o.n_windows), "overflow": bool(o.overflow)}
+        return res
+
+
+class Server:
+    """Serving session on a Context (or on a host-only context for the
+    PDV_EXEC_HOST scheduler executor)."""
+
+    def __init__(self, ctx: "Context | None" = None, **opts):
+        self.lib = load()
+        _load_serving(self.lib)
+        self._own = None
+        if ctx is None:
+            h = ctypes.c_void_p()
+            rc = self.lib.pdv_create_host(ctypes.byref(h))
+            if rc != 0:
+                raise PdvError(rc, "host context")
+            self.h = h
+            self._own = h
+            opts.setdefault("executor", EXEC_HOST)
+        else:
+            self.h = ctx.h
+        o = ServeOpts()
+        for k, v in opts.items():
+            setattr(o, k, v)
+        rc = self.lib.pdv_serve_start(self.h, ctypes.byref(o))
+        if rc != 0:
+            msg = self.lib.pdv_last_error(self.h).decode()
+            if self._own:
+                self.lib.pdv_destroy(self._own)
+            raise PdvError(rc, msg)
+
+    def submit(self, p: dict, sg: dict | None = None) -> Ticket:
+        keep = []
+        req = Request()
+        req.params = make_params(p, keep)
+        nb = int(p["n_bins"])
+        W, W2 = np.zeros(nb, dtype=np.uint64), np.zeros(nb, dtype=np.uint64)
+        out = SpectrumOut()
+        out.w_fx, out.w2_fx = _u64ptr(W), _u64ptr(W2)
+        keep += [out, W, W2]
+        req.out = ctypes.pointer(out)
+        sg_bufs = None
+        if sg is not None:
+            s = SgParams(int(sg["n_frames"]), int(sg["nfft"]), int(sg["hop"]), int(sg["n_samples"]),
+                         int(sg["packets_per_frame"]),
+                         int(sg.get("list_capacity", max(4096, sg["packets_per_frame"] // 10))), float(sg["fs"]))
+            n_s, nfft = int(sg["n_samples"]), int(sg["nfft"])
+            n_win = (n_s - nfft) // int(sg["hop"]) + 1 if n_s >= nfft else 0
+            m = np.zeros((max(n_win, 1), nfft // 2 + 1), dtype=np.float32)
+            so = SgOut()
+            so.map = _fptr(m)
+            keep += [s, so, m]
+            req.sg = ctypes.pointer(s)
+            req.sg_out = ctypes.pointer(so)
+            sg_bufs = (m, so)
+        t = ctypes.c_uint64()
+        rc = self.lib.pdv_submit(self.h, ctypes.byref(req), ctypes.byref(t))
+        if rc != 0:
+            raise PdvError(rc, "submit rejected")
+        keep.append(req)
+        return Ticket(t.value, req, (W, W2, nb), keep, sg_bufs)
+
+    def poll(self, tk: Ticket, wait_ms: int = 0) -> int:
+        if tk.status != PDV_PENDING:
+            return tk.status
+        rc = self.lib.pdv_poll(self.h, tk.ticket, int(wait_ms))
+        if rc != PDV_PENDING:
+            tk.status = rc
+        return rc
+
+    def cancel(self, tk: Ticket) -> int:
+        return self.lib.pdv_cancel(self.h, tk.ticket)
+
+    def stats(self) -> dict:
+        s = ServeStats()
+        rc = self.lib.pdv_serve_report(self.h, ctypes.byref(s))
+        if rc != 0:
+            raise PdvError(rc, "stats")
+        return {n: getattr(s, n) for n, _ in ServeStats._fields_}
+
+    def stop(self, drain: bool = True) -> int:
+        rc = self.lib.pdv_serve_stop(self.h, 1 if drain else 0)
+        self.last_error = self.lib.pdv_last_error(self.h).decode()
+        if self._own:
+            self.lib.pdv_destroy(self._own)
+            self._own = None
+        return rc
+
+
+# ---------------------------------------------------------------------------
+# autotuning
+# ---------------------------------------------------------------------------
+class TuneReport(ctypes.Structure):
+    _fields_ = [("candidates", ctypes.c_int32), ("invariant", ctypes.c_int32), ("best_ms", ctypes.c_double),
+                ("worst_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
+
+
+def build_id() -> str:
+    lib = load()
+    lib.pdv_build_id.restype = ctypes.c_char_p
+    return lib.pdv_build_id().decode()
+
+
+def _shape_bucket(sets: list) -> str:
+    total = sum(int(s["n_packets"]) for s in sets)
+    n = len(sets)
+    nb = "1" if n == 1 else ("16" if n <= 16 else "many")
+    return f"p{int(sets[0].get('precision', 0))}-n{nb}-pk{max(0, int(math.log2(max(total, 1))))}"
+
+
+def _autotune(self, sets: list, repeats: int = 3, cache_path: str | None = None) -> dict:
+    """Tune the batch launch shape on ``sets`` (or load it from the JSON
+    cache keyed by device, library build and workload shape) and make it the
+    context's default."""
+    import json
+    lib = self.lib
+    lib.pdv_autotune.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.POINTER(LaunchOpts), ctypes.POINTER(TuneReport)]
+    lib.pdv_set_launch_defaults.argtypes = [ctypes.c_void_p, ctypes.POINTER(LaunchOpts)]
+    key = f"{build_id()}/{_shape_bucket(sets)}"
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f)
+        if key in cache:
+            e = cache[key]
+            o = LaunchOpts(e["block_size"], e["blocks_per_cu"], e["packets_per_item"], e["persistent"], 0)
+            self._check(lib.pdv_set_launch_defaults(self.h, ctypes.byref(o)))
+            return dict(e, cached=True)
+    keep = []
+    arr = (Params * len(sets))()
+    for i, p in enumerate(sets):
+        arr[i] = make_params(p, keep)
+    best, rep = LaunchOpts(), TuneReport()
+    self._check(lib.pdv_autotune(self.h, arr, len(sets), int(repeats), ctypes.byref(best), ctypes.byref(rep)))
+    e = {"block_size": best.block_size, "blocks_per_cu": best.blocks_per_cu,
+         "packets_per_item": best.packets_per_item, "persistent": best.persistent,
+         "candidates": rep.candidates, "invariant": bool(rep.invariant), "best_ms": rep.best_ms,
+         "worst_ms": rep.worst_ms, "default_ms": rep.default_ms}
+    if cache_path:
+        cache[key] = e
+        with open(cache_path, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+    return dict(e, cached=False)
+
+
+Context.autotune = _autotune

@@ -183,3 +183,20 @@ def test_large_mie_full_size(ctx, oracle_mc):
     rate_s = os_["sinks"]["detected"] / sample["n_packets"]
     sd = math.sqrt(max(os_["W2"].sum(), 1e-30)) / sample["n_packets"]
     assert abs(rate_full - rate_s) < 5 * sd + 1e-12
+
+
+def test_autotune_is_result_invariant(ctx, tmp_path):
+    from paper_2012_00963_amd import pdv
+    sets = wl.batched_sets(16, seed=21, packets_scale=0.02)
+    ref = ctx.spectrum_batch(sets)
+    cache = str(tmp_path / "tune.json")
+    rep = ctx.autotune(sets, repeats=1, cache_path=cache)
+    assert rep["invariant"] and rep["candidates"] > 40 and not rep["cached"]
+    assert rep["best_ms"] <= rep["default_ms"] + 1e-9
+    again = ctx.autotune(sets, repeats=1, cache_path=cache)
+    assert again["cached"] and again["block_size"] == rep["block_size"]
+    # the tuned default reproduces the reference tallies
+    tuned = ctx.spectrum_batch(sets)
+    for a, b in zip(ref, tuned):
+        assert np.array_equal(a["w_fx"], b["w_fx"]) and a["sinks_fx"] == b["sinks_fx"]
+    ctx.lib.pdv_set_launch_defaults(ctx.h, pdv.LaunchOpts(0, 0, 0, -1, 0))
