@@ -10,6 +10,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "pdv.h"
@@ -32,6 +33,7 @@ void launch_mie_basis(hipStream_t s, int n, int nmax, int n_angles, const void* 
 void launch_phase_cdf(hipStream_t s, int n_jobs, const void* jobs, int n_nodes, const void* info,
                       const double* basis, uint8_t* tables, SetDesc* descs);
 void launch_zero_u64(hipStream_t s, uint64_t* p, uint64_t n);
+void launch_copy_desc_fields(hipStream_t s, SetDesc* descs, const int* src, int n);
 int transport_lds_bytes(int real_bytes, int max_layers, int max_cells, int max_bins);
 hipError_t launch_synth(hipStream_t s, int n_frames, const void* frames, const ListEntry* entries, double r_scale,
                         int n_chunks, int max_samples, float* partial, float* signal);
@@ -245,7 +247,7 @@ extern "C" void pdv_destroy(pdv_ctx* ctx) {
 void pdv_ctx::release_all() {
     DevBuf* all[] = {&descs, &tables, &tallies, &items, &queue, &layer_jobs, &phase_jobs, &density, &lists,
                      &list_counts, &mie_info, &mie_a, &mie_b, &mie_d, &mie_basis, &mie_gx, &mie_gw, &sg_entries,
-                     &sg_offsets, &sg_signal, &sg_map, &sg_frames, &sg_partial, &sg_tab};
+                     &sg_offsets, &sg_signal, &sg_map, &sg_frames, &sg_partial, &sg_tab, &dup_src};
     for (DevBuf* b : all) {
         if (b->ptr) (void)hipFree(b->ptr);
         b->ptr = nullptr;
@@ -299,6 +301,36 @@ int pdv_ctx::ensure_mie_basis(const pdv_params& p) {
 // ---------------------------------------------------------------------------
 // Batch preparation and launch
 // ---------------------------------------------------------------------------
+// Everything the table kernels read: sets with equal keys get equal tables.
+static std::string table_key(const pdv_params& p) {
+    std::string k;
+    auto put = [&](const void* x, size_t nb) { k.append((const char*)x, nb); };
+    put(&p.v_bottom, 8);
+    put(&p.v_top, 8);
+    put(&p.density_kind, 4);
+    put(&p.n_layers, 4);
+    put(&p.tau_total, 8);
+    if (p.density_kind == PDV_DENSITY_EXP) put(&p.v0, 8);
+    if (p.density_kind == PDV_DENSITY_TABLE) put(p.density, 8ull * p.n_layers);
+    put(&p.phase_kind, 4);
+    if (p.phase_kind == PDV_PHASE_TABLE) {
+        put(&p.n_angles, 4);
+        put(p.phase, 8ull * p.n_angles);
+    }
+    if (p.phase_kind == PDV_PHASE_MIE) {
+        put(&p.n_angles, 4);
+        put(&p.wavelength, 8);
+        put(&p.m_re, 8);
+        put(&p.m_im, 8);
+        put(&p.d_median, 8);
+        put(&p.sigma_ln, 8);
+        put(&p.d_min, 8);
+        put(&p.d_max, 8);
+        put(&p.n_size_nodes, 4);
+    }
+    return k;
+}
+
 void pdv::fill_desc(SetDesc& d, const pdv_params& p) {
     std::memset(&d, 0, sizeof d);
     d.v_top = p.v_top;
@@ -384,38 +416,55 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
         return fail(PDV_EINVAL, "block_size must be 256, 512 or 1024");
 
     // ---- host-side packing ----
+    // Sets whose tables would be identical (same cloud and optics, e.g. the
+    // frames of a spectrogram) share one table block; only the first of them
+    // runs the table kernels.
     h_desc.assign(n, SetDesc{});
-    h_layer.assign(n, LayerJob{});
+    h_layer.clear();
     h_phase.clear();
     h_density.clear();
+    h_src.assign(n, 0);
+    std::unordered_map<std::string, int> first_with_key;
+    int n_unique = 0;
     uint64_t tally_words_total = 0;
     int max_layers = 1, max_cells = 0, max_bins = 1;
     for (int i = 0; i < n; ++i) {
         const pdv_params& p = sets[i];
         SetDesc& d = h_desc[i];
         fill_desc(d, p);
-        d.tab_offset = (uint64_t)i * TableLayout::BYTES;
+        auto ins = first_with_key.emplace(table_key(p), i);
+        const int src = ins.first->second;
+        h_src[i] = src;
+        if (src == i) {
+            d.tab_offset = (uint64_t)n_unique * TableLayout::BYTES;
+            ++n_unique;
+            LayerJob L;
+            L.v_bottom = p.v_bottom;
+            L.v_top = p.v_top;
+            L.v0 = p.v0;
+            L.tau_total = p.tau_total;
+            L.n_layers = p.n_layers;
+            L.density_kind = p.density_kind;
+            L.tab_offset = d.tab_offset;
+            L.density_offset = h_density.size();
+            L.set = i;
+            L.pad = 0;
+            if (p.density_kind == PDV_DENSITY_TABLE)
+                h_density.insert(h_density.end(), p.density, p.density + p.n_layers);
+            h_layer.push_back(L);
+        } else {
+            d.tab_offset = h_desc[src].tab_offset;
+        }
         d.tally_offset = tally_words_total;
         tally_words_total += tally_words(p.n_bins);
         d.list_offset = (uint64_t)i * list_capacity;
         d.list_capacity = list_capacity;
         if (list_capacity) d.flags |= SF_LIST;
-        LayerJob& L = h_layer[i];
-        L.v_bottom = p.v_bottom;
-        L.v_top = p.v_top;
-        L.v0 = p.v0;
-        L.tau_total = p.tau_total;
-        L.n_layers = p.n_layers;
-        L.density_kind = p.density_kind;
-        L.tab_offset = d.tab_offset;
-        L.density_offset = h_density.size();
-        L.set = i;
-        L.pad = 0;
-        if (p.density_kind == PDV_DENSITY_TABLE) h_density.insert(h_density.end(), p.density, p.density + p.n_layers);
         max_layers = std::max(max_layers, p.n_layers);
         max_bins = std::max(max_bins, p.n_bins);
         if (p.phase_kind != PDV_PHASE_HG) max_cells = std::max(max_cells, p.n_angles - 1);
     }
+    const int n_layer_jobs = (int)h_layer.size();
     // work items, largest set first
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
@@ -438,7 +487,8 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
     // ---- device buffers ----
     int r;
     if ((r = ensure(descs, sizeof(SetDesc) * n, "set descriptors"))) return r;
-    if ((r = ensure(tables, TableLayout::BYTES * (size_t)n, "set tables"))) return r;
+    if ((r = ensure(tables, TableLayout::BYTES * (size_t)n_unique, "set tables"))) return r;
+    if ((r = ensure(dup_src, sizeof(int) * n, "table sharing map"))) return r;
     if ((r = ensure(tallies, 8ull * tally_words_total, "tallies"))) return r;
     if ((r = ensure(items, sizeof(WorkItem) * std::max(1, n_items), "work items"))) return r;
     if ((r = ensure(queue, 256, "queue"))) return r;
@@ -455,18 +505,21 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
         return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
     };
     if ((r = hip_check(H2D(descs.ptr, h_desc.data(), sizeof(SetDesc) * n), "copy descriptors"))) return r;
-    if ((r = hip_check(H2D(layer_jobs.ptr, h_layer.data(), sizeof(LayerJob) * n), "copy layer jobs"))) return r;
+    if ((r = hip_check(H2D(layer_jobs.ptr, h_layer.data(), sizeof(LayerJob) * n_layer_jobs), "copy layer jobs")))
+        return r;
+    if ((r = hip_check(H2D(dup_src.ptr, h_src.data(), sizeof(int) * n), "copy sharing map"))) return r;
     if (!h_density.empty())
         if ((r = hip_check(H2D(density.ptr, h_density.data(), 8 * h_density.size()), "copy densities"))) return r;
     if (n_items)
         if ((r = hip_check(H2D(items.ptr, h_items.data(), sizeof(WorkItem) * n_items), "copy work items"))) return r;
 
     // ---- tables ----
-    launch_layer_tables(s, n, layer_jobs.ptr, (const double*)density.ptr, (uint8_t*)tables.ptr,
+    launch_layer_tables(s, n_layer_jobs, layer_jobs.ptr, (const double*)density.ptr, (uint8_t*)tables.ptr,
                         (SetDesc*)descs.ptr);
     // caller phase tables and Mie sets
     for (int i = 0; i < n; ++i) {
         const pdv_params& p = sets[i];
+        if (h_src[i] != i) continue;
         if (p.phase_kind == PDV_PHASE_TABLE) {
             uint8_t* dst = (uint8_t*)tables.ptr + h_desc[i].tab_offset + TableLayout::PHASE;
             if ((r = hip_check(H2D(dst, p.phase, 8ull * p.n_angles), "copy phase table"))) return r;
@@ -484,12 +537,12 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
     // Mie sets grouped by optics key (one cached basis at a time)
     std::vector<char> done(n, 0);
     for (int i = 0; i < n; ++i) {
-        if (sets[i].phase_kind != PDV_PHASE_MIE || done[i]) continue;
+        if (sets[i].phase_kind != PDV_PHASE_MIE || done[i] || h_src[i] != i) continue;
         if ((r = ensure_mie_basis(sets[i]))) return r;
         h_phase.clear();
         for (int j = i; j < n; ++j) {
             const pdv_params& p = sets[j];
-            if (p.phase_kind != PDV_PHASE_MIE || done[j]) continue;
+            if (p.phase_kind != PDV_PHASE_MIE || done[j] || h_src[j] != j) continue;
             MieKey k{p.m_re, p.m_im, p.wavelength, p.d_min, p.d_max, p.n_size_nodes, p.n_angles};
             if (!(k == mie_key)) continue;
             PhaseJob J{0, p.n_angles, p.d_median, p.sigma_ln, h_desc[j].tab_offset, j, 0};
@@ -502,6 +555,8 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
                          (const double*)mie_basis.ptr, (uint8_t*)tables.ptr, (SetDesc*)descs.ptr);
         if ((r = hip_check(hipStreamSynchronize(s), "mie phase kernels"))) return r;
     }
+
+    if (n_unique < n) launch_copy_desc_fields(s, (SetDesc*)descs.ptr, (const int*)dup_src.ptr, n);
 
     // ---- transport ----
     launch_zero_u64(s, (uint64_t*)tallies.ptr, tally_words_total);

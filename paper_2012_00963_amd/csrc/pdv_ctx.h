@@ -63,7 +63,7 @@ struct pdv_ctx {
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
 
     // batch buffers
-    DevBuf descs, tables, tallies, items, queue, layer_jobs, phase_jobs, density, lists, list_counts;
+    DevBuf descs, tables, tallies, items, queue, layer_jobs, phase_jobs, density, lists, list_counts, dup_src;
     // Mie basis cache
     DevBuf mie_info, mie_a, mie_b, mie_d, mie_basis, mie_gx, mie_gw;
     MieKey mie_key{};
@@ -77,6 +77,7 @@ struct pdv_ctx {
     // host staging
     std::vector<pdv::SetDesc> h_desc;
     std::vector<pdv::LayerJob> h_layer;
+    std::vector<int> h_src;              // first set with the same tables
     std::vector<pdv::PhaseJob> h_phase;
     std::vector<double> h_density;
     std::vector<pdv::WorkItem> h_items;

@@ -22,11 +22,12 @@ __device__ __forceinline__ Block4 philox10(uint32_t c0, uint32_t c1, uint32_t c2
     constexpr uint32_t BUMP_A = 0x9E3779B9u, BUMP_B = 0xBB67AE85u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t a_hi = __umulhi(MUL_A, c0), a_lo = MUL_A * c0;
-        const uint32_t b_hi = __umulhi(MUL_B, c2), b_lo = MUL_B * c2;
-        const uint32_t n0 = b_hi ^ c1 ^ k0;
-        const uint32_t n2 = a_hi ^ c3 ^ k1;
-        c0 = n0; c1 = b_lo; c2 = n2; c3 = a_lo;
+        // one 32x32->64 multiply per product (a single v_mad_u64_u32)
+        const uint64_t pa = (uint64_t)MUL_A * c0;
+        const uint64_t pb = (uint64_t)MUL_B * c2;
+        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        c0 = n0; c1 = (uint32_t)pb; c2 = n2; c3 = (uint32_t)pa;
         k0 += BUMP_A; k1 += BUMP_B;
     }
     return Block4{c0, c1, c2, c3};
@@ -36,7 +37,13 @@ __device__ __forceinline__ Block4 philox10(uint32_t c0, uint32_t c1, uint32_t c2
 // binary64, so both precisions see the same uniform.
 template <typename Real>
 __device__ __forceinline__ Real unit_open(uint32_t x) {
-    return (Real)(((x >> 9) << 1) | 1u) * (Real)5.9604644775390625e-08;
+    if constexpr (sizeof(Real) == 4) {
+        // 1 + m 2^-23 from the top 23 bits as the mantissa, minus (1 - 2^-24):
+        // exact (Sterbenz), and equal to (2m + 1) 2^-24
+        return __uint_as_float(0x3f800000u | (x >> 9)) - 0.99999994039535522461f;
+    } else {
+        return (Real)(((x >> 9) << 1) | 1u) * (Real)5.9604644775390625e-08;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -72,8 +79,13 @@ template <> struct M<double> {
 template <typename Real>
 __device__ __forceinline__ uint64_t to_fixed32(Real w) {
     // w * 2^32 rounded to nearest; w in [0, 1]
-    if constexpr (sizeof(Real) == 4) return __float2ull_rn(w * 4294967296.0f);
-    else return __double2ull_rn(w * 4294967296.0);
+    if constexpr (sizeof(Real) == 4) {
+        // below 1 the scaled value fits 32 bits (and is exact for w >= 2^-8)
+        const uint32_t lo = (uint32_t)__builtin_rintf(w * 4294967296.0f);
+        return w >= 1.0f ? 4294967296ull : (uint64_t)lo;
+    } else {
+        return __double2ull_rn(w * 4294967296.0);
+    }
 }
 
 // ---------------------------------------------------------------------------

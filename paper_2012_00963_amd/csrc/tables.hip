@@ -177,7 +177,7 @@ __global__ void gauss_legendre_kernel(int n, double* __restrict__ x_out, double*
 
 // --------------------------------------------------------------------------
 // Mie basis: sizes on Gauss-Legendre nodes in ln d over [d_min, d_max].
-// Layout: coef[n][i] (n = 1..nmax at index n-1), basis[j][i] (angle-major).
+// Layout: coef[n][i] (n = 1..nmax at index n-1), basis[i][j] (node-major).
 // --------------------------------------------------------------------------
 
 __global__ void mie_nodes_kernel(int n, const double* __restrict__ gl_x, const double* __restrict__ gl_w,
@@ -257,7 +257,7 @@ __global__ void mie_coef_kernel(int n_nodes, int nmax, int nmx_max, double m_re,
     info[i] = I;
 }
 
-// basis[j][i] = |S1|^2 + |S2|^2 at theta_j for size i; one block per angle.
+// basis[i][j] = |S1|^2 + |S2|^2 at theta_j for size i; one block per angle.
 __global__ void __launch_bounds__(256)
 mie_basis_kernel(int n_nodes, int nmax, int n_angles, const MieNodeInfo* __restrict__ info,
                  const Cplx* __restrict__ coef_a, const Cplx* __restrict__ coef_b, double* __restrict__ basis) {
@@ -278,7 +278,7 @@ mie_basis_kernel(int n_nodes, int nmax, int n_angles, const MieNodeInfo* __restr
             const double pi_next = ((2.0 * k + 1.0) * mu * pi_n - (double)(k + 1) * pi_prev) / (double)k;
             pi_prev = pi_n; pi_n = pi_next;
         }
-        basis[(uint64_t)j * n_nodes + i] = cabs2(S1) + cabs2(S2);
+        basis[(uint64_t)i * n_angles + j] = cabs2(S1) + cabs2(S2);
     }
 }
 
@@ -339,9 +339,9 @@ phase_cdf_kernel(const PhaseJob* __restrict__ jobs, int n_nodes, const MieNodeIn
         ext = block_sum(ext, s_red);
         gsum = block_sum(gsum, s_red);
         for (int j = tid; j < na; j += nt) {
-            const double* row = basis + (uint64_t)j * n_nodes;
+            // basis is node-major: consecutive threads read consecutive angles
             double acc = 0.0;
-            for (int i = 0; i < n_nodes; ++i) acc += s_w[i] * row[i];
+            for (int i = 0; i < n_nodes; ++i) acc += s_w[i] * basis[(uint64_t)i * na + j];
             phase[j] = acc;
             s_ph[j] = acc;
         }
@@ -432,6 +432,20 @@ phase_cdf_kernel(const PhaseJob* __restrict__ jobs, int n_nodes, const MieNodeIn
     }
 }
 
+// Sets that share another set's tables take its device-computed fields.
+__global__ void copy_desc_fields_kernel(SetDesc* d, const int* __restrict__ src, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int s = src[i];
+    if (s == i) return;
+    d[i].albedo = d[s].albedo;
+    d[i].thr_albedo = d[s].thr_albedo;
+    d[i].albedo_one = d[s].albedo_one;
+    d[i].g_mean = d[s].g_mean;
+    d[i].layer_steps = d[s].layer_steps;
+    d[i].cdf_steps = d[s].cdf_steps;
+}
+
 // Fill a uint64 range with zeros (graph-safe replacement for a memset).
 __global__ void zero_u64_kernel(uint64_t* p, uint64_t n) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
@@ -477,6 +491,11 @@ void launch_phase_cdf(hipStream_t s, int n_jobs, const void* jobs, int n_nodes, 
     if (n_jobs <= 0) return;
     hipLaunchKernelGGL(phase_cdf_kernel, dim3(n_jobs), dim3(1024), 0, s, (const PhaseJob*)jobs, n_nodes,
                        (const MieNodeInfo*)info, basis, tables, descs);
+}
+
+void launch_copy_desc_fields(hipStream_t s, SetDesc* descs, const int* src, int n) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(copy_desc_fields_kernel, dim3((n + 255) / 256), dim3(256), 0, s, descs, src, n);
 }
 
 void launch_zero_u64(hipStream_t s, uint64_t* p, uint64_t n) {

@@ -52,7 +52,7 @@ __host__ __device__ inline LdsLayout lds_layout(int real_bytes, int max_layers, 
     L.t_off = 0;
     L.lg_off = align16(L.t_off + (uint32_t)real_bytes * (uint32_t)(max_layers + 1));
     L.cdf_off = align16(L.lg_off + 2u * (LAYER_GUIDE + 1));
-    L.cg_off = align16(L.cdf_off + 4u * (uint32_t)(max_cells > 0 ? max_cells : 1));
+    L.cg_off = align16(L.cdf_off + 4u * (uint32_t)(max_cells + 1));
     L.hist_off = align16(L.cg_off + 2u * (CDF_GUIDE + 1));
     L.hist2_off = align16(L.hist_off + 8u * (uint32_t)(max_bins + N_SINK_SLOTS));
     L.bytes = align16(L.hist2_off + 8u * (uint32_t)max_bins);
@@ -153,11 +153,11 @@ __device__ __forceinline__ void table_angle(const SetConst<Real>& c, const uint3
         lo = le ? mid : lo;
         hi = le ? hi : mid - 1;
     }
+    // C[n_cells] holds 0, so the last cell's width 2^32 - C[j] comes from the
+    // unsigned wrap; a zero difference can only mean one cell holding all mass
     const uint32_t cj = C[lo];
-    const bool last = lo + 1 >= c.n_cells;
-    const uint32_t cn = last ? 0u : C[lo + 1];
-    // last cell's width is 2^32 - C[j] (unsigned wrap), or 2^32 if it holds everything
-    const Real width = (!last || cj != 0u) ? (Real)(uint32_t)(cn - cj) : (Real)4294967296.0;
+    const uint32_t dw = C[lo + 1] - cj;
+    const Real width = dw != 0u ? (Real)dw : (Real)4294967296.0;
     const Real f = M<Real>::div((Real)(x - cj) + (Real)0.5, width);
     if constexpr (sizeof(Real) == 4) {
         const Real rev = ((Real)lo + f) * c.rev_per_cell;
@@ -287,6 +287,7 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
             if (d.phase_kind == PH_TABLE) {
                 const uint32_t* gC = (const uint32_t*)(tb + TableLayout::CDF);
                 for (int i = tid; i < d.n_cells; i += nthr) sC[i] = gC[i];
+                if (tid == 0) sC[d.n_cells] = 0u;
                 const uint16_t* gCG = (const uint16_t*)(tb + TableLayout::CGUIDE);
                 for (int i = tid; i <= CDF_GUIDE; i += nthr) sCG[i] = gCG[i];
             }
