@@ -186,6 +186,9 @@ typedef struct pdv_launch_opts {
     uint64_t packets_per_item;   /* work-item size; 0 = default */
     int32_t persistent;          /* 1 = persistent work queue, 0 = one block per item, -1 = default */
     int32_t use_graph;           /* 1 = capture and replay the batch as a hipGraph, 0 = direct launches */
+    int32_t guide_bits;          /* search-guide cells 2^guide_bits staged in LDS, 11..14; 0 = the finest
+                                    that keeps the launch's blocks resident (a table layout: results are
+                                    bitwise the same for every value) */
 } pdv_launch_opts;
 
 /*
@@ -398,10 +401,11 @@ int pdv_create_host(struct pdv_ctx** out);
 /*
  * Timing of the last transport launch on ctx: kernel time between HIP events
  * recorded on the context stream around the launch (ms), grid and block
- * size, number of work items.  Any pointer may be NULL.
+ * size, number of work items, staged guide bits and LDS bytes per block.
+ * Any pointer may be NULL.
  */
 int pdv_last_launch(const struct pdv_ctx* ctx, float* kernel_ms, int32_t* grid, int32_t* block,
-                    int32_t* n_items);
+                    int32_t* n_items, int32_t* guide_bits, int32_t* lds_bytes);
 
 #ifdef __cplusplus
 }

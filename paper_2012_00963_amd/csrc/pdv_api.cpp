@@ -21,8 +21,7 @@ using namespace pdv;
 
 // ---- kernels (defined in the .hip translation units) ----
 namespace pdv {
-void launch_layer_tables(hipStream_t s, int n_jobs, const void* jobs, const double* density, uint8_t* tables,
-                         SetDesc* descs);
+void launch_layer_tables(hipStream_t s, int n_jobs, const void* jobs, const double* density, uint8_t* tables);
 void launch_gauss_legendre(hipStream_t s, int n, double* x, double* w);
 void launch_mie_nodes(hipStream_t s, int n, const double* gx, const double* gw, double ln_dmin, double ln_dmax,
                       double wavelength, void* info);
@@ -34,17 +33,18 @@ void launch_phase_cdf(hipStream_t s, int n_jobs, const void* jobs, int n_nodes, 
                       const double* basis, uint8_t* tables, SetDesc* descs);
 void launch_zero_u64(hipStream_t s, uint64_t* p, uint64_t n);
 void launch_copy_desc_fields(hipStream_t s, SetDesc* descs, const int* src, int n);
-int transport_lds_bytes(int real_bytes, int max_layers, int max_cells, int max_bins);
+hipError_t plan_transport(TransportShape& sh, int precision, bool list, int want_bits, int lds_per_block,
+                          int lds_per_cu);
 hipError_t launch_synth(hipStream_t s, int n_frames, const void* frames, const ListEntry* entries, double r_scale,
                         int n_chunks, int max_samples, float* partial, float* signal);
 hipError_t launch_stft(hipStream_t s, const float* signal, int n_windows, int nfft, int hop, void* tw, void* tr,
                        float* win, float* map, bool build_tables);
 int synth_chunk();
 size_t synth_frame_bytes();
-hipError_t launch_transport(hipStream_t s, int precision, bool list, int grid, int block, int lds_bytes,
+hipError_t launch_transport(hipStream_t s, int precision, bool list, const TransportShape& sh,
                             const SetDesc* descs, const uint8_t* tables, uint64_t* tallies, const WorkItem* items,
-                            int n_items, uint32_t* queue, int persistent, int max_layers, int max_cells,
-                            int max_bins, ListEntry* lists, uint64_t* list_counts);
+                            int n_items, uint32_t* queue, int persistent, ListEntry* lists,
+                            uint64_t* list_counts);
 }  // namespace pdv
 
 // ---------------------------------------------------------------------------
@@ -200,6 +200,9 @@ extern "C" int pdv_create(pdv_ctx** out, int device, uint64_t mem_budget, void* 
     hipDeviceProp_t prop;
     if (int r = c->hip_check(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties")) return r;
     c->n_cu = prop.multiProcessorCount;
+    c->lds_per_block = (int)prop.sharedMemPerBlock;
+    c->lds_per_cu = (int)prop.maxSharedMemoryPerMultiProcessor;
+    if (c->lds_per_cu < c->lds_per_block) c->lds_per_cu = c->lds_per_block;
     c->arch = prop.gcnArchName;
     size_t free_b = 0, total_b = 0;
     if (int r = c->hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo")) return r;
@@ -355,8 +358,6 @@ void pdv::fill_desc(SetDesc& d, const pdv_params& p) {
     d.rev_per_cell = p.phase_kind == PDV_PHASE_HG ? 0.0 : 0.5 / (double)(p.n_angles - 1);
     d.dtheta = p.phase_kind == PDV_PHASE_HG ? 0.0 : 3.14159265358979323846 / (double)(p.n_angles - 1);
     d.uniform_density = p.density_kind == PDV_DENSITY_UNIFORM;
-    d.layer_steps = 13;   // replaced by the table kernels with the exact bound
-    d.cdf_steps = 13;
     d.seed = p.seed;
     d.stream = p.stream;
     auto thr = [](double a) {
@@ -384,6 +385,7 @@ void pdv_ctx::default_opts(pdv_launch_opts& o, uint64_t total_packets, int n_set
     if (o.block_size <= 0) o.block_size = tuned.block_size > 0 ? tuned.block_size : 512;
     if (o.blocks_per_cu <= 0) o.blocks_per_cu = tuned.blocks_per_cu > 0 ? tuned.blocks_per_cu : 4;
     if (o.persistent < 0) o.persistent = tuned.persistent >= 0 ? tuned.persistent : 1;
+    if (o.guide_bits == 0) o.guide_bits = tuned.guide_bits;
     if (o.packets_per_item == 0) {
         uint64_t grid = (uint64_t)n_cu * (uint64_t)o.blocks_per_cu;
         uint64_t ppi = total_packets / (grid * 4 + 1);
@@ -407,13 +409,15 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
     }
     if (int r = hip_check(hipSetDevice(device), "hipSetDevice")) return r;
 
-    pdv_launch_opts o{0, 0, 0, -1, 0};
+    pdv_launch_opts o{0, 0, 0, -1, 0, 0};
     if (opts_in) o = *opts_in;
     uint64_t total = 0;
     for (int i = 0; i < n; ++i) total += sets[i].n_packets;
     default_opts(o, total, n);
     if (o.block_size != 256 && o.block_size != 512 && o.block_size != 1024)
         return fail(PDV_EINVAL, "block_size must be 256, 512 or 1024");
+    if (o.guide_bits != 0 && (o.guide_bits < MIN_GUIDE_BITS || o.guide_bits > GUIDE_BITS))
+        return fail(PDV_EINVAL, "guide_bits must be 0 or %d..%d", MIN_GUIDE_BITS, GUIDE_BITS);
 
     // ---- host-side packing ----
     // Sets whose tables would be identical (same cloud and optics, e.g. the
@@ -447,8 +451,6 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
             L.density_kind = p.density_kind;
             L.tab_offset = d.tab_offset;
             L.density_offset = h_density.size();
-            L.set = i;
-            L.pad = 0;
             if (p.density_kind == PDV_DENSITY_TABLE)
                 h_density.insert(h_density.end(), p.density, p.density + p.n_layers);
             h_layer.push_back(L);
@@ -514,8 +516,7 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
         if ((r = hip_check(H2D(items.ptr, h_items.data(), sizeof(WorkItem) * n_items), "copy work items"))) return r;
 
     // ---- tables ----
-    launch_layer_tables(s, n_layer_jobs, layer_jobs.ptr, (const double*)density.ptr, (uint8_t*)tables.ptr,
-                        (SetDesc*)descs.ptr);
+    launch_layer_tables(s, n_layer_jobs, layer_jobs.ptr, (const double*)density.ptr, (uint8_t*)tables.ptr);
     // caller phase tables and Mie sets
     for (int i = 0; i < n; ++i) {
         const pdv_params& p = sets[i];
@@ -562,19 +563,30 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
     launch_zero_u64(s, (uint64_t*)tallies.ptr, tally_words_total);
     launch_zero_u64(s, (uint64_t*)queue.ptr, 1);
     if (list_capacity) launch_zero_u64(s, (uint64_t*)list_counts.ptr, (uint64_t)n);
-    const int lds = transport_lds_bytes(precision == PDV_FP64 ? 8 : 4, max_layers, max_cells, max_bins);
-    if (lds > 64 * 1024) return fail(PDV_EINVAL, "tables need %d bytes of LDS per block (limit 65536)", lds);
-    int grid = o.persistent ? std::min(n_items, n_cu * o.blocks_per_cu) : n_items;
-    if (grid < 1) grid = 1;
-    last_grid = grid;
-    last_block = o.block_size;
+    TransportShape sh;
+    sh.block = o.block_size;
+    sh.grid = o.persistent ? std::min(n_items, n_cu * o.blocks_per_cu) : n_items;
+    if (sh.grid < 1) sh.grid = 1;
+    sh.max_layers = max_layers;
+    sh.max_cells = max_cells;
+    sh.max_bins = max_bins;
+    {
+        hipError_t e = plan_transport(sh, precision, list_capacity > 0, o.guide_bits, lds_per_block, lds_per_cu);
+        if (e == hipErrorInvalidValue)
+            return fail(PDV_EINVAL, "tables need %d bytes of LDS per block (device limit %d)", sh.lds_bytes,
+                        lds_per_block);
+        if ((r = hip_check(e, "transport launch plan"))) return r;
+    }
+    last_grid = sh.grid;
+    last_block = sh.block;
     last_items = n_items;
+    last_guide_bits = sh.guide_bits;
+    last_lds = sh.lds_bytes;
     if ((r = hip_check(hipEventRecord(ev_a, s), "event"))) return r;
     if (n_items > 0) {
-        hipError_t e = launch_transport(s, precision, list_capacity > 0, grid, o.block_size, lds,
-                                        (const SetDesc*)descs.ptr, (const uint8_t*)tables.ptr,
-                                        (uint64_t*)tallies.ptr, (const WorkItem*)items.ptr, n_items,
-                                        (uint32_t*)queue.ptr, o.persistent, max_layers, max_cells, max_bins,
+        hipError_t e = launch_transport(s, precision, list_capacity > 0, sh, (const SetDesc*)descs.ptr,
+                                        (const uint8_t*)tables.ptr, (uint64_t*)tallies.ptr,
+                                        (const WorkItem*)items.ptr, n_items, (uint32_t*)queue.ptr, o.persistent,
                                         (ListEntry*)lists.ptr, (uint64_t*)list_counts.ptr);
         if ((r = hip_check(e, "transport launch"))) return r;
     }
@@ -630,12 +642,14 @@ extern "C" int pdv_spectrum_batch(pdv_ctx* ctx, const pdv_params* sets, int32_t 
 // Timing of the last transport launch (HIP events around the kernel on the
 // context stream), its grid and block, for benchmarks.
 extern "C" int pdv_last_launch(const pdv_ctx* ctx, float* kernel_ms, int32_t* grid, int32_t* block,
-                               int32_t* n_items) {
+                               int32_t* n_items, int32_t* guide_bits, int32_t* lds_bytes) {
     if (!ctx) return PDV_EINVAL;
     if (kernel_ms) *kernel_ms = ctx->last_kernel_ms;
     if (grid) *grid = ctx->last_grid;
     if (block) *block = ctx->last_block;
     if (n_items) *n_items = ctx->last_items;
+    if (guide_bits) *guide_bits = ctx->last_guide_bits;
+    if (lds_bytes) *lds_bytes = ctx->last_lds;
     return PDV_OK;
 }
 
@@ -898,10 +912,13 @@ extern "C" int pdv_set_launch_defaults(pdv_ctx* ctx, const pdv_launch_opts* o) {
         return ctx->fail(PDV_EINVAL, "block_size must be 256, 512 or 1024");
     if (o->blocks_per_cu < 0 || o->blocks_per_cu > 64) return ctx->fail(PDV_EINVAL, "blocks_per_cu out of range");
     if (o->packets_per_item > (1ull << 31)) return ctx->fail(PDV_EINVAL, "packets_per_item out of range");
+    if (o->guide_bits != 0 && (o->guide_bits < MIN_GUIDE_BITS || o->guide_bits > GUIDE_BITS))
+        return ctx->fail(PDV_EINVAL, "guide_bits must be 0 or %d..%d", MIN_GUIDE_BITS, GUIDE_BITS);
     ctx->tuned.block_size = o->block_size;
     ctx->tuned.blocks_per_cu = o->blocks_per_cu;
     ctx->tuned.packets_per_item = o->packets_per_item;
     ctx->tuned.persistent = o->persistent;
+    ctx->tuned.guide_bits = o->guide_bits;
     return PDV_OK;
 }
 
@@ -925,8 +942,13 @@ extern "C" int pdv_autotune(pdv_ctx* ctx, const pdv_params* sets, int32_t n, int
         *ms = ctx->last_kernel_ms;
         return r;
     };
-    // reference: default shape
-    pdv_launch_opts def{0, 0, 0, -1, 0};
+    // reference: the current default shape, resolved to explicit values
+    pdv_launch_opts def{0, 0, 0, -1, 0, 0};
+    {
+        uint64_t total = 0;
+        for (int i = 0; i < n; ++i) total += sets[i].n_packets;
+        ctx->default_opts(def, total, n);
+    }
     float ms = 0;
     if (int r = run(def, &ms)) return r;
     std::vector<std::vector<uint64_t>> refW = W, refW2 = W2;
@@ -949,15 +971,18 @@ extern "C" int pdv_autotune(pdv_ctx* ctx, const pdv_params* sets, int32_t n, int
         *med = t[t.size() / 2];
         return PDV_OK;
     };
+    // launch shapes with the default guide resolution, then every guide
+    // resolution for the best shape (the table layout stage)
     std::vector<pdv_launch_opts> cands;
     for (int bs : {256, 512, 1024}) {
         for (uint64_t ppi : {1ull << 12, 1ull << 14, 1ull << 16, 1ull << 18}) {
-            for (int bpc : {1, 2, 4, 8}) cands.push_back(pdv_launch_opts{bs, bpc, ppi, 1, 0});
-            cands.push_back(pdv_launch_opts{bs, 1, ppi, 0, 0});
+            for (int bpc : {1, 2, 4, 8}) cands.push_back(pdv_launch_opts{bs, bpc, ppi, 1, 0, 0});
+            cands.push_back(pdv_launch_opts{bs, 1, ppi, 0, 0, 0});
         }
     }
     double best_ms = 1e300, worst_ms = 0, def_ms = 0;
     bool invariant = true;
+    int timed = 1;
     pdv_launch_opts best_o = def;
     {
         bool same = true;
@@ -966,31 +991,45 @@ extern "C" int pdv_autotune(pdv_ctx* ctx, const pdv_params* sets, int32_t n, int
         best_ms = def_ms;
         worst_ms = def_ms;
     }
-    for (const pdv_launch_opts& o : cands) {
+    auto consider = [&](const pdv_launch_opts& o, bool may_not_fit) -> int {
         double med = 0;
         bool same = true;
-        if (int r = median_ms(o, &med, &same)) return r;
+        if (int r = median_ms(o, &med, &same)) {
+            if (may_not_fit && r == PDV_EINVAL) return PDV_OK;   // staging exceeds the LDS limit
+            return r;
+        }
+        ++timed;
         invariant = invariant && same;
         worst_ms = std::max(worst_ms, med);
         if (med < best_ms) {
             best_ms = med;
             best_o = o;
         }
+        return PDV_OK;
+    };
+    for (const pdv_launch_opts& o : cands)
+        if (int r = consider(o, false)) return r;
+    {
+        pdv_launch_opts base = best_o;
+        for (int gb = MIN_GUIDE_BITS; gb <= GUIDE_BITS; ++gb) {
+            pdv_launch_opts o = base;
+            o.guide_bits = gb;
+            if (int r = consider(o, true)) return r;
+        }
     }
     if (report) {
-        report->candidates = (int32_t)cands.size() + 1;
+        report->candidates = timed;
         report->invariant = invariant ? 1 : 0;
         report->best_ms = best_ms;
         report->worst_ms = worst_ms;
         report->default_ms = def_ms;
     }
     if (!invariant) return ctx->fail(PDV_EDEVICE, "launch shapes gave different tallies");
-    if (best_o.block_size != 0) {
-        ctx->tuned.block_size = best_o.block_size;
-        ctx->tuned.blocks_per_cu = best_o.blocks_per_cu;
-        ctx->tuned.packets_per_item = best_o.packets_per_item;
-        ctx->tuned.persistent = best_o.persistent;
-    }
+    ctx->tuned.block_size = best_o.block_size;
+    ctx->tuned.blocks_per_cu = best_o.blocks_per_cu;
+    ctx->tuned.packets_per_item = best_o.packets_per_item;
+    ctx->tuned.persistent = best_o.persistent;
+    ctx->tuned.guide_bits = best_o.guide_bits;
     if (best) *best = best_o;
     return PDV_OK;
 }

@@ -41,6 +41,7 @@ struct TunedLaunch {
     int32_t blocks_per_cu = 0;
     uint64_t packets_per_item = 0;
     int32_t persistent = -1;
+    int32_t guide_bits = 0;
 };
 
 struct ServeEngine;   // serving loop (serve.cpp)
@@ -53,6 +54,7 @@ using ListEntry_ = pdv::ListEntry;
 struct pdv_ctx {
     int device = 0;
     int n_cu = 256;
+    int lds_per_block = 65536, lds_per_cu = 65536;   // device LDS limits (bytes)
     std::string arch;
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -85,7 +87,7 @@ struct pdv_ctx {
 
     // last launch (benchmarks)
     float last_kernel_ms = 0.f;
-    int32_t last_grid = 0, last_block = 0, last_items = 0;
+    int32_t last_grid = 0, last_block = 0, last_items = 0, last_guide_bits = 0, last_lds = 0;
     TunedLaunch tuned;
 
     // serving

@@ -16,9 +16,12 @@ namespace pdv {
 // Table geometry limits (LDS staging is sized from them per launch).
 constexpr int MAX_LAYERS = 4096;
 constexpr int MAX_ANGLES = 4096;
-constexpr int LAYER_GUIDE = 2048;         // uniform-depth guide entries (+1)
-constexpr int CDF_GUIDE_BITS = 11;        // 2048 guide entries over the 2^32 range
-constexpr int CDF_GUIDE = 1 << CDF_GUIDE_BITS;
+// Search guides are stored at 2^GUIDE_BITS cells (+1 entry); a launch stages
+// every 2^(GUIDE_BITS - b)-th entry in LDS, b in [MIN_GUIDE_BITS, GUIDE_BITS].
+constexpr int GUIDE_BITS = 14;
+constexpr int MIN_GUIDE_BITS = 11;
+constexpr int LAYER_GUIDE = 1 << GUIDE_BITS;   // uniform-depth cells
+constexpr int CDF_GUIDE = 1 << GUIDE_BITS;     // cells of the 2^32 CDF range
 constexpr int MAX_BINS = 4096;
 
 enum PhaseKind : int32_t { PH_HG = 0, PH_TABLE = 1 };
@@ -64,7 +67,7 @@ struct alignas(16) SetDesc {
     double zeta_per_tau;        // uniform density: (v_top - v_bottom) / tau_total
     // precomputed Henyey-Greenstein constants: 1+g^2, 1-g^2, 1-g, 2g, 1/(2g)
     double hg_a, hg_b, hg_c0, hg_c1, hg_inv2g;
-    double lg_scale;            // LAYER_GUIDE / tau_total
+    double lg_scale;            // LAYER_GUIDE / tau_total (finest guide cells per unit depth)
     double rev_per_cell;        // 0.5 / n_cells (table angle in revolutions)
     double dtheta;              // pi / n_cells
     uint64_t seed;
@@ -86,8 +89,6 @@ struct alignas(16) SetDesc {
     int32_t albedo_one;         // (device for Mie) 1 if albedo >= 1
     int32_t surface_one;
     int32_t uniform_density;    // 1: zeta is linear in depth, no table search
-    int32_t layer_steps;        // (device) bisection steps inside a layer-guide window
-    int32_t cdf_steps;          // (device) bisection steps inside a CDF-guide window
 };
 
 struct WorkItem {
@@ -106,14 +107,20 @@ struct alignas(16) ListEntry {
 
 enum SetFlags : uint32_t { SF_CLASS = 1u, SF_LIST = 2u };
 
+// Launch shape of the transport kernel (host side).
+struct TransportShape {
+    int grid = 1, block = 512;
+    int max_layers = 0, max_cells = 0, max_bins = 0;   // LDS staging sizes of the batch
+    int guide_bits = GUIDE_BITS;                        // staged guide resolution
+    int lds_bytes = 0;
+};
+
 // Table-building jobs (host-packed, one per set).
 struct LayerJob {
     double v_bottom, v_top, v0, tau_total;
     int32_t n_layers, density_kind;
     uint64_t tab_offset;
     uint64_t density_offset;   // doubles into the density staging buffer (TABLE kind)
-    int32_t set;               // descriptor to finish (layer_steps)
-    int32_t pad;
 };
 
 struct PhaseJob {

@@ -39,16 +39,15 @@ int pdv_spectrogram_internal(pdv_ctx* ctx, const pdv_params* p, const pdv_sg_par
 namespace pdv {
 int validate_params(pdv_ctx* ctx, const pdv_params* p);
 void fill_desc(SetDesc& d, const pdv_params& p);
-void launch_layer_tables(hipStream_t s, int n_jobs, const void* jobs, const double* density, uint8_t* tables,
-                         SetDesc* descs);
+void launch_layer_tables(hipStream_t s, int n_jobs, const void* jobs, const double* density, uint8_t* tables);
 void launch_phase_cdf(hipStream_t s, int n_jobs, const void* jobs, int n_nodes, const void* info,
                       const double* basis, uint8_t* tables, SetDesc* descs);
 void launch_zero_u64(hipStream_t s, uint64_t* p, uint64_t n);
-int transport_lds_bytes(int real_bytes, int max_layers, int max_cells, int max_bins);
-hipError_t launch_transport_dev(hipStream_t s, int precision, int grid, int block, int lds_bytes,
-                                const SetDesc* descs, const uint8_t* tables, uint64_t* tallies,
-                                const WorkItem* items, const int* n_items_dev, uint32_t* queue, int max_layers,
-                                int max_cells, int max_bins);
+hipError_t plan_transport(TransportShape& sh, int precision, bool list, int want_bits, int lds_per_block,
+                          int lds_per_cu);
+hipError_t launch_transport_dev(hipStream_t s, int precision, const TransportShape& sh, const SetDesc* descs,
+                                const uint8_t* tables, uint64_t* tallies, const WorkItem* items,
+                                const int* n_items_dev, uint32_t* queue);
 }  // namespace pdv
 
 namespace {
@@ -127,7 +126,7 @@ struct HipExecutor : Executor {
     WorkItem* h_items = nullptr;     // pinned staging for graph replays
     int* h_nitems = nullptr;
     int max_items = 0;
-    int grid = 0, block = 512, lds = 0;
+    TransportShape shape;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     std::string err;
@@ -166,11 +165,17 @@ struct HipExecutor : Executor {
         if ((r = hipfail(hipHostMalloc((void**)&h_items, sizeof(WorkItem) * max_items, hipHostMallocDefault),
                          "pinned items"))) return r;
         if ((r = hipfail(hipHostMalloc((void**)&h_nitems, 256, hipHostMallocDefault), "pinned count"))) return r;
-        block = 512;
-        grid = ctx->n_cu * 4;
-        lds = transport_lds_bytes(E->opts.precision == PDV_FP64 ? 8 : 4, E->opts.max_layers, E->opts.max_angles - 1,
-                                  E->opts.max_bins);
-        return PDV_OK;
+        shape.block = 512;
+        shape.grid = ctx->n_cu * 4;
+        shape.max_layers = E->opts.max_layers;
+        shape.max_cells = E->opts.max_angles - 1;
+        shape.max_bins = E->opts.max_bins;
+        hipError_t e = plan_transport(shape, E->opts.precision, false, 0, ctx->lds_per_block, ctx->lds_per_cu);
+        if (e == hipErrorInvalidValue) {
+            err = "serving limits need more LDS per block than the device has";
+            return PDV_EINVAL;
+        }
+        return hipfail(e, "transport launch plan");
     }
     int prepare(const std::vector<Req*>& adm) override {
         if (adm.empty()) return PDV_OK;
@@ -185,7 +190,7 @@ struct HipExecutor : Executor {
             d[i].tally_offset = (uint64_t)q->slot * slot_tally_words(E->opts.max_bins);
             LayerJob& L = lj[i];
             L = LayerJob{q->p.v_bottom, q->p.v_top, q->p.v0, q->p.tau_total, q->p.n_layers, q->p.density_kind,
-                         d[i].tab_offset, dens.size(), q->slot, 0};
+                         d[i].tab_offset, dens.size()};
             if (q->p.density_kind == PDV_DENSITY_TABLE) dens.insert(dens.end(), q->density.begin(), q->density.end());
         }
         int r;
@@ -201,8 +206,7 @@ struct HipExecutor : Executor {
             if ((r = hipfail(hipMemcpyAsync(density.ptr, dens.data(), 8 * dens.size(), hipMemcpyHostToDevice, s),
                              "copy densities")))
                 return r;
-        launch_layer_tables(s, (int)lj.size(), layer_jobs.ptr, (const double*)density.ptr, (uint8_t*)tables.ptr,
-                            (SetDesc*)descs.ptr);
+        launch_layer_tables(s, (int)lj.size(), layer_jobs.ptr, (const double*)density.ptr, (uint8_t*)tables.ptr);
         // phase tables: caller tables, then Mie sets grouped by optics key
         std::vector<PhaseJob> pj;
         for (const Req* q : adm) {
@@ -257,10 +261,9 @@ struct HipExecutor : Executor {
         if ((e = hipMemcpyAsync(nitems.ptr, h_nitems, sizeof(int), hipMemcpyHostToDevice, s)))
             return hipfail(e, "copy item count");
         launch_zero_u64(s, (uint64_t*)queue.ptr, 1);
-        e = launch_transport_dev(s, E->opts.precision, grid, block, lds, (const SetDesc*)descs.ptr,
-                                 (const uint8_t*)tables.ptr, (uint64_t*)tallies.ptr, (const WorkItem*)items.ptr,
-                                 (const int*)nitems.ptr, (uint32_t*)queue.ptr, E->opts.max_layers,
-                                 E->opts.max_angles - 1, E->opts.max_bins);
+        e = launch_transport_dev(s, E->opts.precision, shape, (const SetDesc*)descs.ptr, (const uint8_t*)tables.ptr,
+                                 (uint64_t*)tallies.ptr, (const WorkItem*)items.ptr, (const int*)nitems.ptr,
+                                 (uint32_t*)queue.ptr);
         return hipfail(e, "transport launch");
     }
     int run(const std::vector<WorkItem>& its) override {

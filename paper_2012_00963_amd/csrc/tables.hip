@@ -54,8 +54,7 @@ __device__ __forceinline__ double cabs2(Cplx a) { return a.re * a.re + a.im * a.
 // --------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(1024)
-layer_table_kernel(const LayerJob* __restrict__ jobs, const double* __restrict__ density, uint8_t* tables,
-                   SetDesc* descs) {
+layer_table_kernel(const LayerJob* __restrict__ jobs, const double* __restrict__ density, uint8_t* tables) {
     const LayerJob J = jobs[blockIdx.x];
     const int n = J.n_layers;
     uint8_t* tb = tables + J.tab_offset;
@@ -107,9 +106,6 @@ layer_table_kernel(const LayerJob* __restrict__ jobs, const double* __restrict__
     if (tid == 0) { T64[0] = 0.0; T32[0] = 0.0f; }
     __syncthreads();
     // guide over uniform depth cells
-    __shared__ uint16_t s_lg[LAYER_GUIDE + 1];
-    __shared__ int s_maxwin;
-    if (tid == 0) s_maxwin = 0;
     for (int i = tid; i <= LAYER_GUIDE; i += nt) {
         const double t = J.tau_total * (double)i / (double)LAYER_GUIDE;
         int lo = 0, hi = n - 1;
@@ -118,23 +114,6 @@ layer_table_kernel(const LayerJob* __restrict__ jobs, const double* __restrict__
             if (s_mass[mid - 1] <= t) lo = mid; else hi = mid - 1;
         }
         lg[i] = (uint16_t)lo;
-        s_lg[i] = (uint16_t)lo;
-    }
-    __syncthreads();
-    // widest search window of the transport kernel (+-1 guide cell)
-    int win = 0;
-    for (int g = tid; g < LAYER_GUIDE; g += nt) {
-        const int lo = s_lg[g > 0 ? g - 1 : 0];
-        int hi = s_lg[g + 2 <= LAYER_GUIDE ? g + 2 : LAYER_GUIDE];
-        hi = hi > n - 1 ? n - 1 : hi;
-        win = max(win, hi - lo);
-    }
-    atomicMax(&s_maxwin, win);
-    __syncthreads();
-    if (tid == 0) {
-        int steps = 0;
-        while ((1 << steps) < s_maxwin + 1) ++steps;
-        descs[J.set].layer_steps = steps;
     }
 }
 
@@ -405,31 +384,17 @@ phase_cdf_kernel(const PhaseJob* __restrict__ jobs, int n_nodes, const MieNodeIn
         gpart += (cn - cj) / 4294967296.0 * (sin(th1) - sin(th0)) / dth;
     }
     gpart = block_sum(gpart, s_red);
-    // guide: last cell with C[j] <= i 2^(32-bits)
-    __shared__ uint16_t s_cg[CDF_GUIDE + 1];
-    __shared__ int s_maxwin;
-    if (tid == 0) s_maxwin = 0;
+    // guide: last cell with C[j] <= i 2^(32 - GUIDE_BITS)
     for (int i = tid; i <= CDF_GUIDE; i += nt) {
-        const uint64_t key = (uint64_t)i << (32 - CDF_GUIDE_BITS);
+        const uint64_t key = (uint64_t)i << (32 - GUIDE_BITS);
         int lo = 0, hi = nc - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if ((uint64_t)s_C[mid] <= key) lo = mid; else hi = mid - 1;
         }
         cg[i] = (uint16_t)lo;
-        s_cg[i] = (uint16_t)lo;
     }
-    __syncthreads();
-    int win = 0;
-    for (int i = tid; i < CDF_GUIDE; i += nt) win = max(win, (int)s_cg[i + 1] - (int)s_cg[i]);
-    atomicMax(&s_maxwin, win);
-    __syncthreads();
-    if (tid == 0) {
-        d.g_mean = gpart;
-        int steps = 0;
-        while ((1 << steps) < s_maxwin + 1) ++steps;
-        d.cdf_steps = steps;
-    }
+    if (tid == 0) d.g_mean = gpart;
 }
 
 // Sets that share another set's tables take its device-computed fields.
@@ -442,8 +407,6 @@ __global__ void copy_desc_fields_kernel(SetDesc* d, const int* __restrict__ src,
     d[i].thr_albedo = d[s].thr_albedo;
     d[i].albedo_one = d[s].albedo_one;
     d[i].g_mean = d[s].g_mean;
-    d[i].layer_steps = d[s].layer_steps;
-    d[i].cdf_steps = d[s].cdf_steps;
 }
 
 // Fill a uint64 range with zeros (graph-safe replacement for a memset).
@@ -457,11 +420,9 @@ __global__ void zero_u64_kernel(uint64_t* p, uint64_t n) {
 // ---- host launchers ----
 namespace pdv {
 
-void launch_layer_tables(hipStream_t s, int n_jobs, const void* jobs, const double* density, uint8_t* tables,
-                         SetDesc* descs) {
+void launch_layer_tables(hipStream_t s, int n_jobs, const void* jobs, const double* density, uint8_t* tables) {
     if (n_jobs <= 0) return;
-    hipLaunchKernelGGL(layer_table_kernel, dim3(n_jobs), dim3(1024), 0, s, (const LayerJob*)jobs, density, tables,
-                       descs);
+    hipLaunchKernelGGL(layer_table_kernel, dim3(n_jobs), dim3(1024), 0, s, (const LayerJob*)jobs, density, tables);
 }
 
 void launch_gauss_legendre(hipStream_t s, int n, double* x, double* w) {

@@ -27,12 +27,16 @@
 // one slot per terminal sink, so every finished packet costs one LDS atomic
 // (two for a binned detection).  Waves refill finished lanes with the next
 // packet ids of the current work item (one LDS atomic per wave per refill
-// round).  Table searches are bisections with a per-set step count, so
-// lanes never diverge on loop trip counts.  Event counters and absorbed
+// round).  Table searches are bisections inside the window of a guide of
+// up to 2^14 cells (the launch picks the finest that fits its LDS budget);
+// the guides are fine enough that most windows hold one entry, and a
+// wave leaves the search as soon as all of its lanes have converged.  Event counters and absorbed
 // weight live in registers, are reduced across the wave and reach global
 // memory with one atomic per wave; the LDS histogram is flushed with global
 // 64-bit atomics when the block changes set or retires.  Tallies are
 // integers (weight x 2^32), so results do not depend on the launch shape.
+#include <algorithm>
+
 #include "pdv_device.h"
 #include "pdv_internal.h"
 
@@ -42,18 +46,25 @@ struct LdsLayout {
     uint32_t t_off, lg_off, cdf_off, cg_off, hist_off, hist2_off, bytes;
 };
 
+// A guide cell's margin (in finest cells) around the scaled depth: covers
+// the FP32 rounding of t x scale and of the FP32 layer depths against the
+// FP64 depths the guide was built from (both below 2^-8 of a cell).
+constexpr float GUIDE_MARGIN = 1.0f / 32.0f;
+
 __host__ __device__ inline uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
 
 // terminal-sink slots follow the velocity bins in the LDS histogram
 constexpr int N_SINK_SLOTS = 8;
 
-__host__ __device__ inline LdsLayout lds_layout(int real_bytes, int max_layers, int max_cells, int max_bins) {
+__host__ __device__ inline LdsLayout lds_layout(int real_bytes, int max_layers, int max_cells, int max_bins,
+                                                int guide_bits) {
+    const uint32_t guide_entries = (1u << guide_bits) + 1u;
     LdsLayout L;
     L.t_off = 0;
     L.lg_off = align16(L.t_off + (uint32_t)real_bytes * (uint32_t)(max_layers + 1));
-    L.cdf_off = align16(L.lg_off + 2u * (LAYER_GUIDE + 1));
+    L.cdf_off = align16(L.lg_off + 2u * guide_entries);
     L.cg_off = align16(L.cdf_off + 4u * (uint32_t)(max_cells + 1));
-    L.hist_off = align16(L.cg_off + 2u * (CDF_GUIDE + 1));
+    L.hist_off = align16(L.cg_off + 2u * guide_entries);
     L.hist2_off = align16(L.hist_off + 8u * (uint32_t)(max_bins + N_SINK_SLOTS));
     L.bytes = align16(L.hist2_off + 8u * (uint32_t)max_bins);
     return L;
@@ -67,7 +78,7 @@ struct SetConst {            // wave-uniform per-set constants (kept in SGPRs)
     double v_lo, dv, inv_dv;
     uint32_t k0, k1, stream, thr_albedo, thr_surface, flags;
     int n_layers, n_cells, n_bins, max_orders, phase_kind, surface_law, weighting;
-    int albedo_one, surface_one, hg_zero, uniform_density, layer_steps, cdf_steps;
+    int albedo_one, surface_one, hg_zero, uniform_density;
 };
 
 template <typename Real>
@@ -109,25 +120,28 @@ __device__ __forceinline__ SetConst<Real> load_const(const SetDesc& d) {
     c.albedo_one = d.albedo_one;
     c.surface_one = d.surface_one;
     c.uniform_density = d.uniform_density;
-    c.layer_steps = d.layer_steps;
-    c.cdf_steps = d.cdf_steps;
     return c;
 }
 
 // Velocity coordinate at depth t.  Uniform density: zeta is linear in depth.
-// Otherwise the layer j with T[j] <= t < T[j+1] lies in the window of the
-// uniform-depth guide (+-1 cell absorbs the rounding of t * scale) and is
-// found by a bisection with the set's fixed step count; zeta is linear
-// inside the layer.
+// Otherwise the layer j with T[j] <= t < T[j+1] lies between the guide
+// entries of the cells just below and just above t x scale (padded by
+// GUIDE_MARGIN); the staged guide keeps every 2^gshift-th cell, so the
+// lower cell index rounds down and the upper one up.  zeta is linear inside
+// the layer.
 template <typename Real>
-__device__ __forceinline__ Real zeta_at(const SetConst<Real>& c, const Real* T, const uint16_t* lg, Real t) {
+__device__ __forceinline__ Real zeta_at(const SetConst<Real>& c, const Real* T, const uint16_t* lg, int gshift,
+                                        Real t) {
     if (c.uniform_density) return c.v_top - t * c.zeta_per_tau;
-    int gi = (int)(t * c.lg_scale);
-    gi = gi < 0 ? 0 : (gi > LAYER_GUIDE - 1 ? LAYER_GUIDE - 1 : gi);
-    int lo = lg[gi > 0 ? gi - 1 : 0];
-    int hi = lg[gi + 2 <= LAYER_GUIDE ? gi + 2 : LAYER_GUIDE];
+    const Real x = t * c.lg_scale;
+    int a = (int)(x - (Real)GUIDE_MARGIN);
+    int b = (int)(x + (Real)GUIDE_MARGIN) + 1;
+    a = a < 0 ? 0 : (a > LAYER_GUIDE - 1 ? LAYER_GUIDE - 1 : a);
+    b = b > LAYER_GUIDE ? LAYER_GUIDE : b;
+    int lo = lg[a >> gshift];
+    int hi = lg[(b + (1 << gshift) - 1) >> gshift];
     hi = hi > c.n_layers - 1 ? c.n_layers - 1 : hi;
-    for (int s = 0; s < c.layer_steps; ++s) {
+    while (__ballot(lo < hi) != 0ull) {
         const int mid = (lo + hi + 1) >> 1;
         const bool le = T[mid] <= t;
         lo = le ? mid : lo;
@@ -138,16 +152,15 @@ __device__ __forceinline__ Real zeta_at(const SetConst<Real>& c, const Real* T, 
 }
 
 // Scattering angle (cos, sin) from the integer CDF: the cell is the last j
-// with C[j] <= x; it lies between the guide entries of the top bits of x
-// and is found by a bisection with the set's fixed step count; the angle is
-// uniform inside the cell.
+// with C[j] <= x; it lies between the guide entries of the top guide_bits
+// bits of x; the angle is uniform inside the cell.
 template <typename Real>
 __device__ __forceinline__ void table_angle(const SetConst<Real>& c, const uint32_t* C, const uint16_t* cg,
-                                            uint32_t x, Real& ct, Real& st) {
-    const uint32_t gi = x >> (32 - CDF_GUIDE_BITS);
+                                            int guide_bits, uint32_t x, Real& ct, Real& st) {
+    const uint32_t gi = x >> (32 - guide_bits);
     int lo = cg[gi];
     int hi = cg[gi + 1];
-    for (int s = 0; s < c.cdf_steps; ++s) {
+    while (__ballot(lo < hi) != 0ull) {
         const int mid = (lo + hi + 1) >> 1;
         const bool le = C[mid] <= x;
         lo = le ? mid : lo;
@@ -219,14 +232,16 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                  uint64_t* __restrict__ tallies, const WorkItem* __restrict__ items, int n_items,
                  uint32_t* __restrict__ queue, int persistent, int max_layers, int max_cells, int max_bins,
                  ListEntry* __restrict__ lists, uint64_t* __restrict__ list_counts,
-                 const int* __restrict__ n_items_dev) {
+                 const int* __restrict__ n_items_dev, int guide_bits) {
     extern __shared__ __align__(16) uint8_t lds[];
     if (n_items_dev) n_items = *n_items_dev;   // item count from device memory (graph replays)
     __shared__ WorkItem s_item;
     __shared__ int s_item_idx;
     __shared__ uint32_t s_next;
 
-    const LdsLayout L = lds_layout((int)sizeof(Real), max_layers, max_cells, max_bins);
+    const LdsLayout L = lds_layout((int)sizeof(Real), max_layers, max_cells, max_bins, guide_bits);
+    const int gshift = GUIDE_BITS - guide_bits;
+    const int n_guide = 1 << guide_bits;
     Real* sT = (Real*)(lds + L.t_off);
     uint16_t* sLG = (uint16_t*)(lds + L.lg_off);
     uint32_t* sC = (uint32_t*)(lds + L.cdf_off);
@@ -282,14 +297,14 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                 const Real* gT = (const Real*)(tb + (sizeof(Real) == 4 ? TableLayout::T32 : TableLayout::T64));
                 for (int i = tid; i <= d.n_layers; i += nthr) sT[i] = gT[i];
                 const uint16_t* gLG = (const uint16_t*)(tb + TableLayout::LGUIDE);
-                for (int i = tid; i <= LAYER_GUIDE; i += nthr) sLG[i] = gLG[i];
+                for (int i = tid; i <= n_guide; i += nthr) sLG[i] = gLG[i << gshift];
             }
             if (d.phase_kind == PH_TABLE) {
                 const uint32_t* gC = (const uint32_t*)(tb + TableLayout::CDF);
                 for (int i = tid; i < d.n_cells; i += nthr) sC[i] = gC[i];
                 if (tid == 0) sC[d.n_cells] = 0u;
                 const uint16_t* gCG = (const uint16_t*)(tb + TableLayout::CGUIDE);
-                for (int i = tid; i <= CDF_GUIDE; i += nthr) sCG[i] = gCG[i];
+                for (int i = tid; i <= n_guide; i += nthr) sCG[i] = gCG[i << gshift];
             }
             for (int i = tid; i < d.n_bins + N_SINK_SLOTS; i += nthr) sW[i] = 0ull;
             for (int i = tid; i < d.n_bins; i += nthr) sW2[i] = 0ull;
@@ -344,9 +359,9 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
             // particle interaction: scatterer speed, new direction
             Real Vc = 0, mu_c = 0, omc_c = 0;
             if (coll) {
-                Vc = zeta_at<Real>(c, sT, sLG, Tn);
+                Vc = zeta_at<Real>(c, sT, sLG, gshift, Tn);
                 Real ct, st;
-                if (c.phase_kind == PH_TABLE) table_angle<Real>(c, sC, sCG, X.y, ct, st);
+                if (c.phase_kind == PH_TABLE) table_angle<Real>(c, sC, sCG, guide_bits, X.y, ct, st);
                 else hg_angle<Real>(c, u1, ct, st);
                 const Real cphi = M<Real>::cos_rev(u2);
                 const Real sm2 = ((Real)1.0 - mu) * ((Real)1.0 + mu);
@@ -475,53 +490,89 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
 // ---- host launchers ----
 namespace pdv {
 
-int transport_lds_bytes(int real_bytes, int max_layers, int max_cells, int max_bins) {
-    return (int)lds_layout(real_bytes, max_layers, max_cells, max_bins).bytes;
+template <typename Real, bool LIST>
+static const void* kernel_ptr() {
+    return reinterpret_cast<const void*>(&transport_kernel<Real, LIST>);
+}
+
+static const void* select_kernel(int precision, bool list) {
+    if (precision == 1) return list ? kernel_ptr<double, true>() : kernel_ptr<double, false>();
+    return list ? kernel_ptr<float, true>() : kernel_ptr<float, false>();
+}
+
+static hipError_t allow_lds(const void* k, int bytes) {
+    // dynamic LDS beyond 64 KiB must be allowed per kernel
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+// Pick the guide resolution and LDS size of a launch and allow that LDS
+// size for the kernel (outside any graph capture).  want_bits in
+// [MIN_GUIDE_BITS, GUIDE_BITS] forces the resolution; 0 takes the finest
+// whose staging lets as many blocks share a CU's LDS as the kernel's
+// registers allow.  Fails with hipErrorInvalidValue when even the coarsest
+// guide exceeds the per-block LDS limit.
+hipError_t plan_transport(TransportShape& sh, int precision, bool list, int want_bits, int lds_per_block,
+                          int lds_per_cu) {
+    const int rb = precision == 1 ? 8 : 4;
+    auto bytes = [&](int bits) {
+        return (int)lds_layout(rb, sh.max_layers, sh.max_cells, sh.max_bins, bits).bytes;
+    };
+    if (want_bits != 0) {
+        if (want_bits < MIN_GUIDE_BITS || want_bits > GUIDE_BITS) return hipErrorInvalidValue;
+        sh.guide_bits = want_bits;
+    } else {
+        int resident = 1;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, select_kernel(precision, list),
+                                                                    sh.block, 0);
+        if (e != hipSuccess) return e;
+        if (resident < 1) resident = 1;
+        const int budget = std::min(lds_per_block, lds_per_cu / resident);
+        sh.guide_bits = MIN_GUIDE_BITS;
+        for (int b = GUIDE_BITS; b > MIN_GUIDE_BITS; --b)
+            if (bytes(b) <= budget) { sh.guide_bits = b; break; }
+    }
+    sh.lds_bytes = bytes(sh.guide_bits);
+    if (sh.lds_bytes > lds_per_block) return hipErrorInvalidValue;
+    return allow_lds(select_kernel(precision, list), sh.lds_bytes);
 }
 
 template <typename Real, bool LIST>
-static hipError_t launch_one(hipStream_t s, int grid, int block, int lds, const SetDesc* descs,
-                             const uint8_t* tables, uint64_t* tallies, const WorkItem* items, int n_items,
-                             uint32_t* queue, int persistent, int max_layers, int max_cells, int max_bins,
-                             ListEntry* lists, uint64_t* list_counts) {
-    hipLaunchKernelGGL((transport_kernel<Real, LIST>), dim3(grid), dim3(block), lds, s, descs, tables, tallies,
-                       items, n_items, queue, persistent, max_layers, max_cells, max_bins, lists, list_counts,
-                       (const int*)nullptr);
+static hipError_t launch_one(hipStream_t s, const TransportShape& sh, const SetDesc* descs, const uint8_t* tables,
+                             uint64_t* tallies, const WorkItem* items, int n_items, const int* n_items_dev,
+                             uint32_t* queue, int persistent, ListEntry* lists, uint64_t* list_counts) {
+    hipLaunchKernelGGL((transport_kernel<Real, LIST>), dim3(sh.grid), dim3(sh.block), sh.lds_bytes, s, descs,
+                       tables, tallies, items, n_items, queue, persistent, sh.max_layers, sh.max_cells, sh.max_bins,
+                       lists, list_counts, n_items_dev, sh.guide_bits);
     return hipGetLastError();
 }
 
 // Persistent launch whose item count is read from device memory, so a
 // captured graph can be replayed with a different item list.
-hipError_t launch_transport_dev(hipStream_t s, int precision, int grid, int block, int lds_bytes,
-                                const SetDesc* descs, const uint8_t* tables, uint64_t* tallies,
-                                const WorkItem* items, const int* n_items_dev, uint32_t* queue, int max_layers,
-                                int max_cells, int max_bins) {
+hipError_t launch_transport_dev(hipStream_t s, int precision, const TransportShape& sh, const SetDesc* descs,
+                                const uint8_t* tables, uint64_t* tallies, const WorkItem* items,
+                                const int* n_items_dev, uint32_t* queue) {
     if (precision == 1)
-        hipLaunchKernelGGL((transport_kernel<double, false>), dim3(grid), dim3(block), lds_bytes, s, descs, tables,
-                           tallies, items, 0, queue, 1, max_layers, max_cells, max_bins, (ListEntry*)nullptr,
-                           (uint64_t*)nullptr, n_items_dev);
-    else
-        hipLaunchKernelGGL((transport_kernel<float, false>), dim3(grid), dim3(block), lds_bytes, s, descs, tables,
-                           tallies, items, 0, queue, 1, max_layers, max_cells, max_bins, (ListEntry*)nullptr,
-                           (uint64_t*)nullptr, n_items_dev);
-    return hipGetLastError();
+        return launch_one<double, false>(s, sh, descs, tables, tallies, items, 0, n_items_dev, queue, 1, nullptr,
+                                         nullptr);
+    return launch_one<float, false>(s, sh, descs, tables, tallies, items, 0, n_items_dev, queue, 1, nullptr,
+                                    nullptr);
 }
 
-hipError_t launch_transport(hipStream_t s, int precision, bool list, int grid, int block, int lds_bytes,
+hipError_t launch_transport(hipStream_t s, int precision, bool list, const TransportShape& sh,
                             const SetDesc* descs, const uint8_t* tables, uint64_t* tallies, const WorkItem* items,
-                            int n_items, uint32_t* queue, int persistent, int max_layers, int max_cells,
-                            int max_bins, ListEntry* lists, uint64_t* list_counts) {
+                            int n_items, uint32_t* queue, int persistent, ListEntry* lists,
+                            uint64_t* list_counts) {
     if (precision == 1) {
-        return list ? launch_one<double, true>(s, grid, block, lds_bytes, descs, tables, tallies, items, n_items,
-                                               queue, persistent, max_layers, max_cells, max_bins, lists, list_counts)
-                    : launch_one<double, false>(s, grid, block, lds_bytes, descs, tables, tallies, items, n_items,
-                                                queue, persistent, max_layers, max_cells, max_bins, lists,
-                                                list_counts);
+        return list ? launch_one<double, true>(s, sh, descs, tables, tallies, items, n_items, nullptr, queue,
+                                               persistent, lists, list_counts)
+                    : launch_one<double, false>(s, sh, descs, tables, tallies, items, n_items, nullptr, queue,
+                                                persistent, lists, list_counts);
     }
-    return list ? launch_one<float, true>(s, grid, block, lds_bytes, descs, tables, tallies, items, n_items, queue,
-                                          persistent, max_layers, max_cells, max_bins, lists, list_counts)
-                : launch_one<float, false>(s, grid, block, lds_bytes, descs, tables, tallies, items, n_items, queue,
-                                           persistent, max_layers, max_cells, max_bins, lists, list_counts);
+    return list ? launch_one<float, true>(s, sh, descs, tables, tallies, items, n_items, nullptr, queue, persistent,
+                                          lists, list_counts)
+                : launch_one<float, false>(s, sh, descs, tables, tallies, items, n_items, nullptr, queue,
+                                           persistent, lists, list_counts);
 }
 
 }  // namespace pdv

@@ -76,7 +76,7 @@ class SpectrumOut(ctypes.Structure):
 class LaunchOpts(ctypes.Structure):
     _fields_ = [("block_size", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("packets_per_item", ctypes.c_uint64), ("persistent", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("guide_bits", ctypes.c_int32)]
 
 
 class SgParams(ctypes.Structure):
@@ -122,7 +122,8 @@ def load():
                                         ctypes.c_int32, P(ctypes.c_float)]
     lib.pdv_stft.argtypes = [V, P(ctypes.c_float), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                              P(ctypes.c_float), P(ctypes.c_int32)]
-    lib.pdv_last_launch.argtypes = [V, P(ctypes.c_float), P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32)]
+    lib.pdv_last_launch.argtypes = [V, P(ctypes.c_float), P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32),
+                                    P(ctypes.c_int32), P(ctypes.c_int32)]
     _lib = lib
     return lib
 
@@ -241,15 +242,17 @@ class Context:
         if opts:
             o = LaunchOpts(int(opts.get("block_size", 0)), int(opts.get("blocks_per_cu", 0)),
                            int(opts.get("packets_per_item", 0)), int(opts.get("persistent", -1)),
-                           int(opts.get("use_graph", 0)))
+                           int(opts.get("use_graph", 0)), int(opts.get("guide_bits", 0)))
         self._check(self.lib.pdv_spectrum_batch(self.h, arr, n, outs, ctypes.byref(o) if o else None))
         return [_result(outs[i], *bufs[i]) for i in range(n)]
 
     def last_launch(self) -> dict:
         ms = ctypes.c_float()
-        g, b, it = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        self.lib.pdv_last_launch(self.h, ctypes.byref(ms), ctypes.byref(g), ctypes.byref(b), ctypes.byref(it))
-        return {"kernel_ms": float(ms.value), "grid": g.value, "block": b.value, "items": it.value}
+        g, b, it, gb, lds = (ctypes.c_int32() for _ in range(5))
+        self.lib.pdv_last_launch(self.h, ctypes.byref(ms), ctypes.byref(g), ctypes.byref(b), ctypes.byref(it),
+                                 ctypes.byref(gb), ctypes.byref(lds))
+        return {"kernel_ms": float(ms.value), "grid": g.value, "block": b.value, "items": it.value,
+                "guide_bits": gb.value, "lds_bytes": lds.value}
 
 
 def _fptr(a):
@@ -520,7 +523,8 @@ def _autotune(self, sets: list, repeats: int = 3, cache_path: str | None = None)
             cache = json.load(f)
         if key in cache:
             e = cache[key]
-            o = LaunchOpts(e["block_size"], e["blocks_per_cu"], e["packets_per_item"], e["persistent"], 0)
+            o = LaunchOpts(e["block_size"], e["blocks_per_cu"], e["packets_per_item"], e["persistent"], 0,
+                           e.get("guide_bits", 0))
             self._check(lib.pdv_set_launch_defaults(self.h, ctypes.byref(o)))
             return dict(e, cached=True)
     keep = []
@@ -531,7 +535,8 @@ def _autotune(self, sets: list, repeats: int = 3, cache_path: str | None = None)
     self._check(lib.pdv_autotune(self.h, arr, len(sets), int(repeats), ctypes.byref(best), ctypes.byref(rep)))
     e = {"block_size": best.block_size, "blocks_per_cu": best.blocks_per_cu,
          "packets_per_item": best.packets_per_item, "persistent": best.persistent,
-         "candidates": rep.candidates, "invariant": bool(rep.invariant), "best_ms": rep.best_ms,
+         "guide_bits": best.guide_bits, "candidates": rep.candidates, "invariant": bool(rep.invariant),
+         "best_ms": rep.best_ms,
          "worst_ms": rep.worst_ms, "default_ms": rep.default_ms}
     if cache_path:
         cache[key] = e

@@ -126,6 +126,28 @@ def test_launch_shape_invariance(ctx):
         assert r["sinks_fx"] == ref["sinks_fx"], opts
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_guide_resolution_invariance(ctx, precision):
+    # the staged guide resolution is a table layout: tallies are bitwise equal
+    # for every resolution, on layered (exponential and tabulated) clouds with
+    # a tabulated phase function
+    rng = np.random.Generator(np.random.PCG64(23))
+    dens = np.exp(rng.uniform(-9.0, 0.0, 700))
+    dens[100:140] = 0.0
+    cases = [dict(wl.large_mie(150_000), precision=precision),
+             dict(wl.large_mie(150_000), precision=precision, density_kind=wl.DENSITY_TABLE, density=dens,
+                  n_layers=700, tau_total=3.0)]
+    for p in cases:
+        ref = ctx.spectrum_batch([p], opts=dict(guide_bits=11))[0]
+        assert ctx.last_launch()["guide_bits"] == 11
+        for gb in (12, 13, 14, 0):
+            r = ctx.spectrum_batch([p], opts=dict(guide_bits=gb))[0]
+            if gb:
+                assert ctx.last_launch()["guide_bits"] == gb
+            assert np.array_equal(r["w_fx"], ref["w_fx"]) and np.array_equal(r["w2_fx"], ref["w2_fx"]), gb
+            assert r["sinks_fx"] == ref["sinks_fx"] and r["counts"] == ref["counts"], gb
+
+
 def test_partition_invariance(ctx):
     # two launches over disjoint packet ranges sum to one launch, bitwise
     p = _c1(n_packets=250_000, tau_total=1.0, cone_half_angle=math.radians(50))
@@ -160,6 +182,10 @@ def test_validation_errors(ctx):
                 dict(albedo=1.5), dict(tau_total=-1.0), dict(n_layers=0), dict(n_packets=2**33)):
         with pytest.raises(pdv.PdvError) as e:
             ctx.spectrum(_c1(**bad))
+        assert e.value.code == -1
+    for gb in (10, 15):
+        with pytest.raises(pdv.PdvError) as e:
+            ctx.spectrum_batch([_c1(n_packets=1000)], opts=dict(guide_bits=gb))
         assert e.value.code == -1
     # context stays usable after validation errors
     assert conservation_exact(ctx.spectrum(_c1(n_packets=1000)), 1000)
