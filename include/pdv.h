@@ -189,6 +189,9 @@ typedef struct pdv_launch_opts {
     int32_t guide_bits;          /* search-guide cells 2^guide_bits staged in LDS, 11..14; 0 = the finest
                                     that keeps the launch's blocks resident (a table layout: results are
                                     bitwise the same for every value) */
+    int32_t retire_batch;        /* finished lanes a wave collects before it tallies and refills them,
+                                    1..64; 0 = default (12 for FP32, 1 for FP64); results do not
+                                    depend on it */
 } pdv_launch_opts;
 
 /*

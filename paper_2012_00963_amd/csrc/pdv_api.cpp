@@ -380,12 +380,15 @@ void pdv::fill_desc(SetDesc& d, const pdv_params& p) {
     d.n_bins = p.n_bins;
 }
 
-void pdv_ctx::default_opts(pdv_launch_opts& o, uint64_t total_packets, int n_sets) const {
+void pdv_ctx::default_opts(pdv_launch_opts& o, uint64_t total_packets, int n_sets, bool fp64) const {
     (void)n_sets;
     if (o.block_size <= 0) o.block_size = tuned.block_size > 0 ? tuned.block_size : 512;
     if (o.blocks_per_cu <= 0) o.blocks_per_cu = tuned.blocks_per_cu > 0 ? tuned.blocks_per_cu : 4;
     if (o.persistent < 0) o.persistent = tuned.persistent >= 0 ? tuned.persistent : 1;
     if (o.guide_bits == 0) o.guide_bits = tuned.guide_bits;
+    // measured on the large case: 12 for FP32 transport; FP64 is fastest
+    // tallying every round
+    if (o.retire_batch == 0) o.retire_batch = tuned.retire_batch > 0 ? tuned.retire_batch : (fp64 ? 1 : 12);
     if (o.packets_per_item == 0) {
         uint64_t grid = (uint64_t)n_cu * (uint64_t)o.blocks_per_cu;
         uint64_t ppi = total_packets / (grid * 4 + 1);
@@ -409,15 +412,16 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
     }
     if (int r = hip_check(hipSetDevice(device), "hipSetDevice")) return r;
 
-    pdv_launch_opts o{0, 0, 0, -1, 0, 0};
+    pdv_launch_opts o{0, 0, 0, -1, 0, 0, 0};
     if (opts_in) o = *opts_in;
     uint64_t total = 0;
     for (int i = 0; i < n; ++i) total += sets[i].n_packets;
-    default_opts(o, total, n);
+    default_opts(o, total, n, precision == PDV_FP64);
     if (o.block_size != 256 && o.block_size != 512 && o.block_size != 1024)
         return fail(PDV_EINVAL, "block_size must be 256, 512 or 1024");
     if (o.guide_bits != 0 && (o.guide_bits < MIN_GUIDE_BITS || o.guide_bits > GUIDE_BITS))
         return fail(PDV_EINVAL, "guide_bits must be 0 or %d..%d", MIN_GUIDE_BITS, GUIDE_BITS);
+    if (o.retire_batch < 1 || o.retire_batch > 64) return fail(PDV_EINVAL, "retire_batch must be 0 or 1..64");
 
     // ---- host-side packing ----
     // Sets whose tables would be identical (same cloud and optics, e.g. the
@@ -570,6 +574,7 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
     sh.max_layers = max_layers;
     sh.max_cells = max_cells;
     sh.max_bins = max_bins;
+    sh.retire_min = o.retire_batch;
     {
         hipError_t e = plan_transport(sh, precision, list_capacity > 0, o.guide_bits, lds_per_block, lds_per_cu);
         if (e == hipErrorInvalidValue)
@@ -914,11 +919,13 @@ extern "C" int pdv_set_launch_defaults(pdv_ctx* ctx, const pdv_launch_opts* o) {
     if (o->packets_per_item > (1ull << 31)) return ctx->fail(PDV_EINVAL, "packets_per_item out of range");
     if (o->guide_bits != 0 && (o->guide_bits < MIN_GUIDE_BITS || o->guide_bits > GUIDE_BITS))
         return ctx->fail(PDV_EINVAL, "guide_bits must be 0 or %d..%d", MIN_GUIDE_BITS, GUIDE_BITS);
+    if (o->retire_batch < 0 || o->retire_batch > 64) return ctx->fail(PDV_EINVAL, "retire_batch must be 0..64");
     ctx->tuned.block_size = o->block_size;
     ctx->tuned.blocks_per_cu = o->blocks_per_cu;
     ctx->tuned.packets_per_item = o->packets_per_item;
     ctx->tuned.persistent = o->persistent;
     ctx->tuned.guide_bits = o->guide_bits;
+    ctx->tuned.retire_batch = o->retire_batch;
     return PDV_OK;
 }
 
@@ -943,11 +950,11 @@ extern "C" int pdv_autotune(pdv_ctx* ctx, const pdv_params* sets, int32_t n, int
         return r;
     };
     // reference: the current default shape, resolved to explicit values
-    pdv_launch_opts def{0, 0, 0, -1, 0, 0};
+    pdv_launch_opts def{0, 0, 0, -1, 0, 0, 0};
     {
         uint64_t total = 0;
         for (int i = 0; i < n; ++i) total += sets[i].n_packets;
-        ctx->default_opts(def, total, n);
+        ctx->default_opts(def, total, n, sets[0].precision == PDV_FP64);
     }
     float ms = 0;
     if (int r = run(def, &ms)) return r;
@@ -976,8 +983,8 @@ extern "C" int pdv_autotune(pdv_ctx* ctx, const pdv_params* sets, int32_t n, int
     std::vector<pdv_launch_opts> cands;
     for (int bs : {256, 512, 1024}) {
         for (uint64_t ppi : {1ull << 12, 1ull << 14, 1ull << 16, 1ull << 18}) {
-            for (int bpc : {1, 2, 4, 8}) cands.push_back(pdv_launch_opts{bs, bpc, ppi, 1, 0, 0});
-            cands.push_back(pdv_launch_opts{bs, 1, ppi, 0, 0, 0});
+            for (int bpc : {1, 2, 4, 8}) cands.push_back(pdv_launch_opts{bs, bpc, ppi, 1, 0, 0, 0});
+            cands.push_back(pdv_launch_opts{bs, 1, ppi, 0, 0, 0, 0});
         }
     }
     double best_ms = 1e300, worst_ms = 0, def_ms = 0;
@@ -1016,6 +1023,12 @@ extern "C" int pdv_autotune(pdv_ctx* ctx, const pdv_params* sets, int32_t n, int
             o.guide_bits = gb;
             if (int r = consider(o, true)) return r;
         }
+        base = best_o;
+        for (int rb : {4, 8, 12, 24, 32}) {
+            pdv_launch_opts o = base;
+            o.retire_batch = rb;
+            if (int r = consider(o, false)) return r;
+        }
     }
     if (report) {
         report->candidates = timed;
@@ -1030,6 +1043,7 @@ extern "C" int pdv_autotune(pdv_ctx* ctx, const pdv_params* sets, int32_t n, int
     ctx->tuned.packets_per_item = best_o.packets_per_item;
     ctx->tuned.persistent = best_o.persistent;
     ctx->tuned.guide_bits = best_o.guide_bits;
+    ctx->tuned.retire_batch = best_o.retire_batch;
     if (best) *best = best_o;
     return PDV_OK;
 }

@@ -42,6 +42,7 @@ struct TunedLaunch {
     uint64_t packets_per_item = 0;
     int32_t persistent = -1;
     int32_t guide_bits = 0;
+    int32_t retire_batch = 0;
 };
 
 struct ServeEngine;   // serving loop (serve.cpp)
@@ -99,7 +100,7 @@ struct pdv_ctx {
     int hip_check(hipError_t e, const char* what);
     int ensure(DevBuf& b, size_t bytes, const char* what);
     int ensure_mie_basis(const pdv_params& p);
-    void default_opts(pdv_launch_opts& o, uint64_t total_packets, int n_sets) const;
+    void default_opts(pdv_launch_opts& o, uint64_t total_packets, int n_sets, bool fp64) const;
     int run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, const pdv_launch_opts* opts,
                   uint64_t list_capacity, bool keep_device);
     int synthesize(int n_frames, const uint64_t* entry_begin, const uint64_t* n_entries, const ListEntry_* entries,

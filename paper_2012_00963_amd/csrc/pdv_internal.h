@@ -113,6 +113,7 @@ struct TransportShape {
     int max_layers = 0, max_cells = 0, max_bins = 0;   // LDS staging sizes of the batch
     int guide_bits = GUIDE_BITS;                        // staged guide resolution
     int lds_bytes = 0;
+    int retire_min = 12;                                // finished lanes per retire round
 };
 
 // Table-building jobs (host-packed, one per set).

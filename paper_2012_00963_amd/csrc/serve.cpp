@@ -170,6 +170,7 @@ struct HipExecutor : Executor {
         shape.max_layers = E->opts.max_layers;
         shape.max_cells = E->opts.max_angles - 1;
         shape.max_bins = E->opts.max_bins;
+        shape.retire_min = E->opts.precision == PDV_FP64 ? 1 : 12;
         hipError_t e = plan_transport(shape, E->opts.precision, false, 0, ctx->lds_per_block, ctx->lds_per_cu);
         if (e == hipErrorInvalidValue) {
             err = "serving limits need more LDS per block than the device has";

@@ -25,9 +25,11 @@
 // tables (layer depths + uniform-depth guide, integer phase CDF + guide) and
 // a private histogram in LDS; the histogram carries the velocity bins and
 // one slot per terminal sink, so every finished packet costs one LDS atomic
-// (two for a binned detection).  Waves refill finished lanes with the next
-// packet ids of the current work item (one LDS atomic per wave per refill
-// round).  Table searches are bisections inside the window of a guide of
+// (two for a binned detection).  A finished lane keeps its packet's final
+// state until enough lanes of its wave have finished; the wave then tallies
+// them together and refills them from a wave-private range of the work item
+// (one LDS atomic per range), so the divergent tally and refill code runs
+// once per round instead of on nearly every event.  Table searches are bisections inside the window of a guide of
 // up to 2^14 cells (the launch picks the finest that fits its LDS budget);
 // the guides are fine enough that most windows hold one entry, and a
 // wave leaves the search as soon as all of its lanes have converged.  Event counters and absorbed
@@ -55,6 +57,12 @@ __host__ __device__ inline uint32_t align16(uint32_t x) { return (x + 15u) & ~15
 
 // terminal-sink slots follow the velocity bins in the LDS histogram
 constexpr int N_SINK_SLOTS = 8;
+
+// lane states of the event loop
+enum LaneState : int { ST_EMPTY = 0, ST_ALIVE = 1, ST_EXIT = 2, ST_TRUNC = 3, ST_ABS_SURF = 4, ST_ABS_PART = 5 };
+
+// packet indices a wave claims from its work item at a time
+constexpr int REFILL_CHUNK = 128;
 
 __host__ __device__ inline LdsLayout lds_layout(int real_bytes, int max_layers, int max_cells, int max_bins,
                                                 int guide_bits) {
@@ -232,7 +240,7 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                  uint64_t* __restrict__ tallies, const WorkItem* __restrict__ items, int n_items,
                  uint32_t* __restrict__ queue, int persistent, int max_layers, int max_cells, int max_bins,
                  ListEntry* __restrict__ lists, uint64_t* __restrict__ list_counts,
-                 const int* __restrict__ n_items_dev, int guide_bits) {
+                 const int* __restrict__ n_items_dev, int guide_bits, int retire_min) {
     extern __shared__ __align__(16) uint8_t lds[];
     if (n_items_dev) n_items = *n_items_dev;   // item count from device memory (graph replays)
     __shared__ WorkItem s_item;
@@ -316,36 +324,119 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
         const int nb = c.n_bins;
 
         // ---- per-lane packet state ----
-        bool alive = false;
-        bool exhausted = false;
+        // st: ST_EMPTY (no packet), ST_ALIVE, or how the packet ended (its
+        // tally waits for the wave's next retire round)
+        int st = ST_EMPTY;
+        bool exhausted = false;              // the item has no packets left for this wave
+        uint32_t w_next = 0, w_end = 0;      // wave-private range of item-local packet indices
         uint64_t pid = 0;
         uint32_t k = 0;
         int n_sc = 0, n_surf = 0;
         Real T = 0, mu = -1, w = 1, big = 0, small = 0, abs_s = 0;
 
         while (true) {
-            // refill finished lanes with the next packets of the item
-            const uint64_t dead = __ballot(!alive);
-            if (dead != 0ull && !exhausted) {
-                const uint32_t n = (uint32_t)__popcll(dead);
-                uint32_t base = 0;
-                if (lane == 0) base = atomicAdd(&s_next, n);
-                base = uniform_u32(base);
-                if (base + n >= count) exhausted = true;
-                if (!alive) {
-                    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(dead >> 32),
-                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)dead, 0u));
-                    const uint32_t local = base + rank;
-                    if (local < count) {
-                        alive = true;
-                        pid = pid0 + local;
-                        k = 0; n_sc = 0; n_surf = 0;
-                        T = 0; mu = -1; w = 1; big = 0; small = 0; abs_s = 0;
+            // Retire and refill in rounds: when retire_min lanes wait (or all
+            // do), tally the finished packets and start new ones from the
+            // wave's range, claiming a new range from the item when it runs out.
+            const uint64_t idle = __ballot(st != ST_ALIVE);
+            if (idle == ~0ull || (!exhausted && (int)__popcll(idle) >= retire_min)) {
+                if (st >= ST_EXIT) {
+                    // ---- the packet's tally: one terminal slot of the LDS histogram ----
+                    const bool detected = st == ST_EXIT && mu >= c.cos_cone;
+                    int slot;
+                    double vt = 0.0;
+                    if (detected) {
+                        vt = (double)big - (double)small;
+                        double bf;
+                        if constexpr (sizeof(Real) == 8) bf = floor((vt - c.v_lo) / c.dv);
+                        else bf = floor((vt - c.v_lo) * c.inv_dv);
+                        slot = bf < 0.0 ? nb + SK_UNDER : (bf >= (double)nb ? nb + SK_OVER : (int)bf);
+                    } else {
+                        slot = nb + (st == ST_EXIT ? SK_UNDETECTED
+                                                   : (st == ST_TRUNC ? SK_TRUNCATED
+                                                                     : (st == ST_ABS_SURF ? SK_ABS_SURFACE
+                                                                                          : SK_ABS_PARTICLE)));
                     }
+                    const uint64_t fw = to_fixed32<Real>(w);
+                    atomicAdd(&sW[slot], (unsigned long long)fw);
+                    if (slot < nb) {
+                        atomicAdd(&sW2[slot], (unsigned long long)to_fixed32<Real>(w * w));
+                        if (c.flags & SF_CLASS) {
+                            unsigned long long* gcl =
+                                (unsigned long long*)(tallies + descs[set].tally_offset + tw_class(nb));
+                            if (n_sc == 1 && n_surf == 0) atomicAdd(gcl + slot, (unsigned long long)fw);
+                            if (n_sc == 0 && n_surf == 1) atomicAdd(gcl + nb + slot, (unsigned long long)fw);
+                        }
+                    }
+                    if constexpr (LIST) {
+                        if (detected) {
+                            const Block4 P = philox10(0xffffffffu, (uint32_t)pid, (uint32_t)(pid >> 32), c.stream,
+                                                      c.k0, c.k1);
+                            const SetDesc& d = descs[set];
+                            const uint64_t m = __ballot(1);
+                            const int leader = __ffsll((unsigned long long)m) - 1;
+                            const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+                            unsigned long long lbase = 0;
+                            if (lane == leader)
+                                lbase = atomicAdd((unsigned long long*)(list_counts + set),
+                                                  (unsigned long long)__popcll(m));
+                            lbase = __shfl(lbase, leader, 64);
+                            const unsigned long long lslot = lbase + rank;
+                            if (lslot < d.list_capacity) {
+                                ListEntry e;
+                                e.w = (float)w;
+                                e.phase = P.x;
+                                e.v = vt;
+                                lists[d.list_offset + lslot] = e;
+                            }
+                        }
+                    }
+                    // implicit capture: the packet's 2^32 units are split exactly
+                    // between its terminal slot and the two absorption sinks
+                    if (c.weighting == 0) {
+                        const uint64_t fs = to_fixed32<Real>(abs_s);
+                        acc.abs_surface += fs;
+                        acc.abs_particle += (4294967296ull - fw) - fs;
+                    }
+                    acc.packets += 1;
+                    acc.collisions += (uint32_t)n_sc;
+                    acc.surface += (uint32_t)n_surf;
+                    acc.exits += st == ST_EXIT ? 1u : 0u;
+                    acc.detected += detected ? 1u : 0u;
+                    st = ST_EMPTY;
                 }
+                uint64_t empty = __ballot(st == ST_EMPTY);
+                while (empty != 0ull && !exhausted) {
+                    if (w_next >= w_end) {
+                        uint32_t base = 0;
+                        if (lane == 0) base = atomicAdd(&s_next, (uint32_t)REFILL_CHUNK);
+                        base = uniform_u32(base);
+                        if (base >= count) {
+                            exhausted = true;
+                            break;
+                        }
+                        w_next = base;
+                        w_end = count - base < (uint32_t)REFILL_CHUNK ? count : base + (uint32_t)REFILL_CHUNK;
+                    }
+                    const uint32_t n = (uint32_t)__popcll(empty);
+                    const uint32_t avail = w_end - w_next;
+                    const uint32_t take = n < avail ? n : avail;
+                    if (st == ST_EMPTY) {
+                        const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(empty >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)empty, 0u));
+                        if (rank < take) {
+                            st = ST_ALIVE;
+                            pid = pid0 + w_next + rank;
+                            k = 0; n_sc = 0; n_surf = 0;
+                            T = 0; mu = -1; w = 1; big = 0; small = 0; abs_s = 0;
+                        }
+                    }
+                    w_next += take;
+                    empty = __ballot(st == ST_EMPTY);
+                }
+                if (__ballot(st == ST_ALIVE) == 0ull) break;
             }
-            if (__ballot(alive) == 0ull) break;
-            if (alive) {
+            if (st == ST_ALIVE) {
             const Block4 X = philox10(k, (uint32_t)pid, (uint32_t)(pid >> 32), c.stream, c.k0, c.k1);
             k += 1;
             const Real u0 = unit_open<Real>(X.x);
@@ -360,12 +451,12 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
             Real Vc = 0, mu_c = 0, omc_c = 0;
             if (coll) {
                 Vc = zeta_at<Real>(c, sT, sLG, gshift, Tn);
-                Real ct, st;
-                if (c.phase_kind == PH_TABLE) table_angle<Real>(c, sC, sCG, guide_bits, X.y, ct, st);
-                else hg_angle<Real>(c, u1, ct, st);
+                Real ct, st_;
+                if (c.phase_kind == PH_TABLE) table_angle<Real>(c, sC, sCG, guide_bits, X.y, ct, st_);
+                else hg_angle<Real>(c, u1, ct, st_);
                 const Real cphi = M<Real>::cos_rev(u2);
                 const Real sm2 = ((Real)1.0 - mu) * ((Real)1.0 + mu);
-                Real m2 = mu * ct + M<Real>::sqrt(sm2 > (Real)0 ? sm2 : (Real)0) * st * cphi;
+                Real m2 = mu * ct + M<Real>::sqrt(sm2 > (Real)0 ? sm2 : (Real)0) * st_ * cphi;
                 m2 = m2 > (Real)1.0 ? (Real)1.0 : (m2 < (Real)-1.0 ? (Real)-1.0 : m2);
                 mu_c = m2;
                 omc_c = (Real)1.0 - m2;
@@ -400,6 +491,10 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                 const bool one = surf ? (bool)c.surface_one : (bool)c.albedo_one;
                 absorbed = !leave && !trunc && !one && X.w >= thr;
             }
+            // the event counts as a collision or surface hit whether or not
+            // the packet continues
+            n_surf += surf ? 1 : 0;
+            n_sc += coll ? 1 : 0;
             if (!(leave || trunc || absorbed)) {
                 if (c.weighting == 0) {
                     const Real lost = w * ((Real)1.0 - a);
@@ -410,73 +505,8 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                 small += (Real)0.5 * V * omc;
                 mu = mu_new;
                 T = surf ? c.tau : Tn;
-                n_surf += surf ? 1 : 0;
-                n_sc += surf ? 0 : 1;
             } else {
-                // ---- the packet ends: one terminal slot of the LDS histogram ----
-                const bool detected = leave && mu >= c.cos_cone;
-                int slot;
-                double vt = 0.0;
-                if (detected) {
-                    vt = (double)big - (double)small;
-                    double bf;
-                    if constexpr (sizeof(Real) == 8) bf = floor((vt - c.v_lo) / c.dv);
-                    else bf = floor((vt - c.v_lo) * c.inv_dv);
-                    slot = bf < 0.0 ? nb + SK_UNDER : (bf >= (double)nb ? nb + SK_OVER : (int)bf);
-                } else if (leave) {
-                    slot = nb + SK_UNDETECTED;
-                } else if (trunc) {
-                    slot = nb + SK_TRUNCATED;
-                } else {
-                    slot = nb + (surf ? SK_ABS_SURFACE : SK_ABS_PARTICLE);
-                }
-                const uint64_t fw = to_fixed32<Real>(w);
-                atomicAdd(&sW[slot], (unsigned long long)fw);
-                if (slot < nb) {
-                    atomicAdd(&sW2[slot], (unsigned long long)to_fixed32<Real>(w * w));
-                    if (c.flags & SF_CLASS) {
-                        unsigned long long* gcl =
-                            (unsigned long long*)(tallies + descs[set].tally_offset + tw_class(nb));
-                        if (n_sc == 1 && n_surf == 0) atomicAdd(gcl + slot, (unsigned long long)fw);
-                        if (n_sc == 0 && n_surf == 1) atomicAdd(gcl + nb + slot, (unsigned long long)fw);
-                    }
-                }
-                if constexpr (LIST) {
-                    if (detected) {
-                        const Block4 P = philox10(0xffffffffu, (uint32_t)pid, (uint32_t)(pid >> 32), c.stream,
-                                                  c.k0, c.k1);
-                        const SetDesc& d = descs[set];
-                        const uint64_t m = __ballot(1);
-                        const int leader = __ffsll((unsigned long long)m) - 1;
-                        const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-                        unsigned long long lbase = 0;
-                        if (lane == leader)
-                            lbase = atomicAdd((unsigned long long*)(list_counts + set),
-                                              (unsigned long long)__popcll(m));
-                        lbase = __shfl(lbase, leader, 64);
-                        const unsigned long long lslot = lbase + rank;
-                        if (lslot < d.list_capacity) {
-                            ListEntry e;
-                            e.w = (float)w;
-                            e.phase = P.x;
-                            e.v = vt;
-                            lists[d.list_offset + lslot] = e;
-                        }
-                    }
-                }
-                // implicit capture: the packet's 2^32 units are split exactly
-                // between its terminal slot and the two absorption sinks
-                if (c.weighting == 0) {
-                    const uint64_t fs = to_fixed32<Real>(abs_s);
-                    acc.abs_surface += fs;
-                    acc.abs_particle += (4294967296ull - fw) - fs;
-                }
-                acc.packets += 1;
-                acc.collisions += (uint32_t)n_sc + (coll ? 1u : 0u);
-                acc.surface += (uint32_t)n_surf + (surf ? 1u : 0u);
-                acc.exits += leave ? 1u : 0u;
-                acc.detected += detected ? 1u : 0u;
-                alive = false;
+                st = leave ? ST_EXIT : (trunc ? ST_TRUNC : (surf ? ST_ABS_SURF : ST_ABS_PART));
             }
             }  // alive
         }
@@ -543,7 +573,7 @@ static hipError_t launch_one(hipStream_t s, const TransportShape& sh, const SetD
                              uint32_t* queue, int persistent, ListEntry* lists, uint64_t* list_counts) {
     hipLaunchKernelGGL((transport_kernel<Real, LIST>), dim3(sh.grid), dim3(sh.block), sh.lds_bytes, s, descs,
                        tables, tallies, items, n_items, queue, persistent, sh.max_layers, sh.max_cells, sh.max_bins,
-                       lists, list_counts, n_items_dev, sh.guide_bits);
+                       lists, list_counts, n_items_dev, sh.guide_bits, sh.retire_min);
     return hipGetLastError();
 }
 

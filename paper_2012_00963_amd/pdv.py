@@ -76,7 +76,8 @@ class SpectrumOut(ctypes.Structure):
 class LaunchOpts(ctypes.Structure):
     _fields_ = [("block_size", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("packets_per_item", ctypes.c_uint64), ("persistent", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("guide_bits", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("guide_bits", ctypes.c_int32),
+                ("retire_batch", ctypes.c_int32)]
 
 
 class SgParams(ctypes.Structure):
@@ -242,7 +243,8 @@ class Context:
         if opts:
             o = LaunchOpts(int(opts.get("block_size", 0)), int(opts.get("blocks_per_cu", 0)),
                            int(opts.get("packets_per_item", 0)), int(opts.get("persistent", -1)),
-                           int(opts.get("use_graph", 0)), int(opts.get("guide_bits", 0)))
+                           int(opts.get("use_graph", 0)), int(opts.get("guide_bits", 0)),
+                           int(opts.get("retire_batch", 0)))
         self._check(self.lib.pdv_spectrum_batch(self.h, arr, n, outs, ctypes.byref(o) if o else None))
         return [_result(outs[i], *bufs[i]) for i in range(n)]
 
@@ -524,7 +526,7 @@ def _autotune(self, sets: list, repeats: int = 3, cache_path: str | None = None)
         if key in cache:
             e = cache[key]
             o = LaunchOpts(e["block_size"], e["blocks_per_cu"], e["packets_per_item"], e["persistent"], 0,
-                           e.get("guide_bits", 0))
+                           e.get("guide_bits", 0), e.get("retire_batch", 0))
             self._check(lib.pdv_set_launch_defaults(self.h, ctypes.byref(o)))
             return dict(e, cached=True)
     keep = []
@@ -535,9 +537,9 @@ def _autotune(self, sets: list, repeats: int = 3, cache_path: str | None = None)
     self._check(lib.pdv_autotune(self.h, arr, len(sets), int(repeats), ctypes.byref(best), ctypes.byref(rep)))
     e = {"block_size": best.block_size, "blocks_per_cu": best.blocks_per_cu,
          "packets_per_item": best.packets_per_item, "persistent": best.persistent,
-         "guide_bits": best.guide_bits, "candidates": rep.candidates, "invariant": bool(rep.invariant),
-         "best_ms": rep.best_ms,
-         "worst_ms": rep.worst_ms, "default_ms": rep.default_ms}
+         "guide_bits": best.guide_bits, "retire_batch": best.retire_batch, "candidates": rep.candidates,
+         "invariant": bool(rep.invariant), "best_ms": rep.best_ms, "worst_ms": rep.worst_ms,
+         "default_ms": rep.default_ms}
     if cache_path:
         cache[key] = e
         with open(cache_path, "w") as f:

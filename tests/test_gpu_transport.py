@@ -120,7 +120,8 @@ def test_launch_shape_invariance(ctx):
     ref = ctx.spectrum_batch([p])[0]
     for opts in (dict(block_size=256, blocks_per_cu=1, packets_per_item=4096, persistent=1),
                  dict(block_size=1024, packets_per_item=70_001, persistent=0),
-                 dict(block_size=512, blocks_per_cu=3, packets_per_item=100_000, persistent=1)):
+                 dict(block_size=512, blocks_per_cu=3, packets_per_item=100_000, persistent=1),
+                 dict(retire_batch=1), dict(retire_batch=64, block_size=256, packets_per_item=5000)):
         r = ctx.spectrum_batch([p], opts=opts)[0]
         assert np.array_equal(r["w_fx"], ref["w_fx"]) and np.array_equal(r["w2_fx"], ref["w2_fx"]), opts
         assert r["sinks_fx"] == ref["sinks_fx"], opts
@@ -183,9 +184,9 @@ def test_validation_errors(ctx):
         with pytest.raises(pdv.PdvError) as e:
             ctx.spectrum(_c1(**bad))
         assert e.value.code == -1
-    for gb in (10, 15):
+    for bad in (dict(guide_bits=10), dict(guide_bits=15), dict(retire_batch=65), dict(retire_batch=-1)):
         with pytest.raises(pdv.PdvError) as e:
-            ctx.spectrum_batch([_c1(n_packets=1000)], opts=dict(guide_bits=gb))
+            ctx.spectrum_batch([_c1(n_packets=1000)], opts=bad)
         assert e.value.code == -1
     # context stays usable after validation errors
     assert conservation_exact(ctx.spectrum(_c1(n_packets=1000)), 1000)
