@@ -377,6 +377,9 @@ typedef struct pdv_serve_stats {
     double p50_ms, p99_ms, mean_ms, max_ms;   /* latency: submission -> result on the host */
     double busy_s;                 /* scheduler time spent in table builds and launches */
     double wall_s;                 /* since pdv_serve_start */
+    double prepare_s, launch_s, collect_s;   /* scheduler time per phase: tables, launch + wait, result copies */
+    double spectrogram_s;          /* spectrogram worker time */
+    double queue_p50_ms;           /* median time from submission to admission */
 } pdv_serve_stats;
 
 /* Start the scheduler thread (opts nullable).  PDV_ESTATE if already serving. */

@@ -30,7 +30,7 @@ void launch_mie_coef(hipStream_t s, int n, int nmax, int nmx_max, double m_re, d
 void launch_mie_basis(hipStream_t s, int n, int nmax, int n_angles, const void* info, const void* a, const void* b,
                       double* basis);
 void launch_phase_cdf(hipStream_t s, int n_jobs, const void* jobs, int n_nodes, const void* info,
-                      const double* basis, uint8_t* tables, SetDesc* descs);
+                      const double* basis, uint8_t* tables, SetDesc* descs, int n_angles);
 void launch_zero_u64(hipStream_t s, uint64_t* p, uint64_t n);
 void launch_copy_desc_fields(hipStream_t s, SetDesc* descs, const int* src, int n);
 hipError_t plan_transport(TransportShape& sh, int precision, bool list, int want_bits, int lds_per_block,
@@ -43,7 +43,7 @@ int synth_chunk();
 size_t synth_frame_bytes();
 hipError_t launch_transport(hipStream_t s, int precision, bool list, const TransportShape& sh,
                             const SetDesc* descs, const uint8_t* tables, uint64_t* tallies, const WorkItem* items,
-                            int n_items, uint32_t* queue, int persistent, ListEntry* lists,
+                            int n_items, const int* n_items_dev, uint32_t* queue, int persistent, ListEntry* lists,
                             uint64_t* list_counts);
 }  // namespace pdv
 
@@ -250,7 +250,10 @@ extern "C" void pdv_destroy(pdv_ctx* ctx) {
 void pdv_ctx::release_all() {
     DevBuf* all[] = {&descs, &tables, &tallies, &items, &queue, &layer_jobs, &phase_jobs, &density, &lists,
                      &list_counts, &mie_info, &mie_a, &mie_b, &mie_d, &mie_basis, &mie_gx, &mie_gw, &sg_entries,
-                     &sg_offsets, &sg_signal, &sg_map, &sg_frames, &sg_partial, &sg_tab, &dup_src};
+                     &sg_offsets, &sg_signal, &sg_map, &sg_frames, &sg_partial, &sg_tab, &dup_src, &n_items_dev};
+    if (batch_gexec) (void)hipGraphExecDestroy(batch_gexec);
+    batch_gexec = nullptr;
+    batch_key = BatchGraphKey{};
     for (DevBuf* b : all) {
         if (b->ptr) (void)hipFree(b->ptr);
         b->ptr = nullptr;
@@ -536,7 +539,7 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
         if ((r = hip_check(H2D(phase_jobs.ptr, h_phase.data(), sizeof(PhaseJob) * h_phase.size()), "copy jobs")))
             return r;
         launch_phase_cdf(s, (int)h_phase.size(), phase_jobs.ptr, 0, nullptr, nullptr, (uint8_t*)tables.ptr,
-                         (SetDesc*)descs.ptr);
+                         (SetDesc*)descs.ptr, 0);
         if ((r = hip_check(hipStreamSynchronize(s), "table kernels"))) return r;
     }
     // Mie sets grouped by optics key (one cached basis at a time)
@@ -557,7 +560,7 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
         if ((r = hip_check(H2D(phase_jobs.ptr, h_phase.data(), sizeof(PhaseJob) * h_phase.size()), "copy jobs")))
             return r;
         launch_phase_cdf(s, (int)h_phase.size(), phase_jobs.ptr, mie_nodes, mie_info.ptr,
-                         (const double*)mie_basis.ptr, (uint8_t*)tables.ptr, (SetDesc*)descs.ptr);
+                         (const double*)mie_basis.ptr, (uint8_t*)tables.ptr, (SetDesc*)descs.ptr, mie_key.n_angles);
         if ((r = hip_check(hipStreamSynchronize(s), "mie phase kernels"))) return r;
     }
 
@@ -565,7 +568,6 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
 
     // ---- transport ----
     launch_zero_u64(s, (uint64_t*)tallies.ptr, tally_words_total);
-    launch_zero_u64(s, (uint64_t*)queue.ptr, 1);
     if (list_capacity) launch_zero_u64(s, (uint64_t*)list_counts.ptr, (uint64_t)n);
     TransportShape sh;
     sh.block = o.block_size;
@@ -587,13 +589,23 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
     last_items = n_items;
     last_guide_bits = sh.guide_bits;
     last_lds = sh.lds_bytes;
+    if (o.use_graph && n_items > 0) {
+        if ((r = ensure(n_items_dev, 256, "item count"))) return r;
+        h_n_items = n_items;
+        if ((r = hip_check(H2D(n_items_dev.ptr, &h_n_items, sizeof(int)), "copy item count"))) return r;
+    }
     if ((r = hip_check(hipEventRecord(ev_a, s), "event"))) return r;
     if (n_items > 0) {
-        hipError_t e = launch_transport(s, precision, list_capacity > 0, sh, (const SetDesc*)descs.ptr,
-                                        (const uint8_t*)tables.ptr, (uint64_t*)tallies.ptr,
-                                        (const WorkItem*)items.ptr, n_items, (uint32_t*)queue.ptr, o.persistent,
-                                        (ListEntry*)lists.ptr, (uint64_t*)list_counts.ptr);
-        if ((r = hip_check(e, "transport launch"))) return r;
+        if (o.use_graph) {
+            if ((r = launch_batch_graph(sh, precision, list_capacity > 0, o.persistent))) return r;
+        } else {
+            launch_zero_u64(s, (uint64_t*)queue.ptr, 1);
+            hipError_t e = launch_transport(s, precision, list_capacity > 0, sh, (const SetDesc*)descs.ptr,
+                                            (const uint8_t*)tables.ptr, (uint64_t*)tallies.ptr,
+                                            (const WorkItem*)items.ptr, n_items, nullptr, (uint32_t*)queue.ptr,
+                                            o.persistent, (ListEntry*)lists.ptr, (uint64_t*)list_counts.ptr);
+            if ((r = hip_check(e, "transport launch"))) return r;
+        }
     }
     if ((r = hip_check(hipEventRecord(ev_b, s), "event"))) return r;
 
@@ -612,6 +624,65 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
         for (int i = 0; i < n; ++i) unpack(sets[i], h_desc[i], h_tally.data() + h_desc[i].tally_offset, outs[i]);
     }
     return PDV_OK;
+}
+
+// The transport launch of a batch as a captured hipGraph: the queue reset
+// and the persistent launch, which reads the item count from device memory.
+// The graph is kept and replayed while the launch shape and the buffers it
+// points to stay the same; any change captures a new one.
+int pdv_ctx::launch_batch_graph(const TransportShape& sh, int precision, bool list, int persistent) {
+    BatchGraphKey k;
+    k.precision = precision;
+    k.list = list ? 1 : 0;
+    k.persistent = persistent;
+    k.grid = sh.grid;
+    k.block = sh.block;
+    k.lds = sh.lds_bytes;
+    k.guide_bits = sh.guide_bits;
+    k.retire_min = sh.retire_min;
+    k.max_layers = sh.max_layers;
+    k.max_cells = sh.max_cells;
+    k.max_bins = sh.max_bins;
+    k.ptr[0] = descs.ptr;
+    k.ptr[1] = tables.ptr;
+    k.ptr[2] = tallies.ptr;
+    k.ptr[3] = items.ptr;
+    k.ptr[4] = queue.ptr;
+    k.ptr[5] = list ? lists.ptr : nullptr;
+    k.ptr[6] = list ? list_counts.ptr : nullptr;
+    k.ptr[7] = n_items_dev.ptr;
+    int r;
+    if (!batch_gexec || !(k == batch_key)) {
+        if (batch_gexec) {
+            (void)hipGraphExecDestroy(batch_gexec);
+            batch_gexec = nullptr;
+        }
+        if ((r = hip_check(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal), "begin capture")))
+            return r;
+        launch_zero_u64(stream, (uint64_t*)queue.ptr, 1);
+        hipError_t e = launch_transport(stream, precision, list, sh, (const SetDesc*)descs.ptr,
+                                        (const uint8_t*)tables.ptr, (uint64_t*)tallies.ptr,
+                                        (const WorkItem*)items.ptr, 0, (const int*)n_items_dev.ptr,
+                                        (uint32_t*)queue.ptr, persistent, (ListEntry*)lists.ptr,
+                                        (uint64_t*)list_counts.ptr);
+        hipGraph_t g = nullptr;
+        hipError_t ec = hipStreamEndCapture(stream, &g);
+        if ((r = hip_check(e, "transport launch (capture)"))) {
+            if (g) (void)hipGraphDestroy(g);
+            return r;
+        }
+        if ((r = hip_check(ec, "end capture"))) return r;
+        hipError_t ei = hipGraphInstantiate(&batch_gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if ((r = hip_check(ei, "graph instantiate"))) {
+            batch_gexec = nullptr;
+            return r;
+        }
+        batch_key = k;
+        ++graph_captures;
+    }
+    ++graph_replays;
+    return hip_check(hipGraphLaunch(batch_gexec, stream), "graph launch");
 }
 
 void pdv_ctx::unpack(const pdv_params& p, const SetDesc& d, const uint64_t* t, pdv_spectrum_out& o) {

@@ -45,6 +45,22 @@ struct TunedLaunch {
     int32_t retire_batch = 0;
 };
 
+// What a captured batch graph was recorded with.
+struct BatchGraphKey {
+    int precision = -1, list = 0, persistent = 0, grid = 0, block = 0, lds = 0, guide_bits = 0, retire_min = 0;
+    int max_layers = 0, max_cells = 0, max_bins = 0;
+    void* ptr[8] = {};
+    bool operator==(const BatchGraphKey& o) const {
+        if (precision != o.precision || list != o.list || persistent != o.persistent || grid != o.grid ||
+            block != o.block || lds != o.lds || guide_bits != o.guide_bits || retire_min != o.retire_min ||
+            max_layers != o.max_layers || max_cells != o.max_cells || max_bins != o.max_bins)
+            return false;
+        for (int i = 0; i < 8; ++i)
+            if (ptr[i] != o.ptr[i]) return false;
+        return true;
+    }
+};
+
 struct ServeEngine;   // serving loop (serve.cpp)
 namespace pdv {
 int validate_params(pdv_ctx* ctx, const pdv_params* p);
@@ -67,6 +83,11 @@ struct pdv_ctx {
 
     // batch buffers
     DevBuf descs, tables, tallies, items, queue, layer_jobs, phase_jobs, density, lists, list_counts, dup_src;
+    DevBuf n_items_dev;                  // item count read by graph replays
+    int h_n_items = 0;
+    hipGraphExec_t batch_gexec = nullptr;
+    BatchGraphKey batch_key;
+    uint64_t graph_captures = 0, graph_replays = 0;
     // Mie basis cache
     DevBuf mie_info, mie_a, mie_b, mie_d, mie_basis, mie_gx, mie_gw;
     MieKey mie_key{};
@@ -107,6 +128,7 @@ struct pdv_ctx {
                    double wavelength, double fs, int n_samples);
     int stft(const float* d_signal, int n_samples, int nfft, int hop, int* n_windows);
     void unpack(const pdv_params& p, const pdv::SetDesc& d, const uint64_t* t, pdv_spectrum_out& o);
+    int launch_batch_graph(const pdv::TransportShape& sh, int precision, bool list, int persistent);
     void release_all();
     void shutdown_serving();
 };

@@ -64,6 +64,8 @@ template <> struct M<float> {
     // cos(2 pi r), sin(2 pi r) for |r| <= 1
     static __device__ __forceinline__ float cos_rev(float r) { return __builtin_amdgcn_cosf(r); }
     static __device__ __forceinline__ float sin_rev(float r) { return __builtin_amdgcn_sinf(r); }
+    // x clamped to [-1, 1] (one v_med3_f32)
+    static __device__ __forceinline__ float clamp1(float x) { return __builtin_amdgcn_fmed3f(x, -1.0f, 1.0f); }
 };
 
 template <> struct M<double> {
@@ -74,6 +76,7 @@ template <> struct M<double> {
     static __device__ __forceinline__ double div(double a, double b) { return a / b; }
     static __device__ __forceinline__ double cos_rev(double r) { return ::cos(2.0 * PI * r); }
     static __device__ __forceinline__ double sin_rev(double r) { return ::sin(2.0 * PI * r); }
+    static __device__ __forceinline__ double clamp1(double x) { return x > 1.0 ? 1.0 : (x < -1.0 ? -1.0 : x); }
 };
 
 template <typename Real>

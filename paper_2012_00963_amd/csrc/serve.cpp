@@ -11,10 +11,14 @@
 //      items of one persistent transport launch (replayed from a captured
 //      hipGraph when enabled),
 //   4. retires requests whose packets are all transported: copies their
-//      tallies to the caller's buffers, runs their spectrogram if asked,
-//      and stamps the latency (submission -> result on the host).
-// Requests that arrive while an iteration runs join the next one, so their
-// work overlaps on the device with older requests.  Tallies are integer sums
+//      tallies to the caller's buffers (one batched device-to-host copy per
+//      iteration) and stamps the latency (submission -> result on the host).
+// A request that also asks for a spectrogram is handed, once its spectrum
+// is done, to a spectrogram worker thread that owns a second context with
+// its own stream, so its frame transport, beat synthesis and STFT overlap
+// on the device with the scheduler's next iterations instead of stalling
+// them.  Requests that arrive while an iteration runs join the next one, so
+// their work overlaps on the device with older requests.  Tallies are integer sums
 // over the same (seed, stream, packet id) random streams whatever the slicing,
 // so a result is bitwise the same alone and in any mix.
 //
@@ -41,7 +45,7 @@ int validate_params(pdv_ctx* ctx, const pdv_params* p);
 void fill_desc(SetDesc& d, const pdv_params& p);
 void launch_layer_tables(hipStream_t s, int n_jobs, const void* jobs, const double* density, uint8_t* tables);
 void launch_phase_cdf(hipStream_t s, int n_jobs, const void* jobs, int n_nodes, const void* info,
-                      const double* basis, uint8_t* tables, SetDesc* descs);
+                      const double* basis, uint8_t* tables, SetDesc* descs, int n_angles);
 void launch_zero_u64(hipStream_t s, uint64_t* p, uint64_t n);
 hipError_t plan_transport(TransportShape& sh, int precision, bool list, int want_bits, int lds_per_block,
                           int lds_per_cu);
@@ -86,7 +90,8 @@ struct Executor {
     virtual int init() = 0;
     virtual int prepare(const std::vector<Req*>& admitted) = 0;
     virtual int run(const std::vector<WorkItem>& items) = 0;
-    virtual int collect(Req* r) = 0;
+    // copy the finished requests' results to their callers (st[i] per request)
+    virtual int collect(const std::vector<Req*>& done, std::vector<int>& st) = 0;
     virtual const char* error() const = 0;
 };
 
@@ -110,10 +115,21 @@ struct ServeEngine {
     uint64_t n_submitted = 0, n_completed = 0, n_failed = 0, n_cancelled = 0, n_iterations = 0;
     uint64_t n_packets = 0, n_events = 0;
     uint64_t n_admit_waits = 0;
-    std::vector<double> latencies_ms;
+    std::vector<double> latencies_ms, queue_ms;
     double t_start = 0, busy_s = 0;
+    double prepare_s = 0, launch_s = 0, collect_s = 0, sg_s = 0;
+    // spectrogram worker: its own context (device buffers, stream)
+    pdv_ctx* sg_ctx = nullptr;
+    std::deque<std::shared_ptr<Req>> sg_queue;
+    std::condition_variable cv_sg;
+    bool sg_stop = false;
+    std::thread sg_th;
 
     void loop();
+    void sg_loop();
+    void join_all();
+    // final status of a request (caller holds mu)
+    void finish(const std::shared_ptr<Req>& q, int st);
     uint64_t footprint(const Req& r) const;
     int active_bins(int slot) const;
 };
@@ -125,6 +141,10 @@ struct HipExecutor : Executor {
     DevBuf descs, tables, tallies, items, nitems, queue, layer_jobs, phase_jobs, density;
     WorkItem* h_items = nullptr;     // pinned staging for graph replays
     int* h_nitems = nullptr;
+    SetDesc* h_desc = nullptr;       // pinned staging: descriptors per slot (in and out)
+    LayerJob* h_lj = nullptr;        // pinned staging: layer jobs of one iteration
+    PhaseJob* h_pj = nullptr;        // pinned staging: phase jobs of one iteration
+    uint64_t* h_tally = nullptr;     // pinned staging: tally blocks per slot
     int max_items = 0;
     TransportShape shape;
     hipGraphExec_t gexec = nullptr;
@@ -141,8 +161,9 @@ struct HipExecutor : Executor {
                 (void)hipFree(b->ptr);
                 ctx->mem_used -= b->cap;
             }
-        if (h_items) (void)hipHostFree(h_items);
-        if (h_nitems) (void)hipHostFree(h_nitems);
+        void* pinned[] = {h_items, h_nitems, h_desc, h_lj, h_pj, h_tally};
+        for (void* h : pinned)
+            if (h) (void)hipHostFree(h);
     }
     const char* error() const override { return err.c_str(); }
     int hipfail(hipError_t e, const char* what) {
@@ -165,6 +186,14 @@ struct HipExecutor : Executor {
         if ((r = hipfail(hipHostMalloc((void**)&h_items, sizeof(WorkItem) * max_items, hipHostMallocDefault),
                          "pinned items"))) return r;
         if ((r = hipfail(hipHostMalloc((void**)&h_nitems, 256, hipHostMallocDefault), "pinned count"))) return r;
+        if ((r = hipfail(hipHostMalloc((void**)&h_desc, sizeof(SetDesc) * S, hipHostMallocDefault),
+                         "pinned descriptors"))) return r;
+        if ((r = hipfail(hipHostMalloc((void**)&h_lj, sizeof(LayerJob) * S, hipHostMallocDefault),
+                         "pinned layer jobs"))) return r;
+        if ((r = hipfail(hipHostMalloc((void**)&h_pj, sizeof(PhaseJob) * S, hipHostMallocDefault),
+                         "pinned phase jobs"))) return r;
+        if ((r = hipfail(hipHostMalloc((void**)&h_tally, 8ull * slot_tally_words(E->opts.max_bins) * S,
+                                       hipHostMallocDefault), "pinned tallies"))) return r;
         shape.block = 512;
         shape.grid = ctx->n_cu * 4;
         shape.max_layers = E->opts.max_layers;
@@ -178,82 +207,93 @@ struct HipExecutor : Executor {
         }
         return hipfail(e, "transport launch plan");
     }
+    // Tables of the newly admitted requests, all enqueued on the context
+    // stream from pinned staging; the transport launch that follows on the
+    // same stream sees them complete.
     int prepare(const std::vector<Req*>& adm) override {
         if (adm.empty()) return PDV_OK;
         hipStream_t s = ctx->stream;
-        std::vector<SetDesc> d(adm.size());
-        std::vector<LayerJob> lj(adm.size());
         std::vector<double> dens;
-        for (size_t i = 0; i < adm.size(); ++i) {
+        const int na = (int)adm.size();
+        for (int i = 0; i < na; ++i) {
             const Req* q = adm[i];
-            fill_desc(d[i], q->p);
-            d[i].tab_offset = (uint64_t)q->slot * TableLayout::BYTES;
-            d[i].tally_offset = (uint64_t)q->slot * slot_tally_words(E->opts.max_bins);
-            LayerJob& L = lj[i];
-            L = LayerJob{q->p.v_bottom, q->p.v_top, q->p.v0, q->p.tau_total, q->p.n_layers, q->p.density_kind,
-                         d[i].tab_offset, dens.size()};
+            SetDesc& d = h_desc[q->slot];
+            fill_desc(d, q->p);
+            d.tab_offset = (uint64_t)q->slot * TableLayout::BYTES;
+            d.tally_offset = (uint64_t)q->slot * slot_tally_words(E->opts.max_bins);
+            h_lj[i] = LayerJob{q->p.v_bottom, q->p.v_top, q->p.v0, q->p.tau_total, q->p.n_layers,
+                               q->p.density_kind, d.tab_offset, dens.size()};
             if (q->p.density_kind == PDV_DENSITY_TABLE) dens.insert(dens.end(), q->density.begin(), q->density.end());
         }
         int r;
         if ((r = ctx->ensure(density, 8 * std::max<size_t>(1, dens.size()), "serve density"))) return r;
-        for (size_t i = 0; i < adm.size(); ++i)
-            if ((r = hipfail(hipMemcpyAsync((SetDesc*)descs.ptr + adm[i]->slot, &d[i], sizeof(SetDesc),
-                                            hipMemcpyHostToDevice, s), "copy descriptor")))
+        for (int i = 0; i < na; ++i)
+            if ((r = hipfail(hipMemcpyAsync((SetDesc*)descs.ptr + adm[i]->slot, h_desc + adm[i]->slot,
+                                            sizeof(SetDesc), hipMemcpyHostToDevice, s), "copy descriptor")))
                 return r;
-        if ((r = hipfail(hipMemcpyAsync(layer_jobs.ptr, lj.data(), sizeof(LayerJob) * lj.size(),
-                                        hipMemcpyHostToDevice, s), "copy layer jobs")))
+        if ((r = hipfail(hipMemcpyAsync(layer_jobs.ptr, h_lj, sizeof(LayerJob) * na, hipMemcpyHostToDevice, s),
+                         "copy layer jobs")))
             return r;
-        if (!dens.empty())
-            if ((r = hipfail(hipMemcpyAsync(density.ptr, dens.data(), 8 * dens.size(), hipMemcpyHostToDevice, s),
+        if (!dens.empty()) {
+            // pageable source: the copy is staged before the call returns
+            if ((r = hipfail(hipMemcpy(density.ptr, dens.data(), 8 * dens.size(), hipMemcpyHostToDevice),
                              "copy densities")))
                 return r;
-        launch_layer_tables(s, (int)lj.size(), layer_jobs.ptr, (const double*)density.ptr, (uint8_t*)tables.ptr);
-        // phase tables: caller tables, then Mie sets grouped by optics key
-        std::vector<PhaseJob> pj;
-        for (const Req* q : adm) {
-            if (q->p.phase_kind != PDV_PHASE_TABLE) continue;
-            uint8_t* dst = (uint8_t*)tables.ptr + (uint64_t)q->slot * TableLayout::BYTES + TableLayout::PHASE;
-            if ((r = hipfail(hipMemcpyAsync(dst, q->phase.data(), 8 * q->phase.size(), hipMemcpyHostToDevice, s),
-                             "copy phase table")))
-                return r;
-            pj.push_back(PhaseJob{1, q->p.n_angles, 0.0, 0.0, (uint64_t)q->slot * TableLayout::BYTES, q->slot, 0});
         }
-        if (!pj.empty()) {
-            if ((r = hipfail(hipMemcpyAsync(phase_jobs.ptr, pj.data(), sizeof(PhaseJob) * pj.size(),
-                                            hipMemcpyHostToDevice, s), "copy phase jobs")))
-                return r;
-            launch_phase_cdf(s, (int)pj.size(), phase_jobs.ptr, 0, nullptr, nullptr, (uint8_t*)tables.ptr,
-                             (SetDesc*)descs.ptr);
-            if ((r = hipfail(hipStreamSynchronize(s), "phase tables"))) return r;
+        launch_layer_tables(s, na, layer_jobs.ptr, (const double*)density.ptr, (uint8_t*)tables.ptr);
+        // phase tables: caller tables, then Mie sets grouped by optics key;
+        // every group's jobs sit in their own range of the staging and device
+        // job arrays, so no group waits for the previous one
+        int n_pj = 0;
+        {
+            const int g0 = n_pj;
+            for (const Req* q : adm) {
+                if (q->p.phase_kind != PDV_PHASE_TABLE) continue;
+                uint8_t* dst = (uint8_t*)tables.ptr + (uint64_t)q->slot * TableLayout::BYTES + TableLayout::PHASE;
+                if ((r = hipfail(hipMemcpy(dst, q->phase.data(), 8 * q->phase.size(), hipMemcpyHostToDevice),
+                                 "copy phase table")))
+                    return r;
+                h_pj[n_pj++] = PhaseJob{1, q->p.n_angles, 0.0, 0.0, (uint64_t)q->slot * TableLayout::BYTES,
+                                        q->slot, 0};
+            }
+            if ((r = launch_phase_group(s, g0, n_pj - g0, 0, nullptr, nullptr))) return r;
         }
-        std::vector<char> done(adm.size(), 0);
-        for (size_t i = 0; i < adm.size(); ++i) {
+        std::vector<char> done(na, 0);
+        for (int i = 0; i < na; ++i) {
             if (adm[i]->p.phase_kind != PDV_PHASE_MIE || done[i]) continue;
             if ((r = ctx->ensure_mie_basis(adm[i]->p))) {
                 err = ctx->err;
                 return r;
             }
-            pj.clear();
-            for (size_t j = i; j < adm.size(); ++j) {
+            const int g0 = n_pj;
+            for (int j = i; j < na; ++j) {
                 const pdv_params& p = adm[j]->p;
                 if (p.phase_kind != PDV_PHASE_MIE || done[j]) continue;
                 MieKey k{p.m_re, p.m_im, p.wavelength, p.d_min, p.d_max, p.n_size_nodes, p.n_angles};
                 if (!(k == ctx->mie_key)) continue;
-                pj.push_back(PhaseJob{0, p.n_angles, p.d_median, p.sigma_ln,
-                                      (uint64_t)adm[j]->slot * TableLayout::BYTES, adm[j]->slot, 0});
+                h_pj[n_pj++] = PhaseJob{0, p.n_angles, p.d_median, p.sigma_ln,
+                                        (uint64_t)adm[j]->slot * TableLayout::BYTES, adm[j]->slot, 0};
                 done[j] = 1;
             }
-            if ((r = hipfail(hipMemcpyAsync(phase_jobs.ptr, pj.data(), sizeof(PhaseJob) * pj.size(),
-                                            hipMemcpyHostToDevice, s), "copy phase jobs")))
+            if ((r = launch_phase_group(s, g0, n_pj - g0, ctx->mie_nodes, ctx->mie_info.ptr,
+                                        (const double*)ctx->mie_basis.ptr)))
                 return r;
-            launch_phase_cdf(s, (int)pj.size(), phase_jobs.ptr, ctx->mie_nodes, ctx->mie_info.ptr,
-                             (const double*)ctx->mie_basis.ptr, (uint8_t*)tables.ptr, (SetDesc*)descs.ptr);
-            if ((r = hipfail(hipStreamSynchronize(s), "mie phase tables"))) return r;
         }
         for (const Req* q : adm)
             launch_zero_u64(s, (uint64_t*)tallies.ptr + (uint64_t)q->slot * slot_tally_words(E->opts.max_bins),
                             slot_tally_words(E->opts.max_bins));
         return hipfail(hipGetLastError(), "table kernels");
+    }
+    int launch_phase_group(hipStream_t s, int first, int n, int n_nodes, const void* info, const double* basis) {
+        if (n <= 0) return PDV_OK;
+        PhaseJob* dj = (PhaseJob*)phase_jobs.ptr + first;
+        int r;
+        if ((r = hipfail(hipMemcpyAsync(dj, h_pj + first, sizeof(PhaseJob) * n, hipMemcpyHostToDevice, s),
+                         "copy phase jobs")))
+            return r;
+        launch_phase_cdf(s, n, dj, n_nodes, info, basis, (uint8_t*)tables.ptr, (SetDesc*)descs.ptr,
+                         h_pj[first].n_angles);
+        return PDV_OK;
     }
     int record(hipStream_t s) {
         hipError_t e;
@@ -290,25 +330,26 @@ struct HipExecutor : Executor {
         }
         return hipfail(hipStreamSynchronize(s), "transport");
     }
-    int collect(Req* q) override {
-        const int nb = q->p.n_bins;
-        std::vector<uint64_t> t(tally_words(nb));
-        const uint64_t* src = (const uint64_t*)tallies.ptr + (uint64_t)q->slot * slot_tally_words(E->opts.max_bins);
+    int collect(const std::vector<Req*>& done, std::vector<int>& st) override {
+        hipStream_t s = ctx->stream;
+        const uint64_t words = slot_tally_words(E->opts.max_bins);
         int r;
-        if ((r = hipfail(hipMemcpy(t.data(), src, 8 * t.size(), hipMemcpyDeviceToHost), "copy tallies"))) return r;
-        SetDesc d;
-        if ((r = hipfail(hipMemcpy(&d, (SetDesc*)descs.ptr + q->slot, sizeof d, hipMemcpyDeviceToHost),
-                         "copy descriptor")))
-            return r;
-        // the slot's tally block has the request's own n_bins layout
-        ctx->unpack(q->p, d, t.data(), *q->out);
-        if (q->want_sg) {
-            int rc = pdv_spectrogram_internal(ctx, &q->p, &q->sg, q->sg_out);
-            if (rc != PDV_OK && rc != PDV_EOVERFLOW) {
-                err = ctx->err;
-                return rc;
-            }
-            if (rc == PDV_EOVERFLOW) return PDV_EOVERFLOW;
+        for (Req* q : done) {
+            const uint64_t off = (uint64_t)q->slot * words;
+            if ((r = hipfail(hipMemcpyAsync(h_tally + off, (const uint64_t*)tallies.ptr + off,
+                                            8 * tally_words(q->p.n_bins), hipMemcpyDeviceToHost, s),
+                             "copy tallies")))
+                return r;
+            if ((r = hipfail(hipMemcpyAsync(h_desc + q->slot, (const SetDesc*)descs.ptr + q->slot, sizeof(SetDesc),
+                                            hipMemcpyDeviceToHost, s), "copy descriptor")))
+                return r;
+        }
+        if ((r = hipfail(hipStreamSynchronize(s), "copy results"))) return r;
+        st.assign(done.size(), PDV_OK);
+        for (size_t i = 0; i < done.size(); ++i) {
+            Req* q = done[i];
+            // the slot's tally block has the request's own n_bins layout
+            ctx->unpack(q->p, h_desc[q->slot], h_tally + (uint64_t)q->slot * words, *q->out);
         }
         return PDV_OK;
     }
@@ -350,12 +391,15 @@ struct HostExecutor : Executor {
             std::this_thread::sleep_for(std::chrono::nanoseconds((uint64_t)(E->opts.host_ns_per_packet * pk)));
         return PDV_OK;
     }
-    int collect(Req* q) override {
-        SetDesc d;
-        std::memset(&d, 0, sizeof d);
-        d.albedo = q->p.albedo;
-        d.g_mean = q->p.hg_g;
-        E->ctx->unpack(q->p, d, slots[q->slot].data(), *q->out);
+    int collect(const std::vector<Req*>& done, std::vector<int>& st) override {
+        st.assign(done.size(), PDV_OK);
+        for (Req* q : done) {
+            SetDesc d;
+            std::memset(&d, 0, sizeof d);
+            d.albedo = q->p.albedo;
+            d.g_mean = q->p.hg_g;
+            E->ctx->unpack(q->p, d, slots[q->slot].data(), *q->out);
+        }
         return PDV_OK;
     }
 };
@@ -405,6 +449,7 @@ void ServeEngine::loop() {
                 q->footprint = fp;
                 mem_in_use += fp;
                 q->t_admit = now_s();
+                queue_ms.push_back((q->t_admit - q->t_submit) * 1e3);
                 active.push_back(q);
                 admitted.push_back(q.get());
             }
@@ -424,6 +469,7 @@ void ServeEngine::loop() {
         }
         const double t0 = now_s();
         int rc = exec->prepare(admitted);
+        const double t_prep = now_s();
         std::vector<WorkItem> items;
         if (rc == PDV_OK) {
             std::unique_lock<std::mutex> lk(mu);
@@ -444,39 +490,46 @@ void ServeEngine::loop() {
             }
         }
         if (rc == PDV_OK) rc = exec->run(items);
-        busy_s += now_s() - t0;
+        const double t_run = now_s();
+        busy_s += t_run - t0;
+        prepare_s += t_prep - t0;
+        launch_s += t_run - t_prep;
         ++n_iterations;
-        // retire finished requests
+        // retire finished requests: one batched copy of their results
         std::vector<std::shared_ptr<Req>> done_now;
         {
             std::unique_lock<std::mutex> lk(mu);
             for (auto& q : active)
                 if (rc != PDV_OK || q->cancel || q->issued >= q->p.n_packets) done_now.push_back(q);
         }
-        for (auto& q : done_now) {
-            int st = rc;
-            if (st == PDV_OK && q->cancel) st = PDV_ECANCELLED;
-            if (st == PDV_OK) st = exec->collect(q.get());
+        std::vector<Req*> to_copy;
+        for (auto& q : done_now)
+            if (rc == PDV_OK && !q->cancel) to_copy.push_back(q.get());
+        std::vector<int> cst;
+        if (rc == PDV_OK && !to_copy.empty()) rc = exec->collect(to_copy, cst);
+        collect_s += now_s() - t_run;
+        bool handed = false;
+        {
             std::unique_lock<std::mutex> lk(mu);
-            if (st != PDV_OK && st != PDV_EOVERFLOW && st != PDV_ECANCELLED && fail_msg.empty())
-                fail_msg = exec->error();
-            q->t_done = now_s();
-            if (st == PDV_OK || st == PDV_EOVERFLOW) {
-                ++n_completed;
-                latencies_ms.push_back((q->t_done - q->t_submit) * 1e3);
-                n_packets += q->out->counters.packets;
-                n_events += q->out->counters.collisions + q->out->counters.surface;
-            } else if (st == PDV_ECANCELLED) {
-                ++n_cancelled;
-            } else {
-                ++n_failed;
+            if (rc != PDV_OK && fail_msg.empty()) fail_msg = exec->error();
+            size_t ci = 0;
+            for (auto& q : done_now) {
+                int st = rc;
+                if (st == PDV_OK && q->cancel) st = PDV_ECANCELLED;
+                if (st == PDV_OK) st = cst[ci++];
+                // the slot is free once the spectrum is out
+                free_slots.push_back(q->slot);
+                active.erase(std::find(active.begin(), active.end(), q));
+                if (st == PDV_OK && q->want_sg) {
+                    sg_queue.push_back(q);          // finished by the spectrogram worker
+                    handed = true;
+                    continue;
+                }
+                finish(q, st);
             }
-            q->status = st;
-            free_slots.push_back(q->slot);
-            mem_in_use -= q->footprint;
-            active.erase(std::find(active.begin(), active.end(), q));
             cv_done.notify_all();
         }
+        if (handed) cv_sg.notify_one();
         if (rc != PDV_OK) {
             // the device failed: every waiting request fails the same way
             std::unique_lock<std::mutex> lk(mu);
@@ -492,6 +545,65 @@ void ServeEngine::loop() {
     }
 }
 
+void ServeEngine::finish(const std::shared_ptr<Req>& q, int st) {
+    q->t_done = now_s();
+    if (st == PDV_OK || st == PDV_EOVERFLOW) {
+        ++n_completed;
+        latencies_ms.push_back((q->t_done - q->t_submit) * 1e3);
+        n_packets += q->out->counters.packets;
+        n_events += q->out->counters.collisions + q->out->counters.surface;
+    } else if (st == PDV_ECANCELLED) {
+        ++n_cancelled;
+    } else {
+        ++n_failed;
+    }
+    q->status = st;
+    mem_in_use -= q->footprint;
+}
+
+// Spectrogram worker: frames, beat synthesis and STFT of requests whose
+// spectrum is done, on the worker's own context and stream.
+void ServeEngine::sg_loop() {
+    for (;;) {
+        std::shared_ptr<Req> q;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv_sg.wait(lk, [&] { return sg_stop || !sg_queue.empty(); });
+            if (sg_queue.empty()) return;
+            q = sg_queue.front();
+            sg_queue.pop_front();
+            if (q->cancel || (sg_stop && !drain)) {
+                finish(q, PDV_ECANCELLED);
+                cv_done.notify_all();
+                continue;
+            }
+        }
+        const double t0 = now_s();
+        const int st = pdv_spectrogram_internal(sg_ctx, &q->p, &q->sg, q->sg_out);
+        std::unique_lock<std::mutex> lk(mu);
+        sg_s += now_s() - t0;
+        if (st != PDV_OK && st != PDV_EOVERFLOW && fail_msg.empty()) fail_msg = pdv_last_error(sg_ctx);
+        finish(q, st);
+        cv_done.notify_all();
+    }
+}
+
+// Stop the scheduler, then let the spectrogram worker finish (drain) or
+// cancel what it still holds, and release its context.
+void ServeEngine::join_all() {
+    if (th.joinable()) th.join();
+    {
+        std::unique_lock<std::mutex> lk(mu);
+        sg_stop = true;
+    }
+    cv_sg.notify_all();
+    if (sg_th.joinable()) sg_th.join();
+    if (sg_ctx) {
+        pdv_destroy(sg_ctx);
+        sg_ctx = nullptr;
+    }
+}
+
 void pdv_ctx::shutdown_serving() {
     if (!serve) return;
     {
@@ -500,7 +612,7 @@ void pdv_ctx::shutdown_serving() {
         serve->drain = false;
     }
     serve->cv_work.notify_all();
-    if (serve->th.joinable()) serve->th.join();
+    serve->join_all();
     serve.reset();
 }
 
@@ -546,10 +658,21 @@ extern "C" int pdv_serve_start(pdv_ctx* ctx, const pdv_serve_opts* o) {
         if (msg.empty()) msg = ctx->err;
         return ctx->fail(r, "serving executor: %s", msg.c_str());
     }
+    if (opts.executor == PDV_EXEC_HIP) {
+        // the spectrogram worker's own context: buffers, Mie basis and stream
+        const int r = pdv_create(&E->sg_ctx, ctx->device, opts.mem_budget, nullptr);
+        if (r != PDV_OK) {
+            std::string msg = E->sg_ctx ? pdv_last_error(E->sg_ctx) : "pdv_create failed";
+            if (E->sg_ctx) pdv_destroy(E->sg_ctx);
+            E->sg_ctx = nullptr;
+            return ctx->fail(r, "serving spectrogram context: %s", msg.c_str());
+        }
+    }
     E->t_start = now_s();
     ServeEngine* raw = E.get();
     ctx->serve = std::move(E);
     raw->th = std::thread([raw] { raw->loop(); });
+    if (raw->sg_ctx) raw->sg_th = std::thread([raw] { raw->sg_loop(); });
     return PDV_OK;
 }
 
@@ -646,21 +769,31 @@ extern "C" int pdv_serve_report(pdv_ctx* ctx, pdv_serve_stats* s) {
     s->mem_in_use = E->mem_in_use;
     s->busy_s = E->busy_s;
     s->wall_s = now_s() - E->t_start;
+    s->prepare_s = E->prepare_s;
+    s->launch_s = E->launch_s;
+    s->collect_s = E->collect_s;
+    s->spectrogram_s = E->sg_s;
+    // linear-interpolated percentile of a sorted sample
+    auto pct = [](const std::vector<double>& l, double q) {
+        const double pos = q * (double)(l.size() - 1);
+        const size_t i = (size_t)pos;
+        const double f = pos - (double)i;
+        return i + 1 < l.size() ? l[i] * (1.0 - f) + l[i + 1] * f : l[i];
+    };
     std::vector<double> l = E->latencies_ms;
     if (!l.empty()) {
         std::sort(l.begin(), l.end());
-        auto pct = [&](double q) {
-            const double pos = q * (double)(l.size() - 1);
-            const size_t i = (size_t)pos;
-            const double f = pos - (double)i;
-            return i + 1 < l.size() ? l[i] * (1.0 - f) + l[i + 1] * f : l[i];
-        };
-        s->p50_ms = pct(0.50);
-        s->p99_ms = pct(0.99);
+        s->p50_ms = pct(l, 0.50);
+        s->p99_ms = pct(l, 0.99);
         s->max_ms = l.back();
         double sum = 0;
         for (double v : l) sum += v;
         s->mean_ms = sum / (double)l.size();
+    }
+    std::vector<double> w = E->queue_ms;
+    if (!w.empty()) {
+        std::sort(w.begin(), w.end());
+        s->queue_p50_ms = pct(w, 0.50);
     }
     return PDV_OK;
 }
@@ -675,7 +808,7 @@ extern "C" int pdv_serve_stop(pdv_ctx* ctx, int32_t drain) {
         E->drain = drain != 0;
     }
     E->cv_work.notify_all();
-    if (E->th.joinable()) E->th.join();
+    E->join_all();
     const bool failed = E->failed;
     std::string msg = E->fail_msg;
     ctx->serve.reset();

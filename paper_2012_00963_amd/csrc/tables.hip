@@ -53,6 +53,21 @@ __device__ __forceinline__ double cabs2(Cplx a) { return a.re * a.re + a.im * a.
 // Layer table: one block per set.
 // --------------------------------------------------------------------------
 
+// Depth of guide point i, and the first guide point at or below depth T
+// (the smallest i in [0, G+1] with tau i / G >= T), found from an estimate
+// and corrected with the same expression.
+__device__ __forceinline__ double guide_depth(double tau, int i) {
+    return tau * (double)i / (double)LAYER_GUIDE;
+}
+__device__ int first_cell_at_or_above(double tau, double T) {
+    if (!(tau > 0.0)) return T <= 0.0 ? 0 : LAYER_GUIDE + 1;
+    double e = ceil(T / tau * (double)LAYER_GUIDE);
+    int i = e < 0.0 ? 0 : (e > (double)(LAYER_GUIDE + 1) ? LAYER_GUIDE + 1 : (int)e);
+    while (i > 0 && guide_depth(tau, i - 1) >= T) --i;
+    while (i <= LAYER_GUIDE && guide_depth(tau, i) < T) ++i;
+    return i;
+}
+
 __global__ void __launch_bounds__(1024)
 layer_table_kernel(const LayerJob* __restrict__ jobs, const double* __restrict__ density, uint8_t* tables) {
     const LayerJob J = jobs[blockIdx.x];
@@ -105,15 +120,12 @@ layer_table_kernel(const LayerJob* __restrict__ jobs, const double* __restrict__
     }
     if (tid == 0) { T64[0] = 0.0; T32[0] = 0.0f; }
     __syncthreads();
-    // guide over uniform depth cells
-    for (int i = tid; i <= LAYER_GUIDE; i += nt) {
-        const double t = J.tau_total * (double)i / (double)LAYER_GUIDE;
-        int lo = 0, hi = n - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_mass[mid - 1] <= t) lo = mid; else hi = mid - 1;
-        }
-        lg[i] = (uint16_t)lo;
+    // guide over uniform depth cells: lg[i] = last layer j with T[j] <= t_i,
+    // t_i = tau i / G; every layer writes the entries whose t_i falls inside it
+    for (int j = tid; j < n; j += nt) {
+        const int lo = first_cell_at_or_above(J.tau_total, j == 0 ? 0.0 : s_mass[j - 1]);
+        const int hi = j + 1 < n ? first_cell_at_or_above(J.tau_total, s_mass[j]) : LAYER_GUIDE + 1;
+        for (int i = lo; i < hi; ++i) lg[i] = (uint16_t)j;
     }
 }
 
@@ -278,61 +290,102 @@ __device__ double block_sum(double v, double* sh) {
     return r;
 }
 
-__global__ void __launch_bounds__(1024)
-phase_cdf_kernel(const PhaseJob* __restrict__ jobs, int n_nodes, const MieNodeInfo* __restrict__ info,
+// Size-averaged Mie intensity of a group of jobs (one optics key, so one
+// basis and one angle count): the (jobs x nodes) log-normal weights times
+// the (nodes x angles) basis.  A block takes 256 angles of PH_JT jobs, so
+// every basis element it reads serves PH_JT jobs; each (job, angle) sum runs
+// over the nodes in order.  The blocks of the first angle range also form
+// the size-averaged albedo <C_sca>/<C_ext> of their jobs (eq. 11).
+constexpr int PH_JT = 8;      // jobs per block
+constexpr int PH_NC = 256;    // nodes per weight chunk in LDS
+
+__global__ void __launch_bounds__(256)
+mie_phase_kernel(const PhaseJob* __restrict__ jobs, int n_jobs, int n_nodes, const MieNodeInfo* __restrict__ info,
                  const double* __restrict__ basis, uint8_t* tables, SetDesc* descs) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int g0 = blockIdx.y * PH_JT;
+    const int nj = min(PH_JT, n_jobs - g0);
+    const int na = jobs[g0].n_angles;
+    const int j = blockIdx.x * nt + tid;
+    __shared__ double s_w[PH_JT][PH_NC];
+    __shared__ double s_lnm[PH_JT], s_sig[PH_JT];
+    __shared__ double s_red[256];
+    if (tid < PH_JT) {
+        s_lnm[tid] = tid < nj ? log(jobs[g0 + tid].d_median) : 0.0;
+        s_sig[tid] = tid < nj ? jobs[g0 + tid].sigma_ln : 1.0;
+    }
+    double acc[PH_JT];
+#pragma unroll
+    for (int t = 0; t < PH_JT; ++t) acc[t] = 0.0;
+    for (int c0 = 0; c0 < n_nodes; c0 += PH_NC) {
+        const int cn = min(PH_NC, n_nodes - c0);
+        __syncthreads();
+        // number weights of the truncated log-normal (eq. 21) on the ln d nodes
+        for (int e = tid; e < PH_JT * PH_NC; e += nt) {
+            const int t = e / PH_NC, i = e % PH_NC;
+            double q = 0.0;
+            if (t < nj && i < cn) {
+                const MieNodeInfo I = info[c0 + i];
+                const double z = (I.lnd - s_lnm[t]) / s_sig[t];
+                q = I.wq * exp(-0.5 * z * z) / (2.5066282746310002 * s_sig[t]);
+            }
+            s_w[t][i] = q;
+        }
+        __syncthreads();
+        if (j < na) {
+            for (int i = 0; i < cn; ++i) {
+                const double b = basis[(uint64_t)(c0 + i) * na + j];
+#pragma unroll
+                for (int t = 0; t < PH_JT; ++t) acc[t] += s_w[t][i] * b;
+            }
+        }
+    }
+    if (j < na) {
+        for (int t = 0; t < nj; ++t) {
+            double* phase = (double*)(tables + jobs[g0 + t].tab_offset + TableLayout::PHASE);
+            phase[j] = acc[t];
+        }
+    }
+    if (blockIdx.x != 0) return;
+    for (int t = 0; t < nj; ++t) {
+        double sca = 0.0, ext = 0.0;
+        for (int i = tid; i < n_nodes; i += nt) {
+            const MieNodeInfo I = info[i];
+            const double z = (I.lnd - s_lnm[t]) / s_sig[t];
+            const double q = I.wq * exp(-0.5 * z * z) / (2.5066282746310002 * s_sig[t]);
+            const double x2 = I.x * I.x;
+            sca += q * x2 * I.q_sca;
+            ext += q * x2 * I.q_ext;
+        }
+        sca = block_sum(sca, s_red);
+        ext = block_sum(ext, s_red);
+        if (tid == 0) {
+            SetDesc& d = descs[jobs[g0 + t].set];
+            const double alb = sca / ext;
+            d.albedo = alb;
+            d.albedo_one = alb >= 1.0;
+            const double th = floor(alb * 4294967296.0);
+            d.thr_albedo = (uint32_t)(th > 4294967295.0 ? 4294967295.0 : (th < 0.0 ? 0.0 : th));
+        }
+    }
+}
+
+__global__ void __launch_bounds__(1024)
+phase_cdf_kernel(const PhaseJob* __restrict__ jobs, uint8_t* tables, SetDesc* descs) {
     const PhaseJob J = jobs[blockIdx.x];
     uint8_t* tb = tables + J.tab_offset;
     double* phase = (double*)(tb + TableLayout::PHASE);
     uint32_t* C = (uint32_t*)(tb + TableLayout::CDF);
     uint16_t* cg = (uint16_t*)(tb + TableLayout::CGUIDE);
-    __shared__ double s_w[1024];
     __shared__ double s_red[1024];
     __shared__ double s_cell[MAX_ANGLES];
-    __shared__ float s_dummy;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int na = J.n_angles, nc = na - 1;
     SetDesc& d = descs[J.set];
     double* s_ph = s_cell;       // phase values staged here, then replaced by cell masses
-    (void)s_dummy;
-    if (J.kind == 1) {
-        for (int j = tid; j < na; j += nt) s_ph[j] = phase[j];
-    }
-
-    if (J.kind == 0) {
-        // number weights of the truncated log-normal (eq. 21) on the ln d nodes
-        double sca = 0.0, ext = 0.0, gsum = 0.0;
-        const double lnm = log(J.d_median);
-        for (int i = tid; i < n_nodes; i += nt) {
-            const MieNodeInfo I = info[i];
-            const double z = (I.lnd - lnm) / J.sigma_ln;
-            const double q = I.wq * exp(-0.5 * z * z) / (2.5066282746310002 * J.sigma_ln);
-            s_w[i] = q;
-            const double x2 = I.x * I.x;
-            sca += q * x2 * I.q_sca;
-            ext += q * x2 * I.q_ext;
-            gsum += q * x2 * I.q_sca * I.g;
-        }
-        __syncthreads();
-        sca = block_sum(sca, s_red);
-        ext = block_sum(ext, s_red);
-        gsum = block_sum(gsum, s_red);
-        for (int j = tid; j < na; j += nt) {
-            // basis is node-major: consecutive threads read consecutive angles
-            double acc = 0.0;
-            for (int i = 0; i < n_nodes; ++i) acc += s_w[i] * basis[(uint64_t)i * na + j];
-            phase[j] = acc;
-            s_ph[j] = acc;
-        }
-        if (tid == 0) {
-            const double alb = sca / ext;
-            d.albedo = alb;
-            d.albedo_one = alb >= 1.0;
-            const double t = floor(alb * 4294967296.0);
-            d.thr_albedo = (uint32_t)(t > 4294967295.0 ? 4294967295.0 : (t < 0.0 ? 0.0 : t));
-        }
-        __syncthreads();
-    }
+    // the phase function sits in the table (caller table, or written by
+    // mie_phase_kernel)
+    for (int j = tid; j < na; j += nt) s_ph[j] = phase[j];
     __syncthreads();
     // trapezoid cell masses of p sin(theta): q_j = p_j sin(theta_j) first
     double qv[4];
@@ -384,15 +437,15 @@ phase_cdf_kernel(const PhaseJob* __restrict__ jobs, int n_nodes, const MieNodeIn
         gpart += (cn - cj) / 4294967296.0 * (sin(th1) - sin(th0)) / dth;
     }
     gpart = block_sum(gpart, s_red);
-    // guide: last cell with C[j] <= i 2^(32 - GUIDE_BITS)
-    for (int i = tid; i <= CDF_GUIDE; i += nt) {
-        const uint64_t key = (uint64_t)i << (32 - GUIDE_BITS);
-        int lo = 0, hi = nc - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if ((uint64_t)s_C[mid] <= key) lo = mid; else hi = mid - 1;
-        }
-        cg[i] = (uint16_t)lo;
+    // guide: cg[i] = last cell j with C[j] <= i 2^(32 - GUIDE_BITS); every
+    // cell writes the entries whose key falls inside it (C is non-decreasing,
+    // an empty cell's range is empty and the next cell takes the entries)
+    constexpr int SH = 32 - GUIDE_BITS;
+    constexpr uint64_t RND = (1ull << SH) - 1ull;
+    for (int j = tid; j < nc; j += nt) {
+        const uint64_t lo = ((uint64_t)s_C[j] + RND) >> SH;
+        const uint64_t hi = j + 1 < nc ? (((uint64_t)s_C[j + 1] + RND) >> SH) : (uint64_t)CDF_GUIDE + 1ull;
+        for (uint64_t i = lo; i < hi; ++i) cg[i] = (uint16_t)j;
     }
     if (tid == 0) d.g_mean = gpart;
 }
@@ -447,11 +500,18 @@ void launch_mie_basis(hipStream_t s, int n, int nmax, int n_angles, const void* 
                        (const MieNodeInfo*)info, (const Cplx*)a, (const Cplx*)b, basis);
 }
 
+// Phase tables of n_jobs jobs: Mie jobs (basis != nullptr; all of one
+// optics key) get their size-averaged phase function and albedo first, then
+// every job its integer CDF, guide and mean cosine.
 void launch_phase_cdf(hipStream_t s, int n_jobs, const void* jobs, int n_nodes, const void* info,
-                      const double* basis, uint8_t* tables, SetDesc* descs) {
+                      const double* basis, uint8_t* tables, SetDesc* descs, int n_angles) {
     if (n_jobs <= 0) return;
-    hipLaunchKernelGGL(phase_cdf_kernel, dim3(n_jobs), dim3(1024), 0, s, (const PhaseJob*)jobs, n_nodes,
-                       (const MieNodeInfo*)info, basis, tables, descs);
+    if (basis) {
+        const dim3 grid((unsigned)((n_angles + 255) / 256), (unsigned)((n_jobs + PH_JT - 1) / PH_JT));
+        hipLaunchKernelGGL(mie_phase_kernel, grid, dim3(256), 0, s, (const PhaseJob*)jobs, n_jobs, n_nodes,
+                           (const MieNodeInfo*)info, basis, tables, descs);
+    }
+    hipLaunchKernelGGL(phase_cdf_kernel, dim3(n_jobs), dim3(1024), 0, s, (const PhaseJob*)jobs, tables, descs);
 }
 
 void launch_copy_desc_fields(hipStream_t s, SetDesc* descs, const int* src, int n) {

@@ -201,7 +201,7 @@ __device__ __forceinline__ void hg_angle(const SetConst<Real>& c, Real u, Real& 
         if constexpr (sizeof(Real) == 4) x = (c.hg_a - q * q) * c.hg_inv2g;
         else x = (c.hg_a - q * q) / c.hg_c1;
     }
-    x = x > (Real)1.0 ? (Real)1.0 : (x < (Real)-1.0 ? (Real)-1.0 : x);
+    x = M<Real>::clamp1(x);
     ct = x;
     const Real s2 = ((Real)1.0 - x) * ((Real)1.0 + x);
     st = M<Real>::sqrt(s2 > (Real)0.0 ? s2 : (Real)0.0);
@@ -457,7 +457,7 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                 const Real cphi = M<Real>::cos_rev(u2);
                 const Real sm2 = ((Real)1.0 - mu) * ((Real)1.0 + mu);
                 Real m2 = mu * ct + M<Real>::sqrt(sm2 > (Real)0 ? sm2 : (Real)0) * st_ * cphi;
-                m2 = m2 > (Real)1.0 ? (Real)1.0 : (m2 < (Real)-1.0 ? (Real)-1.0 : m2);
+                m2 = M<Real>::clamp1(m2);
                 mu_c = m2;
                 omc_c = (Real)1.0 - m2;
             }
@@ -589,19 +589,21 @@ hipError_t launch_transport_dev(hipStream_t s, int precision, const TransportSha
                                     nullptr);
 }
 
+// n_items_dev (nullable): read the item count from device memory instead of
+// n_items, so a captured graph can be replayed for another item list.
 hipError_t launch_transport(hipStream_t s, int precision, bool list, const TransportShape& sh,
                             const SetDesc* descs, const uint8_t* tables, uint64_t* tallies, const WorkItem* items,
-                            int n_items, uint32_t* queue, int persistent, ListEntry* lists,
+                            int n_items, const int* n_items_dev, uint32_t* queue, int persistent, ListEntry* lists,
                             uint64_t* list_counts) {
     if (precision == 1) {
-        return list ? launch_one<double, true>(s, sh, descs, tables, tallies, items, n_items, nullptr, queue,
+        return list ? launch_one<double, true>(s, sh, descs, tables, tallies, items, n_items, n_items_dev, queue,
                                                persistent, lists, list_counts)
-                    : launch_one<double, false>(s, sh, descs, tables, tallies, items, n_items, nullptr, queue,
+                    : launch_one<double, false>(s, sh, descs, tables, tallies, items, n_items, n_items_dev, queue,
                                                 persistent, lists, list_counts);
     }
-    return list ? launch_one<float, true>(s, sh, descs, tables, tallies, items, n_items, nullptr, queue, persistent,
-                                          lists, list_counts)
-                : launch_one<float, false>(s, sh, descs, tables, tallies, items, n_items, nullptr, queue,
+    return list ? launch_one<float, true>(s, sh, descs, tables, tallies, items, n_items, n_items_dev, queue,
+                                          persistent, lists, list_counts)
+                : launch_one<float, false>(s, sh, descs, tables, tallies, items, n_items, n_items_dev, queue,
                                            persistent, lists, list_counts);
 }
 

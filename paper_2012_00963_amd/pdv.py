@@ -157,19 +157,36 @@ def _u64ptr(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
 
 
+class Result(dict):
+    """One spectrum: fixed-point tallies (w_fx, w2_fx, sinks_fx), counters,
+    albedo and mean cosine; the float views W, W2 (and W_single, W_surface
+    with class tallies) are divided by 2^32 on first access."""
+
+    def __missing__(self, key):
+        if key == "W":
+            v = self["w_fx"].astype(np.float64) / SCALE
+        elif key == "W2":
+            v = self["w2_fx"].astype(np.float64) / SCALE
+        elif key in ("W_single", "W_surface") and self.get("_class") is not None:
+            C, nb = self["_class"]
+            v = (C[:nb] if key == "W_single" else C[nb:]).astype(np.float64) / SCALE
+        else:
+            raise KeyError(key)
+        self[key] = v
+        return v
+
+
 def _result(out: SpectrumOut, W, W2, C, n_bins):
-    res = {
-        "w_fx": W, "w2_fx": W2,
-        "W": W.astype(np.float64) / SCALE, "W2": W2.astype(np.float64) / SCALE,
-        "sinks_fx": {n: int(out.sinks_fx[i]) for i, n in enumerate(SINK_NAMES)},
-        "sinks": {n: int(out.sinks_fx[i]) / SCALE for i, n in enumerate(SINK_NAMES)},
-        "counts": {n: int(getattr(out.counters, n)) for n, _ in Counters._fields_},
-        "albedo": float(out.albedo), "g": float(out.g),
-    }
-    res["sinks"]["detected"] = float(W.sum(dtype=np.float64)) / SCALE
+    sinks_fx = {n: int(out.sinks_fx[i]) for i, n in enumerate(SINK_NAMES)}
+    res = Result(
+        w_fx=W, w2_fx=W2, sinks_fx=sinks_fx,
+        sinks={n: v / SCALE for n, v in sinks_fx.items()},
+        counts={n: int(getattr(out.counters, n)) for n, _ in Counters._fields_},
+        albedo=float(out.albedo), g=float(out.g),
+    )
+    res["sinks"]["detected"] = int(W.sum()) / SCALE     # exact: the bins sum below 2^64
     if C is not None:
-        res["W_single"] = C[:n_bins].astype(np.float64) / SCALE
-        res["W_surface"] = C[n_bins:].astype(np.float64) / SCALE
+        res["_class"] = (C, n_bins)
     return res
 
 
@@ -372,7 +389,9 @@ class ServeStats(ctypes.Structure):
                 ("events", ctypes.c_uint64), ("admission_waits", ctypes.c_uint64), ("mem_in_use", ctypes.c_uint64),
                 ("active", ctypes.c_uint32), ("pending", ctypes.c_uint32),
                 ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
-                ("max_ms", ctypes.c_double), ("busy_s", ctypes.c_double), ("wall_s", ctypes.c_double)]
+                ("max_ms", ctypes.c_double), ("busy_s", ctypes.c_double), ("wall_s", ctypes.c_double),
+                ("prepare_s", ctypes.c_double), ("launch_s", ctypes.c_double), ("collect_s", ctypes.c_double),
+                ("spectrogram_s", ctypes.c_double), ("queue_p50_ms", ctypes.c_double)]
 
 
 def _load_serving(lib):

@@ -90,3 +90,31 @@ def test_spectrogram_request_in_mix():
         for o in others:
             assert srv.poll(o, wait_ms=60_000) == 0
         srv.stop()
+
+
+def test_spectrogram_requests_overlap_spectra():
+    # several spectrogram requests finish on the spectrogram worker while
+    # plain spectra keep flowing; each map equals the direct call
+    from paper_2012_00963_amd import pdv
+    cases = []
+    for k in range(3):
+        p, sg = wl.spectrogram_case(n_frames=6, packets_per_frame=15_000 + 5000 * k)
+        p = dict(p, stream=900 + 50 * k)
+        cases.append((p, dict(sg, n_samples=16_000, list_capacity=4096)))
+    with pdv.Context(0) as c:
+        direct = [c.spectrogram(p, sg)["map"] for p, sg in cases]
+        mix = _mix(8)
+        alone = [c.spectrum(s) for s in mix]
+        srv = pdv.Server(c, max_active=6)
+        tk_sg = [srv.submit(p, sg=sg) for p, sg in cases]
+        tk = [srv.submit(s) for s in mix]
+        for t, r in zip(tk, alone):
+            assert srv.poll(t, wait_ms=60_000) == 0
+            assert np.array_equal(t.result()["w_fx"], r["w_fx"])
+        for t, d in zip(tk_sg, direct):
+            assert srv.poll(t, wait_ms=60_000) == 0
+            m = t.result()["spectrogram"]["map"]
+            assert np.linalg.norm(m - d) <= 1e-5 * np.linalg.norm(d)
+        st = srv.stats()
+        assert st["completed"] == len(mix) + len(cases) and st["failed"] == 0
+        assert srv.stop() == 0

@@ -169,6 +169,22 @@ def test_batch_equals_alone(ctx):
         assert np.array_equal(a["w_fx"], b["w_fx"]) and a["sinks_fx"] == b["sinks_fx"]
 
 
+def test_batch_graph_replays(ctx):
+    # captured batch launches replayed for several item lists, with eager
+    # batches in between: every replay equals the eager result
+    a = wl.batched_sets(10, seed=31, packets_scale=0.01)
+    b = wl.batched_sets(6, seed=32, packets_scale=0.02)
+    ref_a = ctx.spectrum_batch(a)
+    ref_b = ctx.spectrum_batch(b)
+    for rep in range(3):
+        for sets, ref in ((a, ref_a), (b, ref_b)):
+            got = ctx.spectrum_batch(sets, opts=dict(use_graph=1))
+            for x, y in zip(got, ref):
+                assert np.array_equal(x["w_fx"], y["w_fx"]) and x["sinks_fx"] == y["sinks_fx"], rep
+            eager = ctx.spectrum_batch(sets)
+            assert np.array_equal(eager[0]["w_fx"], ref[0]["w_fx"])
+
+
 def test_empty_and_degenerate(ctx):
     p = _c1(n_packets=0)
     g = ctx.spectrum(p)
