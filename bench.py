@@ -18,12 +18,14 @@ Also reported on the same JSON line:
   extra         FP64 ("plain") spectrum of the same workload and its error
                 against FP32, plus the legs (--legs, all by default):
                 "batched" (512 uneven sets in one FP32 launch vs serial FP64
-                launches), "spectrogram" (256 frames x 1e6 packets, beat
-                record, STFT), "serve" (60 s Poisson request stream with
-                continuous batching vs serial FP64, p50/p99 latency).
+                launches), "peaks" (beta / optical-depth sweep and the
+                Sec. III.C peak analysis of every spectrum), "spectrogram"
+                (256 frames x 1e6 packets, beat record, STFT), "serve" (60 s
+                Poisson request stream with continuous batching vs serial
+                FP64, p50/p99 latency).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                       [--legs batched,spectrogram,serve|none] [--serve-duration S]
+                       [--legs batched,peaks,spectrogram,serve|none] [--serve-duration S]
                        [--serve-only] [--calib-copy BYTES]
 """
 from __future__ import annotations
@@ -129,6 +131,7 @@ def batched_leg(ctx):
     tot = [abs(a["W"].sum() - b["W"].sum()) / b["W"].sum() for a, b in zip(r32, r64) if b["W"].sum() > 0]
     ev32 = sum(r["counts"]["collisions"] + r["counts"]["surface"] for r in r32)
     return {
+        "_spectra": [r["W"] / max(s["n_packets"], 1) for r, s in zip(r32, sets)],
         "sets": len(sets),
         "packets": int(sum(s["n_packets"] for s in sets)),
         "events": int(ev32),
@@ -144,6 +147,40 @@ def batched_leg(ctx):
         "median_l1_fp32_vs_fp64": float(np.median(errs)),
         "max_total_rel_fp32_vs_fp64": float(max(tot)),
     }
+
+
+def peaks_leg(ctx, batched_spectra=None):
+    """Peak analysis (Sec. III.C): an 18-set sweep of the large Mie cloud
+    over beta and optical depth (all photons leaving the top counted), one
+    FP32 batch, then the Fourier low-pass peak analysis of every spectrum on
+    the GPU; beta read off each spectrum beside the beta the cloud was built
+    with.  Also the peak analysis of the 512 batched spectra."""
+    import numpy as np
+    from paper_2012_00963_amd import workloads
+    sets = workloads.peak_sweep()
+    t0 = time.perf_counter()
+    res = ctx.spectrum_batch(sets, opts=dict(use_graph=1))
+    t1 = time.perf_counter()
+    p = sets[0]
+    W = np.array([r["W"] for r in res]) / p["n_packets"]
+    args = (p["v_lo"], p["v_hi"], p["v_surface"], 40, 1.02 * p["v_surface"], p["v_hi"])
+    ctx.peak_analysis(W, *args)                              # resident buffers
+    t2 = time.perf_counter()
+    out = ctx.peak_analysis(W, *args)
+    t3 = time.perf_counter()
+    rows = [{"beta_cloud": s["beta"], "tau_ext": s["tau_total"], "status": o["status"],
+             "x_peak": round(o["x_peak"], 4), "beta_from_peak": round(o["beta"], 3), "tau0_from_peak": round(o["tau0"], 3)}
+            for s, o in zip(sets, out)]
+    r = {"sets": len(sets), "packets_per_set": p["n_packets"], "transport_s": t1 - t0,
+         "peak_analysis_ms": (t3 - t2) * 1e3, "keep_modes": 40, "sweep": rows}
+    if batched_spectra is not None:
+        B = np.array(batched_spectra)
+        ctx.peak_analysis(B, *args)
+        t4 = time.perf_counter()
+        ctx.peak_analysis(B, *args)
+        t5 = time.perf_counter()
+        r["batched_512_peak_analysis_ms"] = (t5 - t4) * 1e3
+    return r
 
 
 def spectrogram_leg(ctx):
@@ -233,8 +270,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
-    ap.add_argument("--legs", default="batched,spectrogram,serve",
-                    help="comma list of extra legs: batched,spectrogram,serve (or none)")
+    ap.add_argument("--legs", default="batched,peaks,spectrogram,serve",
+                    help="comma list of extra legs: batched,peaks,spectrogram,serve (or none)")
     ap.add_argument("--cpu-sample", type=int, default=20_000_000, help="packets in the oracle sample")
     ap.add_argument("--calib-copy", type=int, default=0, help="only run a copy of this many bytes")
     ap.add_argument("--serve-duration", type=float, default=60.0, help="seconds of the serving trace")
@@ -343,8 +380,12 @@ def main(argv=None):
         })
 
     legs = [x for x in args.legs.split(",") if x and x != "none"]
+    spectra_512 = None
     if "batched" in legs:
         out["extra"]["batched"] = batched_leg(ctx)
+        spectra_512 = out["extra"]["batched"].pop("_spectra")
+    if "peaks" in legs:
+        out["extra"]["peaks"] = peaks_leg(ctx, spectra_512)
     if "spectrogram" in legs:
         out["extra"]["spectrogram"] = spectrogram_leg(ctx)
     if "serve" in legs:

@@ -413,6 +413,104 @@ int pdv_create_host(struct pdv_ctx** out);
 int pdv_last_launch(const struct pdv_ctx* ctx, float* kernel_ms, int32_t* grid, int32_t* block,
                     int32_t* n_items, int32_t* guide_bits, int32_t* lds_bytes);
 
+/*
+ * ---------------------------------------------------------------------------
+ * Peak analysis (Sec. III.C, eq. 31, 34-35).
+ *
+ * The paper reads the ejecta's velocity-profile coefficient beta and optical
+ * thickness tau0 off the main peak of a PDV spectrum: smooth the spectrum by
+ * a Fourier low-pass filter, take its peak position x = v_peak / v_fs and the
+ * relative curvature I''/I there (second derivative in x), and invert
+ * x = 1 + ln(tau0)/beta and I''/I = -beta^2.
+ *
+ * Each of n_spectra histograms (n_bins equal bins on [v_lo, v_hi), any
+ * non-negative scale) is replaced by its DFT modes k = 0..keep_modes
+ * (keep_modes < n_bins/2), i.e. the band-limited series
+ *   S(t) = (1/n)[A_0 + 2 sum_k (A_k cos(2 pi k t/n) + B_k sin(2 pi k t/n))],
+ * t the continuous bin coordinate (t = b at the centre of bin b).  The peak
+ * is the maximum of S near the bin with the largest S inside the window
+ * search_lo <= v < search_hi (bin centres); it is located with Newton steps
+ * on S' within one bin of that bin.
+ * ---------------------------------------------------------------------------
+ */
+typedef struct pdv_peak_params {
+    double v_lo, v_hi;           /* histogram range (m/s) */
+    int32_t n_bins;              /* 16..4096 */
+    int32_t keep_modes;          /* 0 <= keep_modes < n_bins / 2 */
+    double v_fs;                 /* free-surface velocity (> 0) */
+    double search_lo, search_hi; /* peak window on the bin centres (m/s); must hold a bin centre */
+} pdv_peak_params;
+
+typedef struct pdv_peak_result {
+    int32_t bin;                 /* bin with the largest smoothed value in the window */
+    int32_t status;              /* 0, or 1 if the curvature at the peak is not negative (beta, tau0 NaN) */
+    double t_peak;               /* peak position in bins (bin centres at integers) */
+    double v_peak, x_peak;       /* peak velocity, and v_peak / v_fs */
+    double value;                /* smoothed spectrum at the peak */
+    double rel_curvature;        /* I''/I at the peak, derivative in v / v_fs */
+    double beta, tau0;           /* sqrt(-rel_curvature), exp(beta (x_peak - 1)) */
+} pdv_peak_result;
+
+/*
+ * spectra: host array, n_spectra x n_bins, row-major (read during the call).
+ * smoothed: nullable host array of the same shape for S at the bin centres.
+ * out: host array of n_spectra results.  FP64 throughout.  Errors:
+ * PDV_EINVAL (NULL pointers, sizes or window out of range), PDV_ENOMEM,
+ * PDV_EDEVICE.
+ */
+int pdv_peak_analysis(struct pdv_ctx* ctx, const double* spectra, int32_t n_spectra, const pdv_peak_params* params,
+                      double* smoothed, pdv_peak_result* out);
+
+/*
+ * ---------------------------------------------------------------------------
+ * Ejecta front end (Sec. II.B eq. 8-10, Sec. II.C eq. 20-21, Sec. III.B
+ * eq. 25-27): a cloud stated by the paper's ejecta parameters.
+ *
+ * The extinction of the whole ejecta is the exponent of eq. 10,
+ *   tau_full = 3 m0 <d^2 Q_ext> / (2 rho0 <d^3>),
+ * with number-weighted averages over the log-normal size law (eq. 21)
+ * truncated to [d_min, d_max] on the Gauss-Legendre nodes in ln d of the
+ * Mie tables, Q_ext from Mie theory (eq. 12).  The slab [v_fs, v_top] holds
+ * the share 1 - exp(-beta (v_top/v_fs - 1)) of the exponential mass profile
+ * (eq. 20) and that share of the extinction (tau_total).  The SS model's
+ * optical thickness (eq. 27) uses K*_ext = g_back Q_ext (eq. 25).
+ * ---------------------------------------------------------------------------
+ */
+typedef struct pdv_ejecta {
+    double area_mass;            /* m0, total area mass of the ejecta (kg/m^2), > 0 */
+    double density;              /* rho0, particle material density (kg/m^3), > 0 */
+    double beta;                 /* velocity-profile coefficient (eq. 20), > 0 */
+    double v_fs;                 /* free-surface velocity (m/s), > 0 */
+    double v_top;                /* top of the slab (m/s), > v_fs */
+    double d_median, sigma_ln, d_min, d_max;   /* size law (m), as in pdv_params */
+    int32_t n_size_nodes;        /* Gauss-Legendre nodes, 8..1024 */
+    int32_t pad;
+    double m_re, m_im;           /* complex refractive index (m_im >= 0) */
+    double wavelength;           /* m */
+    double g_back;               /* K*_ext / K_ext for tau0_ss (0.5-0.7 in the paper; 0 allowed) */
+} pdv_ejecta;
+
+typedef struct pdv_ejecta_out {
+    double tau_full;             /* extinction optical depth of the whole ejecta (eq. 10) */
+    double tau_total;            /* ... of the slab [v_fs, v_top] */
+    double mass_share;           /* mass share of the slab */
+    double albedo;               /* <C_sca>/<C_ext> (eq. 11) */
+    double q_ext_mean;           /* <d^2 Q_ext>/<d^2> */
+    double d_sauter;             /* <d^3>/<d^2> (m) */
+    double tau0_ss;              /* eq. 27 with K*_ext = g_back Q_ext */
+} pdv_ejecta_out;
+
+/*
+ * Fill the cloud fields of *p (kept: detector, histogram, packets, seed,
+ * precision, surface albedo and law, n_layers, n_angles, max_orders,
+ * weighting): v_bottom = v_surface = v_fs, v_top, density EXP with
+ * v0 = v_fs/beta, tau_total, phase MIE with the size law and optics.
+ * Builds (or reuses) the device Mie tables of that optics; *out (nullable)
+ * receives the quantities above.  Errors: PDV_EINVAL (bad ejecta or
+ * template), PDV_ENOMEM, PDV_EDEVICE.
+ */
+int pdv_ejecta_params(struct pdv_ctx* ctx, const pdv_ejecta* ejecta, pdv_params* p, pdv_ejecta_out* out);
+
 #ifdef __cplusplus
 }
 #endif

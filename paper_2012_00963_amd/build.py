@@ -21,7 +21,7 @@ OUT = os.path.join(HERE, "libpdv.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("PDV_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["transport.hip", "tables.hip", "stage2.hip", "pdv_api.cpp", "serve.cpp"]
+SOURCES = ["transport.hip", "tables.hip", "stage2.hip", "peak.hip", "pdv_api.cpp", "serve.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-I" + INC, "-I" + CSRC]
 

@@ -40,6 +40,10 @@ hipError_t launch_synth(hipStream_t s, int n_frames, const void* frames, const L
 hipError_t launch_stft(hipStream_t s, const float* signal, int n_windows, int nfft, int hop, void* tw, void* tr,
                        float* win, float* map, bool build_tables);
 int synth_chunk();
+int peak_lds_bytes(int n, int keep);
+hipError_t launch_ejecta(hipStream_t s, int n_nodes, const void* info, const EjectaJob& J, double* out);
+hipError_t launch_peak(hipStream_t s, int n_spectra, const double* spectra, int n, int keep, const PeakJob& J,
+                       double* smoothed, PeakOut* out);
 size_t synth_frame_bytes();
 hipError_t launch_transport(hipStream_t s, int precision, bool list, const TransportShape& sh,
                             const SetDesc* descs, const uint8_t* tables, uint64_t* tallies, const WorkItem* items,
@@ -250,7 +254,7 @@ extern "C" void pdv_destroy(pdv_ctx* ctx) {
 void pdv_ctx::release_all() {
     DevBuf* all[] = {&descs, &tables, &tallies, &items, &queue, &layer_jobs, &phase_jobs, &density, &lists,
                      &list_counts, &mie_info, &mie_a, &mie_b, &mie_d, &mie_basis, &mie_gx, &mie_gw, &sg_entries,
-                     &sg_offsets, &sg_signal, &sg_map, &sg_frames, &sg_partial, &sg_tab, &dup_src, &n_items_dev};
+                     &sg_offsets, &sg_signal, &sg_map, &sg_frames, &sg_partial, &sg_tab, &dup_src, &n_items_dev, &pk_in, &pk_smooth, &pk_out, &ej_out};
     if (batch_gexec) (void)hipGraphExecDestroy(batch_gexec);
     batch_gexec = nullptr;
     batch_key = BatchGraphKey{};
@@ -395,7 +399,7 @@ void pdv_ctx::default_opts(pdv_launch_opts& o, uint64_t total_packets, int n_set
     if (o.packets_per_item == 0) {
         uint64_t grid = (uint64_t)n_cu * (uint64_t)o.blocks_per_cu;
         uint64_t ppi = total_packets / (grid * 4 + 1);
-        ppi = std::max<uint64_t>(ppi, 4096);
+        ppi = std::max<uint64_t>(ppi, 1024);
         ppi = std::min<uint64_t>(ppi, 1ull << 18);
         o.packets_per_item = tuned.packets_per_item > 0 ? tuned.packets_per_item : ppi;
     }
@@ -1116,5 +1120,111 @@ extern "C" int pdv_autotune(pdv_ctx* ctx, const pdv_params* sets, int32_t n, int
     ctx->tuned.guide_bits = best_o.guide_bits;
     ctx->tuned.retire_batch = best_o.retire_batch;
     if (best) *best = best_o;
+    return PDV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Peak analysis
+// ---------------------------------------------------------------------------
+static_assert(sizeof(pdv_peak_result) == sizeof(PeakOut), "peak result layout");
+
+extern "C" int pdv_peak_analysis(pdv_ctx* ctx, const double* spectra, int32_t n_spectra, const pdv_peak_params* P,
+                                 double* smoothed, pdv_peak_result* out) {
+    if (!ctx) return PDV_EINVAL;
+    if (!spectra || !P || !out || n_spectra < 1) return ctx->fail(PDV_EINVAL, "NULL argument or no spectra");
+    if (ctx->poisoned) return ctx->fail(PDV_EDEVICE, "context poisoned by an earlier device error");
+    if (!ctx->ready) return ctx->fail(PDV_ESTATE, "context not initialised");
+    const int n = P->n_bins, keep = P->keep_modes;
+    if (n < 16 || n > 4096) return ctx->fail(PDV_EINVAL, "n_bins must be in [16, 4096]");
+    if (keep < 0 || 2 * keep >= n) return ctx->fail(PDV_EINVAL, "keep_modes must be in [0, n_bins/2)");
+    if (!(P->v_hi > P->v_lo) || !std::isfinite(P->v_lo) || !std::isfinite(P->v_hi))
+        return ctx->fail(PDV_EINVAL, "need v_lo < v_hi");
+    if (!(P->v_fs > 0.0) || !std::isfinite(P->v_fs)) return ctx->fail(PDV_EINVAL, "v_fs must be positive");
+    PeakJob J{P->v_lo, (P->v_hi - P->v_lo) / (double)n, P->v_fs, P->search_lo, P->search_hi, -1, -1};
+    for (int b = 0; b < n; ++b) {
+        const double vc = J.v_lo + ((double)b + 0.5) * J.dv;
+        if (vc >= J.search_lo && vc < J.search_hi) {
+            if (J.wb0 < 0) J.wb0 = b;
+            J.wb1 = b;
+        }
+    }
+    if (J.wb0 < 0) return ctx->fail(PDV_EINVAL, "the search window holds no bin centre");
+    if (peak_lds_bytes(n, keep) > ctx->lds_per_block)
+        return ctx->fail(PDV_EINVAL, "n_bins and keep_modes need more LDS than the device has");
+    if (int r = ctx->hip_check(hipSetDevice(ctx->device), "hipSetDevice")) return r;
+    const size_t vals = (size_t)n_spectra * (size_t)n;
+    int r;
+    if ((r = ctx->ensure(ctx->pk_in, 8 * vals, "peak input"))) return r;
+    if (smoothed && (r = ctx->ensure(ctx->pk_smooth, 8 * vals, "peak smoothed"))) return r;
+    if ((r = ctx->ensure(ctx->pk_out, sizeof(PeakOut) * (size_t)n_spectra, "peak results"))) return r;
+    hipStream_t s = ctx->stream;
+    if ((r = ctx->hip_check(hipMemcpyAsync(ctx->pk_in.ptr, spectra, 8 * vals, hipMemcpyHostToDevice, s),
+                            "copy spectra")))
+        return r;
+    if ((r = ctx->hip_check(launch_peak(s, n_spectra, (const double*)ctx->pk_in.ptr, n, keep, J,
+                                        smoothed ? (double*)ctx->pk_smooth.ptr : nullptr, (PeakOut*)ctx->pk_out.ptr),
+                            "peak kernel")))
+        return r;
+    if ((r = ctx->hip_check(hipMemcpyAsync(out, ctx->pk_out.ptr, sizeof(PeakOut) * (size_t)n_spectra,
+                                           hipMemcpyDeviceToHost, s), "copy peak results")))
+        return r;
+    if (smoothed &&
+        (r = ctx->hip_check(hipMemcpyAsync(smoothed, ctx->pk_smooth.ptr, 8 * vals, hipMemcpyDeviceToHost, s),
+                            "copy smoothed spectra")))
+        return r;
+    return ctx->hip_check(hipStreamSynchronize(s), "peak analysis");
+}
+
+// ---------------------------------------------------------------------------
+// Ejecta front end
+// ---------------------------------------------------------------------------
+static_assert(sizeof(pdv_ejecta_out) == 7 * sizeof(double), "ejecta output layout");
+
+extern "C" int pdv_ejecta_params(pdv_ctx* ctx, const pdv_ejecta* e, pdv_params* p, pdv_ejecta_out* out) {
+    if (!ctx) return PDV_EINVAL;
+    if (!e || !p) return ctx->fail(PDV_EINVAL, "NULL ejecta or params");
+    if (ctx->poisoned) return ctx->fail(PDV_EDEVICE, "context poisoned by an earlier device error");
+    if (!ctx->ready) return ctx->fail(PDV_ESTATE, "context not initialised");
+    auto pos = [](double v) { return std::isfinite(v) && v > 0.0; };
+    if (!pos(e->area_mass) || !pos(e->density) || !pos(e->beta) || !pos(e->v_fs))
+        return ctx->fail(PDV_EINVAL, "area_mass, density, beta and v_fs must be positive");
+    if (!std::isfinite(e->v_top) || !(e->v_top > e->v_fs)) return ctx->fail(PDV_EINVAL, "need v_top > v_fs");
+    if (!std::isfinite(e->g_back) || e->g_back < 0.0) return ctx->fail(PDV_EINVAL, "g_back must be >= 0");
+    pdv_params q = *p;
+    q.v_bottom = e->v_fs;
+    q.v_top = e->v_top;
+    q.v_surface = e->v_fs;
+    q.density_kind = PDV_DENSITY_EXP;
+    q.v0 = e->v_fs / e->beta;
+    q.density = nullptr;
+    q.phase_kind = PDV_PHASE_MIE;
+    q.phase = nullptr;
+    q.m_re = e->m_re;
+    q.m_im = e->m_im;
+    q.wavelength = e->wavelength;
+    q.d_median = e->d_median;
+    q.sigma_ln = e->sigma_ln;
+    q.d_min = e->d_min;
+    q.d_max = e->d_max;
+    q.n_size_nodes = e->n_size_nodes;
+    q.tau_total = 1.0;                    // validated below with the real value
+    if (int r = validate_params(ctx, &q)) return r;
+    if (int r = ctx->hip_check(hipSetDevice(ctx->device), "hipSetDevice")) return r;
+    if (int r = ctx->ensure_mie_basis(q)) return r;
+    if (int r = ctx->ensure(ctx->ej_out, 8 * 8, "ejecta results")) return r;
+    const EjectaJob J{e->area_mass, e->density, e->beta, e->v_fs, e->v_top, e->d_median, e->sigma_ln, e->g_back};
+    double h[7];
+    int r;
+    if ((r = ctx->hip_check(launch_ejecta(ctx->stream, ctx->mie_nodes, ctx->mie_info.ptr, J, (double*)ctx->ej_out.ptr),
+                            "ejecta kernel")))
+        return r;
+    if ((r = ctx->hip_check(hipMemcpyAsync(h, ctx->ej_out.ptr, sizeof h, hipMemcpyDeviceToHost, ctx->stream),
+                            "copy ejecta results")))
+        return r;
+    if ((r = ctx->hip_check(hipStreamSynchronize(ctx->stream), "ejecta front end"))) return r;
+    q.tau_total = h[1];
+    if ((r = validate_params(ctx, &q))) return r;
+    *p = q;
+    if (out) std::memcpy(out, h, sizeof h);
     return PDV_OK;
 }

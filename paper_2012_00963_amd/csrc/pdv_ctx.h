@@ -84,6 +84,8 @@ struct pdv_ctx {
     // batch buffers
     DevBuf descs, tables, tallies, items, queue, layer_jobs, phase_jobs, density, lists, list_counts, dup_src;
     DevBuf n_items_dev;                  // item count read by graph replays
+    DevBuf pk_in, pk_smooth, pk_out;     // peak analysis
+    DevBuf ej_out;                       // ejecta front end
     int h_n_items = 0;
     hipGraphExec_t batch_gexec = nullptr;
     BatchGraphKey batch_key;

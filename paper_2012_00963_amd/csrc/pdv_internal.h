@@ -116,6 +116,21 @@ struct TransportShape {
     int retire_min = 12;                                // finished lanes per retire round
 };
 
+// Peak analysis (host-packed constants of one call) and its per-spectrum result.
+struct PeakJob {
+    double v_lo, dv, v_fs, search_lo, search_hi;
+    int32_t wb0, wb1;          // first and last bin with its centre in the window
+};
+struct PeakOut {
+    int32_t bin, status;
+    double t_peak, v_peak, x_peak, value, rel_curvature, beta, tau0;
+};
+
+// Ejecta front end: the constants of one call.
+struct EjectaJob {
+    double area_mass, density, beta, v_fs, v_top, d_median, sigma_ln, g_back;
+};
+
 // Table-building jobs (host-packed, one per set).
 struct LayerJob {
     double v_bottom, v_top, v0, tau_total;

@@ -478,11 +478,20 @@ void ServeEngine::loop() {
                 if (!q->cancel && q->issued < q->p.n_packets) ++open;
             const uint64_t share = open ? std::max<uint64_t>(opts.packets_per_item, opts.packets_per_iteration / open)
                                         : 0;
+            // item size of this iteration: enough items to spread a small
+            // iteration over the whole device (results do not depend on it)
+            uint64_t total = 0;
+            for (auto& q : active)
+                if (!q->cancel) total += std::min<uint64_t>(q->p.n_packets - q->issued, share);
+            const uint64_t target = 8ull * (uint64_t)std::max(1, ctx->n_cu);
+            uint64_t ppi = (total + target - 1) / target;
+            ppi = std::max<uint64_t>(ppi, (total + opts.max_items - 1) / (uint64_t)opts.max_items);
+            ppi = std::min<uint64_t>(std::max<uint64_t>(ppi, 1024), opts.packets_per_item);
             for (auto& q : active) {
                 if (q->cancel) continue;
                 uint64_t take = std::min<uint64_t>(q->p.n_packets - q->issued, share);
                 while (take > 0 && (int)items.size() < opts.max_items) {
-                    const uint64_t c = std::min<uint64_t>(take, opts.packets_per_item);
+                    const uint64_t c = std::min<uint64_t>(take, ppi);
                     items.push_back(WorkItem{(uint32_t)q->slot, 0, q->p.pid_begin + q->issued, c});
                     q->issued += c;
                     take -= c;

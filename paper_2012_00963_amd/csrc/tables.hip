@@ -450,6 +450,45 @@ phase_cdf_kernel(const PhaseJob* __restrict__ jobs, uint8_t* tables, SetDesc* de
     if (tid == 0) d.g_mean = gpart;
 }
 
+// Ejecta front end (eq. 8-10, 20-21, 27): number-weighted size moments of
+// the truncated log-normal on the Mie nodes, and from them the extinction
+// optical depth of the whole ejecta and of the slab [v_fs, v_top], the
+// size-averaged albedo and efficiency, the Sauter mean diameter and the
+// single-scattering model's optical thickness.  One block of 256 threads.
+__global__ void __launch_bounds__(256)
+ejecta_kernel(int n_nodes, const MieNodeInfo* __restrict__ info, EjectaJob J, double* __restrict__ out) {
+    __shared__ double red[256];
+    const int tid = threadIdx.x;
+    const double lnm = log(J.d_median);
+    double s2 = 0.0, s3 = 0.0, e2 = 0.0, c2 = 0.0;
+    for (int i = tid; i < n_nodes; i += 256) {
+        const MieNodeInfo I = info[i];
+        const double z = (I.lnd - lnm) / J.sigma_ln;
+        const double q = I.wq * exp(-0.5 * z * z) / (2.5066282746310002 * J.sigma_ln);
+        const double d = exp(I.lnd);
+        const double d2 = d * d;
+        s2 += q * d2;
+        s3 += q * d2 * d;
+        e2 += q * d2 * I.q_ext;
+        c2 += q * d2 * I.q_sca;
+    }
+    s2 = block_sum(s2, red);
+    s3 = block_sum(s3, red);
+    e2 = block_sum(e2, red);
+    c2 = block_sum(c2, red);
+    if (tid == 0) {
+        const double tau_full = 1.5 * J.area_mass * e2 / (J.density * s3);
+        const double share = 1.0 - exp(-J.beta * (J.v_top / J.v_fs - 1.0));
+        out[0] = tau_full;
+        out[1] = tau_full * share;
+        out[2] = share;
+        out[3] = c2 / e2;
+        out[4] = e2 / s2;
+        out[5] = s3 / s2;
+        out[6] = 1.5 * J.g_back * J.area_mass * e2 / (J.density * s3);
+    }
+}
+
 // Sets that share another set's tables take its device-computed fields.
 __global__ void copy_desc_fields_kernel(SetDesc* d, const int* __restrict__ src, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -512,6 +551,11 @@ void launch_phase_cdf(hipStream_t s, int n_jobs, const void* jobs, int n_nodes, 
                            (const MieNodeInfo*)info, basis, tables, descs);
     }
     hipLaunchKernelGGL(phase_cdf_kernel, dim3(n_jobs), dim3(1024), 0, s, (const PhaseJob*)jobs, tables, descs);
+}
+
+hipError_t launch_ejecta(hipStream_t s, int n_nodes, const void* info, const EjectaJob& J, double* out) {
+    hipLaunchKernelGGL(ejecta_kernel, dim3(1), dim3(256), 0, s, n_nodes, (const MieNodeInfo*)info, J, out);
+    return hipGetLastError();
 }
 
 void launch_copy_desc_fields(hipStream_t s, SetDesc* descs, const int* src, int n) {

@@ -61,8 +61,10 @@ constexpr int N_SINK_SLOTS = 8;
 // lane states of the event loop
 enum LaneState : int { ST_EMPTY = 0, ST_ALIVE = 1, ST_EXIT = 2, ST_TRUNC = 3, ST_ABS_SURF = 4, ST_ABS_PART = 5 };
 
-// packet indices a wave claims from its work item at a time
+// packet indices a wave claims from its work item at a time (fewer for a
+// small item, so that every wave of the block gets some)
 constexpr int REFILL_CHUNK = 128;
+constexpr int REFILL_CHUNK_MIN = 32;
 
 __host__ __device__ inline LdsLayout lds_layout(int real_bytes, int max_layers, int max_cells, int max_bins,
                                                 int guide_bits) {
@@ -322,6 +324,9 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
 
         const SetConst<Real> c = load_const<Real>(descs[set]);
         const int nb = c.n_bins;
+        uint32_t chunk = count / (2u * (uint32_t)(nthr >> 6));
+        chunk = chunk < (uint32_t)REFILL_CHUNK_MIN ? (uint32_t)REFILL_CHUNK_MIN
+                                                   : (chunk > (uint32_t)REFILL_CHUNK ? (uint32_t)REFILL_CHUNK : chunk);
 
         // ---- per-lane packet state ----
         // st: ST_EMPTY (no packet), ST_ALIVE, or how the packet ended (its
@@ -409,14 +414,14 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                 while (empty != 0ull && !exhausted) {
                     if (w_next >= w_end) {
                         uint32_t base = 0;
-                        if (lane == 0) base = atomicAdd(&s_next, (uint32_t)REFILL_CHUNK);
+                        if (lane == 0) base = atomicAdd(&s_next, chunk);
                         base = uniform_u32(base);
                         if (base >= count) {
                             exhausted = true;
                             break;
                         }
                         w_next = base;
-                        w_end = count - base < (uint32_t)REFILL_CHUNK ? count : base + (uint32_t)REFILL_CHUNK;
+                        w_end = count - base < chunk ? count : base + chunk;
                     }
                     const uint32_t n = (uint32_t)__popcll(empty);
                     const uint32_t avail = w_end - w_next;

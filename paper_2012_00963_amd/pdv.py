@@ -567,3 +567,80 @@ def _autotune(self, sets: list, repeats: int = 3, cache_path: str | None = None)
 
 
 Context.autotune = _autotune
+
+
+class PeakParams(ctypes.Structure):
+    _fields_ = [("v_lo", ctypes.c_double), ("v_hi", ctypes.c_double), ("n_bins", ctypes.c_int32),
+                ("keep_modes", ctypes.c_int32), ("v_fs", ctypes.c_double), ("search_lo", ctypes.c_double),
+                ("search_hi", ctypes.c_double)]
+
+
+class PeakResult(ctypes.Structure):
+    _fields_ = [("bin", ctypes.c_int32), ("status", ctypes.c_int32), ("t_peak", ctypes.c_double),
+                ("v_peak", ctypes.c_double), ("x_peak", ctypes.c_double), ("value", ctypes.c_double),
+                ("rel_curvature", ctypes.c_double), ("beta", ctypes.c_double), ("tau0", ctypes.c_double)]
+
+
+def _peak_analysis(self, spectra, v_lo: float, v_hi: float, v_fs: float, keep_modes: int,
+                   search_lo: float, search_hi: float, want_smoothed: bool = False):
+    """Peak position, relative curvature and (beta, tau0) of each spectrum
+    (rows of ``spectra``) after Fourier low-pass smoothing; returns a list
+    of dicts, and the smoothed spectra when asked."""
+    lib = self.lib
+    P = ctypes.POINTER
+    lib.pdv_peak_analysis.argtypes = [ctypes.c_void_p, P(ctypes.c_double), ctypes.c_int32, P(PeakParams),
+                                      P(ctypes.c_double), P(PeakResult)]
+    S = np.ascontiguousarray(np.atleast_2d(np.asarray(spectra, dtype=np.float64)))
+    m, n = S.shape
+    prm = PeakParams(float(v_lo), float(v_hi), int(n), int(keep_modes), float(v_fs), float(search_lo),
+                     float(search_hi))
+    out = (PeakResult * m)()
+    sm = np.empty_like(S) if want_smoothed else None
+    self._check(lib.pdv_peak_analysis(self.h, S.ctypes.data_as(P(ctypes.c_double)), m, ctypes.byref(prm),
+                                      sm.ctypes.data_as(P(ctypes.c_double)) if sm is not None else None, out))
+    res = [{n_: getattr(out[i], n_) for n_, _ in PeakResult._fields_} for i in range(m)]
+    return (res, sm) if want_smoothed else res
+
+
+Context.peak_analysis = _peak_analysis
+
+
+class Ejecta(ctypes.Structure):
+    _fields_ = [("area_mass", ctypes.c_double), ("density", ctypes.c_double), ("beta", ctypes.c_double),
+                ("v_fs", ctypes.c_double), ("v_top", ctypes.c_double), ("d_median", ctypes.c_double),
+                ("sigma_ln", ctypes.c_double), ("d_min", ctypes.c_double), ("d_max", ctypes.c_double),
+                ("n_size_nodes", ctypes.c_int32), ("pad", ctypes.c_int32), ("m_re", ctypes.c_double),
+                ("m_im", ctypes.c_double), ("wavelength", ctypes.c_double), ("g_back", ctypes.c_double)]
+
+
+class EjectaOut(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("tau_full", "tau_total", "mass_share", "albedo", "q_ext_mean",
+                                               "d_sauter", "tau0_ss")]
+
+
+PARAM_FIELDS = [n for n, _ in Params._fields_ if n not in ("density", "phase")]
+
+
+def _ejecta_params(self, ejecta: dict, template: dict):
+    """Cloud parameters (a params dict) for the paper's ejecta description,
+    and the front end's derived quantities."""
+    lib = self.lib
+    P = ctypes.POINTER
+    lib.pdv_ejecta_params.argtypes = [ctypes.c_void_p, P(Ejecta), P(Params), P(EjectaOut)]
+    e = Ejecta()
+    for n, _ in Ejecta._fields_:
+        if n != "pad":
+            setattr(e, n, ejecta[n])
+    keep = []
+    prm = make_params(template, keep)
+    out = EjectaOut()
+    self._check(lib.pdv_ejecta_params(self.h, ctypes.byref(e), ctypes.byref(prm), ctypes.byref(out)))
+    p = dict(template)
+    p.pop("density", None)
+    p.pop("phase", None)
+    for n in PARAM_FIELDS:
+        p[n] = getattr(prm, n)
+    return p, {n: getattr(out, n) for n, _ in EjectaOut._fields_}
+
+
+Context.ejecta_params = _ejecta_params

@@ -100,6 +100,24 @@ def batched_sets(n_sets: int = 512, seed: int = 4, packets_scale: float = 1.0) -
     return sets
 
 
+def peak_sweep(betas=(4.0, 6.0, 8.0, 10.0, 12.0, 14.0), taus=(10.0, 20.0, 40.0),
+               n_packets: int = 1_000_000) -> list[dict]:
+    """Sensitivity sweep in the spirit of Sec. III.A: the large Mie cloud
+    with every photon leaving the top counted (cone pi/2), density
+    proportional to exp(-beta (v/v_fs - 1)) (eq. 20, v0 = v_fs / beta) for
+    each beta, at each extinction optical depth; stream = sweep index,
+    seed 6."""
+    sets = []
+    for tau in taus:
+        for beta in betas:
+            p = large_mie(n_packets)
+            p.update(cone_half_angle=math.pi / 2, tau_total=float(tau), v0=p["v_surface"] / float(beta),
+                     seed=6, stream=len(sets))
+            p["beta"] = float(beta)
+            sets.append(p)
+    return sets
+
+
 def serving_trace(rate: float = 200.0, duration: float = 60.0, seed: int = 5,
                   p_spectrogram: float = 0.25, sg_frames: int = 64,
                   packets_scale: float = 1.0) -> list[dict]:
