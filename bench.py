@@ -44,16 +44,18 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 # Issue-slot cost of one scatter event in the transport kernel, counted from
-# the algorithm: Philox4x32-10 (10 rounds x
-# 2 mul_hi + 2 mul_lo + 4 xor = 80), three uniforms (12), flight (3),
-# branch tests (4), layer/angle lookup (13), angle sampling (11), azimuth (1),
-# rotation (8), Doppler (6), weight (4): 142 full-rate lane operations, of
-# which 6 are transcendental (log, rcp, 2 sqrt, sin/cos) and occupy 4 issue
-# slots each: 142 + 6 * 3 = 160 slots.
+# the algorithm in full-rate 32-bit lane operations: Philox4x32-10 (10 rounds
+# x (two 32x32->64 multiplies, which issue at half rate = 4 slots, + 4 xor)
+# = 80), three uniforms (12), flight (3), branch tests (4), layer/angle
+# lookup (13), angle sampling (11), azimuth (1), rotation (8), Doppler (6),
+# weight (4): 142, of which 6 are transcendental (log, rcp, 2 sqrt, sin/cos)
+# at quarter rate (+3 slots each): 160 slots.
 SLOTS_PER_EVENT = 160
 FP32_FLOPS_PER_EVENT = 40
-# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane operations/s
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# VALU issue peak in full-rate lane operations/s: the FP32 vector peak of
+# 157.3 TFLOP/s is 78.6 T lane-FMAs/s = 256 CUs x 128 lanes per clock x
+# 2.4 GHz (a wave64 instruction issues in two cycles on a SIMD)
+VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 FP32_PEAK_TFLOPS = 157.3
 
 METRIC = "scatter events/s; spectra/s batched-FP32 vs plain-FP64 at <=1% error; p99 lat"
@@ -114,6 +116,12 @@ def batched_leg(ctx):
     sets = workloads.batched_sets(512)
     s32 = [dict(s, precision=0) for s in sets]
     s64 = [dict(s, precision=1) for s in sets]
+    # the autotuner picks the batch's launch shape and guide resolution
+    # (results are bitwise the same for every candidate; cached per build)
+    import tempfile
+    ta = time.perf_counter()
+    tune = ctx.autotune(s32, repeats=1, cache_path=os.path.join(tempfile.gettempdir(), "pdv_autotune.json"))
+    tb = time.perf_counter()
     # one untimed batch of the same shape: Mie basis, device buffers and the
     # captured launch graph are resident afterwards (tables are rebuilt and
     # every packet is transported again in the timed batch)
@@ -123,7 +131,9 @@ def batched_leg(ctx):
     r32 = ctx.spectrum_batch(s32, opts=dict(use_graph=1))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    k32 = ctx.last_launch()["kernel_ms"]
+    launch = ctx.last_launch()
+    k32 = launch["kernel_ms"]
+    ctx.reset_launch_defaults()            # the FP64 baseline runs with its own defaults
     r64 = [ctx.spectrum(s) for s in s64]
     torch.cuda.synchronize()
     t2 = time.perf_counter()
@@ -138,6 +148,10 @@ def batched_leg(ctx):
         "fp32_batched_s": t1 - t0,
         "fp32_batched_kernel_ms": k32,
         "fp32_launch": "one persistent launch replayed from a captured hipGraph",
+        "autotune": {"block": launch["block"], "grid": launch["grid"], "items": launch["items"],
+                     "guide_bits": launch["guide_bits"], "retire_batch": tune.get("retire_batch"),
+                     "candidates": tune["candidates"], "best_ms": tune["best_ms"], "default_ms": tune["default_ms"],
+                     "cached": tune["cached"], "tuning_s": tb - ta},
         "fp64_plain_serial_s": t2 - t1,
         "spectra_per_s_fp32_batched": len(sets) / (t1 - t0),
         "spectra_per_s_fp64_plain": len(sets) / (t2 - t1),

@@ -181,7 +181,7 @@ typedef struct pdv_spectrum_out {
 
 /* Launch options for batches; pass NULL for the tuned defaults. */
 typedef struct pdv_launch_opts {
-    int32_t block_size;          /* threads per block: 256, 512 or 1024; 0 = default */
+    int32_t block_size;          /* threads per block: 256, 512, 768 or 1024; 0 = default */
     int32_t blocks_per_cu;       /* persistent grid = blocks_per_cu x CUs; 0 = default */
     uint64_t packets_per_item;   /* work-item size; 0 = default */
     int32_t persistent;          /* 1 = persistent work queue, 0 = one block per item, -1 = default */

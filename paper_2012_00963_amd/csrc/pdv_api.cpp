@@ -389,16 +389,22 @@ void pdv::fill_desc(SetDesc& d, const pdv_params& p) {
 
 void pdv_ctx::default_opts(pdv_launch_opts& o, uint64_t total_packets, int n_sets, bool fp64) const {
     (void)n_sets;
-    if (o.block_size <= 0) o.block_size = tuned.block_size > 0 ? tuned.block_size : 512;
-    if (o.blocks_per_cu <= 0) o.blocks_per_cu = tuned.blocks_per_cu > 0 ? tuned.blocks_per_cu : 4;
+    // measured on the large case: FP32 runs best as two 768-thread blocks
+    // per CU (six waves per SIMD), FP64 as one 1024-thread block per CU
+    if (o.block_size <= 0) o.block_size = tuned.block_size > 0 ? tuned.block_size : (fp64 ? 1024 : 768);
+    if (o.blocks_per_cu <= 0) o.blocks_per_cu = tuned.blocks_per_cu > 0 ? tuned.blocks_per_cu : (fp64 ? 1 : 2);
     if (o.persistent < 0) o.persistent = tuned.persistent >= 0 ? tuned.persistent : 1;
     if (o.guide_bits == 0) o.guide_bits = tuned.guide_bits;
     // measured on the large case: 12 for FP32 transport; FP64 is fastest
     // tallying every round
     if (o.retire_batch == 0) o.retire_batch = tuned.retire_batch > 0 ? tuned.retire_batch : (fp64 ? 1 : 12);
     if (o.packets_per_item == 0) {
+        // three large items per block, rounded up so that the item count
+        // does not spill into a further round: every item ends with a block
+        // barrier that waits for the block's longest packet, and the pull of
+        // the last items evens out the blocks' finishing times
         uint64_t grid = (uint64_t)n_cu * (uint64_t)o.blocks_per_cu;
-        uint64_t ppi = total_packets / (grid * 4 + 1);
+        uint64_t ppi = (total_packets + 3 * grid - 1) / (3 * grid);
         ppi = std::max<uint64_t>(ppi, 1024);
         ppi = std::min<uint64_t>(ppi, 1ull << 18);
         o.packets_per_item = tuned.packets_per_item > 0 ? tuned.packets_per_item : ppi;
@@ -424,8 +430,8 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
     uint64_t total = 0;
     for (int i = 0; i < n; ++i) total += sets[i].n_packets;
     default_opts(o, total, n, precision == PDV_FP64);
-    if (o.block_size != 256 && o.block_size != 512 && o.block_size != 1024)
-        return fail(PDV_EINVAL, "block_size must be 256, 512 or 1024");
+    if (o.block_size != 256 && o.block_size != 512 && o.block_size != 768 && o.block_size != 1024)
+        return fail(PDV_EINVAL, "block_size must be 256, 512, 768 or 1024");
     if (o.guide_bits != 0 && (o.guide_bits < MIN_GUIDE_BITS || o.guide_bits > GUIDE_BITS))
         return fail(PDV_EINVAL, "guide_bits must be 0 or %d..%d", MIN_GUIDE_BITS, GUIDE_BITS);
     if (o.retire_batch < 1 || o.retire_batch > 64) return fail(PDV_EINVAL, "retire_batch must be 0 or 1..64");
@@ -988,8 +994,9 @@ extern "C" const char* pdv_build_id(void) { return PDV_BUILD_ID; }
 
 extern "C" int pdv_set_launch_defaults(pdv_ctx* ctx, const pdv_launch_opts* o) {
     if (!ctx || !o) return PDV_EINVAL;
-    if (o->block_size != 0 && o->block_size != 256 && o->block_size != 512 && o->block_size != 1024)
-        return ctx->fail(PDV_EINVAL, "block_size must be 256, 512 or 1024");
+    if (o->block_size != 0 && o->block_size != 256 && o->block_size != 512 && o->block_size != 768 &&
+        o->block_size != 1024)
+        return ctx->fail(PDV_EINVAL, "block_size must be 256, 512, 768 or 1024");
     if (o->blocks_per_cu < 0 || o->blocks_per_cu > 64) return ctx->fail(PDV_EINVAL, "blocks_per_cu out of range");
     if (o->packets_per_item > (1ull << 31)) return ctx->fail(PDV_EINVAL, "packets_per_item out of range");
     if (o->guide_bits != 0 && (o->guide_bits < MIN_GUIDE_BITS || o->guide_bits > GUIDE_BITS))
@@ -1056,7 +1063,7 @@ extern "C" int pdv_autotune(pdv_ctx* ctx, const pdv_params* sets, int32_t n, int
     // launch shapes with the default guide resolution, then every guide
     // resolution for the best shape (the table layout stage)
     std::vector<pdv_launch_opts> cands;
-    for (int bs : {256, 512, 1024}) {
+    for (int bs : {256, 512, 768, 1024}) {
         for (uint64_t ppi : {1ull << 12, 1ull << 14, 1ull << 16, 1ull << 18}) {
             for (int bpc : {1, 2, 4, 8}) cands.push_back(pdv_launch_opts{bs, bpc, ppi, 1, 0, 0, 0});
             cands.push_back(pdv_launch_opts{bs, 1, ppi, 0, 0, 0, 0});

@@ -236,8 +236,11 @@ __device__ __forceinline__ void flush_lane_acc(LaneAcc& a, uint64_t* tally, int 
     a = LaneAcc{0, 0, 0, 0, 0, 0, 0};
 }
 
+// FP32: at most 80 VGPRs so that six waves share a SIMD (three 512-thread
+// blocks per CU), which hides more latency than the few spills cost;
+// FP64 keeps four waves (its spills at six cost more than they gain).
 template <typename Real, bool LIST>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 6 : 4, 8)))
 transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ tables,
                  uint64_t* __restrict__ tallies, const WorkItem* __restrict__ items, int n_items,
                  uint32_t* __restrict__ queue, int persistent, int max_layers, int max_cells, int max_bins,

@@ -569,6 +569,15 @@ def _autotune(self, sets: list, repeats: int = 3, cache_path: str | None = None)
 Context.autotune = _autotune
 
 
+def _reset_launch_defaults(self):
+    """Forget a tuned launch shape: the library's built-in defaults apply."""
+    self.lib.pdv_set_launch_defaults.argtypes = [ctypes.c_void_p, ctypes.POINTER(LaunchOpts)]
+    self._check(self.lib.pdv_set_launch_defaults(self.h, ctypes.byref(LaunchOpts(0, 0, 0, -1, 0, 0, 0))))
+
+
+Context.reset_launch_defaults = _reset_launch_defaults
+
+
 class PeakParams(ctypes.Structure):
     _fields_ = [("v_lo", ctypes.c_double), ("v_hi", ctypes.c_double), ("n_bins", ctypes.c_int32),
                 ("keep_modes", ctypes.c_int32), ("v_fs", ctypes.c_double), ("search_lo", ctypes.c_double),
