@@ -209,36 +209,38 @@ __device__ __forceinline__ void hg_angle(const SetConst<Real>& c, Real u, Real& 
     st = M<Real>::sqrt(s2 > (Real)0.0 ? s2 : (Real)0.0);
 }
 
-struct LaneAcc {             // per-lane accumulators, reduced across the wave at flush
+// Event counters: packets, exits and detections are wave-uniform (counted
+// from ballots when the wave retires packets); collisions, surface hits and
+// the absorbed weight (fixed point) are per-lane sums, reduced across the
+// wave when the block changes set or retires.
+struct WaveAcc {
+    uint64_t packets, exits, detected;
+};
+struct LaneAcc {
     uint64_t abs_particle, abs_surface;
-    uint32_t packets, collisions, surface, exits, detected;
+    uint32_t collisions, surface;
 };
 
-__device__ __forceinline__ void flush_lane_acc(LaneAcc& a, uint64_t* tally, int n_bins) {
+__device__ __forceinline__ void flush_acc(LaneAcc& a, WaveAcc& w, uint64_t* tally, int n_bins) {
     const uint64_t s_ap = wave_sum_u64(a.abs_particle);
     const uint64_t s_as = wave_sum_u64(a.abs_surface);
-    const uint64_t c_p = wave_sum_u64(a.packets);
     const uint64_t c_c = wave_sum_u64(a.collisions);
     const uint64_t c_s = wave_sum_u64(a.surface);
-    const uint64_t c_e = wave_sum_u64(a.exits);
-    const uint64_t c_d = wave_sum_u64(a.detected);
     if (lane_id() == 0) {
         unsigned long long* sk = (unsigned long long*)(tally + tw_sinks(n_bins));
-        unsigned long long* ct = (unsigned long long*)(tally + tw_counts(n_bins));
         if (s_ap) atomicAdd(sk + SK_ABS_PARTICLE, (unsigned long long)s_ap);
         if (s_as) atomicAdd(sk + SK_ABS_SURFACE, (unsigned long long)s_as);
-        if (c_p) atomicAdd(ct + C_PACKETS, (unsigned long long)c_p);
+        unsigned long long* ct = (unsigned long long*)(tally + tw_counts(n_bins));
+        if (w.packets) atomicAdd(ct + C_PACKETS, (unsigned long long)w.packets);
         if (c_c) atomicAdd(ct + C_COLLISIONS, (unsigned long long)c_c);
         if (c_s) atomicAdd(ct + C_SURFACE, (unsigned long long)c_s);
-        if (c_e) atomicAdd(ct + C_EXITS, (unsigned long long)c_e);
-        if (c_d) atomicAdd(ct + C_DETECTED, (unsigned long long)c_d);
+        if (w.exits) atomicAdd(ct + C_EXITS, (unsigned long long)w.exits);
+        if (w.detected) atomicAdd(ct + C_DETECTED, (unsigned long long)w.detected);
     }
-    a = LaneAcc{0, 0, 0, 0, 0, 0, 0};
+    a = LaneAcc{0, 0, 0, 0};
+    w = WaveAcc{0, 0, 0};
 }
 
-// FP32: at most 80 VGPRs so that six waves share a SIMD (three 512-thread
-// blocks per CU), which hides more latency than the few spills cost;
-// FP64 keeps four waves (its spills at six cost more than they gain).
 template <typename Real, bool LIST>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 6 : 4, 8)))
 transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ tables,
@@ -266,12 +268,13 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
     const int nthr = blockDim.x;
     const int lane = lane_id();
     int cur_set = -1;
-    LaneAcc acc = LaneAcc{0, 0, 0, 0, 0, 0, 0};
+    LaneAcc acc = LaneAcc{0, 0, 0, 0};
+    WaveAcc wacc = WaveAcc{0, 0, 0};
 
     auto flush_set = [&](int set) {
         const SetDesc& d = descs[set];
         uint64_t* tally = tallies + d.tally_offset;
-        flush_lane_acc(acc, tally, d.n_bins);
+        flush_acc(acc, wacc, tally, d.n_bins);
         __syncthreads();
         unsigned long long* gW = (unsigned long long*)(tally + tw_w(d.n_bins));
         unsigned long long* gW2 = (unsigned long long*)(tally + tw_w2(d.n_bins));
@@ -348,6 +351,9 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
             // wave's range, claiming a new range from the item when it runs out.
             const uint64_t idle = __ballot(st != ST_ALIVE);
             if (idle == ~0ull || (!exhausted && (int)__popcll(idle) >= retire_min)) {
+                wacc.packets += (uint64_t)__popcll(__ballot(st >= ST_EXIT));
+                wacc.exits += (uint64_t)__popcll(__ballot(st == ST_EXIT));
+                wacc.detected += (uint64_t)__popcll(__ballot(st == ST_EXIT && mu >= c.cos_cone));
                 if (st >= ST_EXIT) {
                     // ---- the packet's tally: one terminal slot of the LDS histogram ----
                     const bool detected = st == ST_EXIT && mu >= c.cos_cone;
@@ -406,11 +412,8 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                         acc.abs_surface += fs;
                         acc.abs_particle += (4294967296ull - fw) - fs;
                     }
-                    acc.packets += 1;
                     acc.collisions += (uint32_t)n_sc;
                     acc.surface += (uint32_t)n_surf;
-                    acc.exits += st == ST_EXIT ? 1u : 0u;
-                    acc.detected += detected ? 1u : 0u;
                     st = ST_EMPTY;
                 }
                 uint64_t empty = __ballot(st == ST_EMPTY);
@@ -445,7 +448,11 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                 if (__ballot(st == ST_ALIVE) == 0ull) break;
             }
             if (st == ST_ALIVE) {
-            const Block4 X = philox10(k, (uint32_t)pid, (uint32_t)(pid >> 32), c.stream, c.k0, c.k1);
+            // the key enters opaquely each event, so the ten round keys are
+            // recomputed on the scalar unit rather than held in 20 SGPRs
+            uint32_t key0 = c.k0, key1 = c.k1;
+            asm volatile("" : "+s"(key0), "+s"(key1));
+            const Block4 X = philox10(k, (uint32_t)pid, (uint32_t)(pid >> 32), c.stream, key0, key1);
             k += 1;
             const Real u0 = unit_open<Real>(X.x);
             const Real u1 = unit_open<Real>(X.y);
