@@ -19,13 +19,15 @@ Also reported on the same JSON line:
                 against FP32, plus the legs (--legs, all by default):
                 "batched" (512 uneven sets in one FP32 launch vs serial FP64
                 launches), "peaks" (beta / optical-depth sweep and the
-                Sec. III.C peak analysis of every spectrum), "spectrogram"
+                Sec. III.C peak analysis of every spectrum), "sensitivity"
+                (the Sec. III.A one-at-a-time ejecta variations through the
+                front end, with their main and free-surface peaks), "spectrogram"
                 (256 frames x 1e6 packets, beat record, STFT), "serve" (60 s
                 Poisson request stream with continuous batching vs serial
                 FP64, p50/p99 latency).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                       [--legs batched,peaks,spectrogram,serve|none] [--serve-duration S]
+                       [--legs batched,peaks,sensitivity,spectrogram,serve|none] [--serve-duration S]
                        [--serve-only] [--calib-copy BYTES]
 """
 from __future__ import annotations
@@ -197,6 +199,36 @@ def peaks_leg(ctx, batched_spectra=None):
     return r
 
 
+def sensitivity_leg(ctx):
+    """Sensitivity study (Sec. III.A): 18 ejecta varied one parameter at a
+    time around the paper's base case, stated through the front end
+    (eq. 8-10, 20-21), 1e6 packets each in one FP32 batch, then the peak
+    analysis of every spectrum; the main-peak position and the free-surface
+    peak relative to it for each variation."""
+    import numpy as np
+    from paper_2012_00963_amd import workloads
+    entries = workloads.sensitivity_study()
+    t0 = time.perf_counter()
+    pe = [ctx.ejecta_params(e["ejecta"], e["template"]) for e in entries]
+    t1 = time.perf_counter()
+    params = [p for p, _ in pe]
+    res = ctx.spectrum_batch(params)
+    t2 = time.perf_counter()
+    W = np.array([r["W"] for r in res]) / params[0]["n_packets"]
+    v_fs = entries[0]["ejecta"]["v_fs"]
+    p0 = params[0]
+    peaks, S = ctx.peak_analysis(W, p0["v_lo"], p0["v_hi"], v_fs, 40, 1.05 * v_fs, p0["v_hi"], want_smoothed=True)
+    t3 = time.perf_counter()
+    b_fs = int(v_fs / ((p0["v_hi"] - p0["v_lo"]) / p0["n_bins"]))
+    rows = [{"vary": e["vary"], "value": e["value"], "tau_ext": round(q["tau_total"], 3),
+             "x_peak": round(pk["x_peak"], 4), "status": pk["status"],
+             "surface_over_main": round(float(s[b_fs] / pk["value"]), 4),
+             "detected_per_packet": round(float(w.sum()), 5)}
+            for e, (_, q), pk, s, w in zip(entries, pe, peaks, S, W)]
+    return {"sets": len(entries), "packets_per_set": p0["n_packets"], "front_end_s": t1 - t0,
+            "transport_s": t2 - t1, "peak_analysis_s": t3 - t2, "rows": rows}
+
+
 def spectrogram_leg(ctx):
     """Time-resolved case: 256 frames x 1e6 packets, 20 GS/s beat record of
     1e5 samples with FP64 phase, 4096-point Hann STFT at 80% overlap."""
@@ -284,8 +316,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
-    ap.add_argument("--legs", default="batched,peaks,spectrogram,serve",
-                    help="comma list of extra legs: batched,peaks,spectrogram,serve (or none)")
+    ap.add_argument("--legs", default="batched,peaks,sensitivity,spectrogram,serve",
+                    help="comma list of extra legs: batched,peaks,sensitivity,spectrogram,serve (or none)")
     ap.add_argument("--cpu-sample", type=int, default=20_000_000, help="packets in the oracle sample")
     ap.add_argument("--calib-copy", type=int, default=0, help="only run a copy of this many bytes")
     ap.add_argument("--serve-duration", type=float, default=60.0, help="seconds of the serving trace")
@@ -400,6 +432,8 @@ def main(argv=None):
         spectra_512 = out["extra"]["batched"].pop("_spectra")
     if "peaks" in legs:
         out["extra"]["peaks"] = peaks_leg(ctx, spectra_512)
+    if "sensitivity" in legs:
+        out["extra"]["sensitivity"] = sensitivity_leg(ctx)
     if "spectrogram" in legs:
         out["extra"]["spectrogram"] = spectrogram_leg(ctx)
     if "serve" in legs:

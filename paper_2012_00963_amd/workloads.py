@@ -118,6 +118,35 @@ def peak_sweep(betas=(4.0, 6.0, 8.0, 10.0, 12.0, 14.0), taus=(10.0, 20.0, 40.0),
     return sets
 
 
+def sensitivity_study(n_packets: int = 1_000_000) -> list[dict]:
+    """One-at-a-time variations of an ejecta around the paper's base case
+    of its sensitivity study (Sec. III.A: beta 10, area mass 20 mg/cm^2,
+    median diameter 1.5 um, sigma 0.5): beta, area mass, median diameter
+    and size width each varied with the others fixed.  Sn-like stand-in:
+    density 7287 kg/m^3, refractive index 2.0+4.0i at 1550 nm (the paper
+    does not give Sn's), free surface at 2 km/s, slab to 5 km/s, every
+    photon leaving the top counted (cone pi/2), 1024 bins on 0-5 km/s.
+    Each entry: {"vary", "value", "ejecta", "template"}; stream = index,
+    seed 7."""
+    base = dict(area_mass=0.2, density=7287.0, beta=10.0, v_fs=2000.0, v_top=5000.0, d_median=1.5e-6,
+                sigma_ln=0.5, d_min=0.05e-6, d_max=60e-6, n_size_nodes=256, m_re=2.0, m_im=4.0,
+                wavelength=WAVELENGTH, g_back=0.6)
+    study = [("beta", "beta", [5.0, 7.5, 10.0, 12.5, 15.0]),
+             ("area_mass_mg_cm2", "area_mass", [2.0, 5.0, 10.0, 20.0, 40.0]),
+             ("d_median_um", "d_median", [0.75, 1.5, 3.0, 6.0]),
+             ("sigma_ln", "sigma_ln", [0.3, 0.5, 0.7, 0.9])]
+    scale = {"area_mass": 1e-2, "d_median": 1e-6}
+    out = []
+    for label, key, values in study:
+        for v in values:
+            e = dict(base)
+            e[key] = v * scale.get(key, 1.0)
+            t = large_mie(n_packets)
+            t.update(cone_half_angle=math.pi / 2, v_lo=0.0, v_hi=5000.0, n_bins=1024, seed=7, stream=len(out))
+            out.append({"vary": label, "value": v, "ejecta": e, "template": t})
+    return out
+
+
 def serving_trace(rate: float = 200.0, duration: float = 60.0, seed: int = 5,
                   p_spectrogram: float = 0.25, sg_frames: int = 64,
                   packets_scale: float = 1.0) -> list[dict]:
