@@ -212,9 +212,9 @@ int pdv_device_count(int* count);
 /*
  * Validate a parameter set without running it.  Returns PDV_OK or
  * PDV_EINVAL with the reason in pdv_last_error (ctx may be NULL: then the
- * reason is not kept).  Checks: n_bins >= 1, v_hi > v_lo, v_top >= v_bottom,
+ * reason is not kept).  Checks: 1 <= n_bins <= 4096, v_hi > v_lo, v_top >= v_bottom,
  * tau_total >= 0, 0 <= albedo, surface_albedo <= 1, |hg_g| < 1, cone in
- * (0, pi/2], 1 <= n_layers <= 8192, 16 <= n_angles <= 4096, Mie sizes
+ * (0, pi/2], 1 <= n_layers <= 4096, 16 <= n_angles <= 4096, Mie sizes
  * 0 < d_min < d_median, d_median < d_max, sigma_ln > 0, 8 <= n_size_nodes <= 1024,
  * 0 <= max_orders <= 100000, n_packets < 2^32 (fixed-point headroom: every
  * tally stays below 2^64).

@@ -341,6 +341,7 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
         bool exhausted = false;              // the item has no packets left for this wave
         uint32_t w_next = 0, w_end = 0;      // wave-private range of item-local packet indices
         uint64_t pid = 0;
+        uint32_t q0 = 0, q1 = 0;             // the packet's fixed first-round Philox words
         uint32_t k = 0;
         int n_sc = 0, n_surf = 0;
         Real T = 0, mu = -1, w = 1, big = 0, small = 0, abs_s = 0;
@@ -384,8 +385,7 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                     }
                     if constexpr (LIST) {
                         if (detected) {
-                            const Block4 P = philox10(0xffffffffu, (uint32_t)pid, (uint32_t)(pid >> 32), c.stream,
-                                                      c.k0, c.k1);
+                            const Block4 P = philox10_event(0xffffffffu, q0, q1, c.stream ^ c.k1, c.k0, c.k1);
                             const SetDesc& d = descs[set];
                             const uint64_t m = __ballot(1);
                             const int leader = __ffsll((unsigned long long)m) - 1;
@@ -438,6 +438,7 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                         if (rank < take) {
                             st = ST_ALIVE;
                             pid = pid0 + w_next + rank;
+                            philox_packet_words((uint32_t)pid, (uint32_t)(pid >> 32), c.k0, q0, q1);
                             k = 0; n_sc = 0; n_surf = 0;
                             T = 0; mu = -1; w = 1; big = 0; small = 0; abs_s = 0;
                         }
@@ -452,7 +453,7 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
             // recomputed on the scalar unit rather than held in 20 SGPRs
             uint32_t key0 = c.k0, key1 = c.k1;
             asm volatile("" : "+s"(key0), "+s"(key1));
-            const Block4 X = philox10(k, (uint32_t)pid, (uint32_t)(pid >> 32), c.stream, key0, key1);
+            const Block4 X = philox10_event(k, q0, q1, c.stream ^ key1, key0, key1);
             k += 1;
             const Real u0 = unit_open<Real>(X.x);
             const Real u1 = unit_open<Real>(X.y);

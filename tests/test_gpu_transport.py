@@ -193,6 +193,27 @@ def test_empty_and_degenerate(ctx):
     assert conservation_exact(g1, 1)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_maximum_sizes(ctx, oracle_mc, precision):
+    # the largest tables and histogram the library takes: LDS staging beyond
+    # 64 KiB, the coarsest guides the LDS budget allows
+    from oracle import tables
+    rng = np.random.Generator(np.random.PCG64(29))
+    dens = rng.uniform(0.0, 1.0, 4096) ** 4
+    th = tables.angle_grid(4096)
+    phase = tables.hg_phase(0.6, th) + 0.02
+    p = _c1(precision=precision, density_kind=wl.DENSITY_TABLE, density=dens, n_layers=4096, tau_total=2.0,
+            phase_kind=wl.PHASE_TABLE, phase=phase, n_angles=4096, albedo=0.85, n_bins=4096,
+            cone_half_angle=math.radians(60), n_packets=200_000)
+    g, o = _run_both(ctx, oracle_mc, p)
+    ll = ctx.last_launch()
+    assert ll["lds_bytes"] > 65536, ll
+    assert conservation_exact(g, p["n_packets"])
+    m = assert_parity(g, o, p["n_packets"])
+    if precision == 1:
+        assert m["l1"] < 1e-9, m
+
+
 def test_validation_errors(ctx):
     from paper_2012_00963_amd import pdv
     for bad in (dict(n_bins=0), dict(v_hi=-1.0), dict(hg_g=1.0), dict(cone_half_angle=0.0),
