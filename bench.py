@@ -48,13 +48,13 @@ if ROOT not in sys.path:
 # Issue-slot cost of one scatter event in the transport kernel, counted from
 # the algorithm in full-rate 32-bit lane operations: Philox4x32-10 (rounds
 # 2-10: 9 x (two 32x32->64 multiplies, which issue at half rate = 4 slots,
-# + 4 xor) = 72; round 1: the product of the packet-id word is fixed per
-# packet, so one multiply + 1 xor = 3), three uniforms (12), flight (3),
-# branch tests (4), layer/angle lookup (13), angle sampling (11), azimuth
-# (1), rotation (8), Doppler (6), weight (4): 137, of which 6 are
-# transcendental (log, rcp, 2 sqrt, sin/cos) at quarter rate (+3 slots
-# each): 155 slots.
-SLOTS_PER_EVENT = 155
+# + two three-way xors, one instruction each) = 54; round 1: the product of
+# the packet-id word is fixed per packet, so one multiply + 1 xor = 3),
+# three uniforms (12), flight (3), branch tests (4), layer/angle lookup (13),
+# angle sampling (11), azimuth (1), rotation (8), Doppler (6), weight (4):
+# 119, of which 6 are transcendental (log, rcp, 2 sqrt, sin/cos) at quarter
+# rate (+3 slots each): 137 slots.
+SLOTS_PER_EVENT = 137
 FP32_FLOPS_PER_EVENT = 40
 # VALU issue peak in full-rate lane operations/s: the FP32 vector peak of
 # 157.3 TFLOP/s is 78.6 T lane-FMAs/s = 256 CUs x 128 lanes per clock x

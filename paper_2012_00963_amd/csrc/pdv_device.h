@@ -16,6 +16,13 @@ namespace pdv {
 // ---------------------------------------------------------------------------
 struct Block4 { uint32_t x, y, z, w; };
 
+// a ^ b ^ c in one instruction: gfx950's three-input bit operation with the
+// truth table of a three-way exclusive or (0x96); the compiler does not form
+// it from two xors by itself
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ Block4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                            uint32_t k0, uint32_t k1) {
     constexpr uint32_t MUL_A = 0xD2511F53u, MUL_B = 0xCD9E8D57u;
@@ -25,8 +32,8 @@ __device__ __forceinline__ Block4 philox10(uint32_t c0, uint32_t c1, uint32_t c2
         // one 32x32->64 multiply per product (a single v_mad_u64_u32)
         const uint64_t pa = (uint64_t)MUL_A * c0;
         const uint64_t pb = (uint64_t)MUL_B * c2;
-        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(pb >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(pa >> 32), c3, k1);
         c0 = n0; c1 = (uint32_t)pb; c2 = n2; c3 = (uint32_t)pa;
         k0 += BUMP_A; k1 += BUMP_B;
     }
@@ -57,8 +64,8 @@ __device__ __forceinline__ Block4 philox10_event(uint32_t k, uint32_t q0, uint32
     for (int r = 1; r < 10; ++r) {
         const uint64_t pa = (uint64_t)MUL_A * c0;
         const uint64_t pb = (uint64_t)MUL_B * c2;
-        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(pb >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(pa >> 32), c3, k1);
         c0 = n0; c1 = (uint32_t)pb; c2 = n2; c3 = (uint32_t)pa;
         k0 += BUMP_A; k1 += BUMP_B;
     }

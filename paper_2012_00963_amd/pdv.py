@@ -65,8 +65,9 @@ class Counters(ctypes.Structure):
 
 class SpectrumOut(ctypes.Structure):
     _fields_ = [
-        ("w_fx", ctypes.POINTER(ctypes.c_uint64)), ("w2_fx", ctypes.POINTER(ctypes.c_uint64)),
-        ("class_fx", ctypes.POINTER(ctypes.c_uint64)),
+        # uint64_t* in the ABI, declared as addresses so that a batch can
+        # point them into one buffer without a pointer object per array
+        ("w_fx", ctypes.c_void_p), ("w2_fx", ctypes.c_void_p), ("class_fx", ctypes.c_void_p),
         ("sinks_fx", ctypes.c_uint64 * 6),
         ("counters", Counters),
         ("albedo", ctypes.c_double), ("g", ctypes.c_double),
@@ -136,21 +137,29 @@ DEFAULTS = dict(wavelength=1550e-9, v_bottom=0.0, v_top=0.0, tau_total=0.0, dens
                 precision=FP32, n_packets=0, pid_begin=0, seed=0, stream=0, flags=0)
 
 
+_PARAM_NAMES = None
+
+
 def make_params(p: dict, keep: list) -> Params:
-    """Fill a pdv_params from a dict; arrays are kept alive in ``keep``."""
-    q = dict(DEFAULTS)
-    q.update({k: v for k, v in p.items() if k in DEFAULTS or k in ("density", "phase")})
-    c = Params()
-    for name, typ in Params._fields_:
+    """Fill a pdv_params from a dict (missing keys take DEFAULTS); arrays are
+    kept alive in ``keep``."""
+    global _PARAM_NAMES
+    if _PARAM_NAMES is None:
+        _PARAM_NAMES = [n for n, _ in Params._fields_]
+    vals = []
+    for name in _PARAM_NAMES:
         if name in ("density", "phase"):
             arr = p.get(name)
-            if arr is not None:
+            if arr is None:
+                vals.append(None)
+            else:
                 a = np.ascontiguousarray(arr, dtype=np.float64)
                 keep.append(a)
-                setattr(c, name, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
-            continue
-        setattr(c, name, q[name])
-    return c
+                vals.append(a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        else:
+            v = p.get(name)
+            vals.append(DEFAULTS[name] if v is None else v)
+    return Params(*vals)
 
 
 def _u64ptr(a):
@@ -176,13 +185,17 @@ class Result(dict):
         return v
 
 
+COUNTER_NAMES = tuple(n for n, _ in Counters._fields_)
+
+
 def _result(out: SpectrumOut, W, W2, C, n_bins):
-    sinks_fx = {n: int(out.sinks_fx[i]) for i, n in enumerate(SINK_NAMES)}
+    sinks_fx = dict(zip(SINK_NAMES, out.sinks_fx))
+    cnt = out.counters
     res = Result(
         w_fx=W, w2_fx=W2, sinks_fx=sinks_fx,
         sinks={n: v / SCALE for n, v in sinks_fx.items()},
-        counts={n: int(getattr(out.counters, n)) for n, _ in Counters._fields_},
-        albedo=float(out.albedo), g=float(out.g),
+        counts={n: getattr(cnt, n) for n in COUNTER_NAMES},
+        albedo=out.albedo, g=out.g,
     )
     res["sinks"]["detected"] = int(W.sum()) / SCALE     # exact: the bins sum below 2^64
     if C is not None:
@@ -242,20 +255,28 @@ class Context:
         n = len(sets)
         arr = (Params * n)()
         outs = (SpectrumOut * n)()
+        # every set's tallies are disjoint views of one buffer, which the
+        # library fills completely on success
+        per = 4 if class_tallies else 2
+        nbs = [int(p.get("n_bins", DEFAULTS["n_bins"])) for p in sets]
+        buf = np.empty(per * sum(nbs), dtype=np.uint64)
+        base = buf.ctypes.data
         bufs = []
+        off = 0
         for i, p in enumerate(sets):
-            q = dict(p)
             if class_tallies:
-                q["flags"] = int(q.get("flags", 0)) | FLAG_CLASS_TALLIES
-            arr[i] = make_params(q, keep)
-            nb = int(q["n_bins"])
-            W = np.zeros(nb, dtype=np.uint64)
-            W2 = np.zeros(nb, dtype=np.uint64)
-            C = np.zeros(2 * nb, dtype=np.uint64) if class_tallies else None
-            outs[i].w_fx, outs[i].w2_fx = _u64ptr(W), _u64ptr(W2)
-            if C is not None:
-                outs[i].class_fx = _u64ptr(C)
-            bufs.append((W, W2, C, nb))
+                p = dict(p, flags=int(p.get("flags", 0)) | FLAG_CLASS_TALLIES)
+            arr[i] = make_params(p, keep)
+            nb = nbs[i]
+            o = outs[i]
+            o.w_fx = base + 8 * off
+            o.w2_fx = base + 8 * (off + nb)
+            C = None
+            if class_tallies:
+                o.class_fx = base + 8 * (off + 2 * nb)
+                C = buf[off + 2 * nb:off + 4 * nb]
+            bufs.append((buf[off:off + nb], buf[off + nb:off + 2 * nb], C, nb))
+            off += per * nb
         o = None
         if opts:
             o = LaunchOpts(int(opts.get("block_size", 0)), int(opts.get("blocks_per_cu", 0)),
@@ -302,7 +323,7 @@ def _spectrogram(self, p: dict, sg: dict, want_signal: bool = False, want_spectr
         nb = int(p["n_bins"])
         W, W2 = np.zeros(nb, dtype=np.uint64), np.zeros(nb, dtype=np.uint64)
         spec = SpectrumOut()
-        spec.w_fx, spec.w2_fx = _u64ptr(W), _u64ptr(W2)
+        spec.w_fx, spec.w2_fx = W.ctypes.data, W2.ctypes.data
         o.spectrum = ctypes.pointer(spec)
     if want_lists:
         stride = int(s.list_capacity)
@@ -456,7 +477,7 @@ class Server:
         nb = int(p["n_bins"])
         W, W2 = np.zeros(nb, dtype=np.uint64), np.zeros(nb, dtype=np.uint64)
         out = SpectrumOut()
-        out.w_fx, out.w2_fx = _u64ptr(W), _u64ptr(W2)
+        out.w_fx, out.w2_fx = W.ctypes.data, W2.ctypes.data
         keep += [out, W, W2]
         req.out = ctypes.pointer(out)
         sg_bufs = None
