@@ -8,7 +8,9 @@ or constant generators.
 
 Contents (each function cites the passage of Shi et al., arXiv 2012.00963,
 that it follows):
-  pdv_oracle.cpp  scalar FP64 transport + tally (Sec. II.B, eq. 4, 7-19)
+  pdv_oracle.cpp  scalar FP64 transport + tally (Sec. II.B, eq. 4, 7-19), and
+                  the paper's literal procedure (fixed-step marching,
+                  acceptance-rejection angles; Sec. II.B steps 2-7)
   mc.py           ctypes driver; builds tables with tables.py
   tables.py       layer depths (eq. 8, 20), log-normal quadrature (eq. 21),
                   size-averaged Mie optics (eq. 11-14), integer phase CDF

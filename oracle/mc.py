@@ -86,6 +86,11 @@ def lib():
         _lib.oracle_scatter_direction.argtypes = [ctypes.POINTER(_Params), ctypes.c_double,
                                                   ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
         _lib.oracle_scatter_direction.restype = ctypes.c_int
+        _lib.oracle_run_literal.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(_Out)]
+        _lib.oracle_run_literal.restype = ctypes.c_int
+        _lib.oracle_sample_scatter_ar.argtypes = [ctypes.POINTER(_Params), ctypes.c_uint64,
+                                                  ctypes.POINTER(ctypes.c_double)]
+        _lib.oracle_sample_scatter_ar.restype = ctypes.c_int
     return _lib
 
 
@@ -124,15 +129,8 @@ def set_tables(p: dict) -> dict:
     return out
 
 
-def run(p: dict, n_threads: int | None = None, pid_begin: int = 0, n_packets: int | None = None,
-        class_tallies: bool = False, list_capacity: int = 0, tabs: dict | None = None) -> dict:
-    """Run the FP64 oracle on parameter dict ``p``; returns tallies in
-    weight units (sums of packet weights)."""
-    if tabs is None:
-        tabs = set_tables(p)
-    if n_threads is None:
-        n_threads = os.cpu_count() or 1
-    nb = int(p["n_bins"])
+def _params(p: dict, tabs: dict, n_threads: int, pid_begin: int, n_packets):
+    """The C parameter block of one set; returns it with the arrays it points to."""
     T = np.ascontiguousarray(tabs["T"], dtype=np.float64)
     cp = _Params()
     cp.v_bottom, cp.v_top = float(p["v_bottom"]), float(p["v_top"])
@@ -156,7 +154,7 @@ def run(p: dict, n_threads: int | None = None, pid_begin: int = 0, n_packets: in
     cp.surface_law = int(p.get("surface_law", 0))
     cp.cos_cone = math.cos(float(p["cone_half_angle"]))
     cp.v_lo, cp.v_hi = float(p["v_lo"]), float(p["v_hi"])
-    cp.n_bins = nb
+    cp.n_bins = int(p["n_bins"])
     cp.max_orders = int(p.get("max_orders", 50))
     cp.weighting = int(p.get("weighting", 0))
     cp.pid_begin = int(pid_begin)
@@ -164,6 +162,19 @@ def run(p: dict, n_threads: int | None = None, pid_begin: int = 0, n_packets: in
     cp.seed = int(p["seed"])
     cp.stream = int(p.get("stream", 0))
     cp.n_threads = int(n_threads)
+    return cp, (T, cdf)
+
+
+def run(p: dict, n_threads: int | None = None, pid_begin: int = 0, n_packets: int | None = None,
+        class_tallies: bool = False, list_capacity: int = 0, tabs: dict | None = None) -> dict:
+    """Run the FP64 oracle on parameter dict ``p``; returns tallies in
+    weight units (sums of packet weights)."""
+    if tabs is None:
+        tabs = set_tables(p)
+    if n_threads is None:
+        n_threads = os.cpu_count() or 1
+    nb = int(p["n_bins"])
+    cp, keep = _params(p, tabs, n_threads, pid_begin, n_packets)
 
     W = np.zeros(nb)
     W2 = np.zeros(nb)
@@ -199,6 +210,41 @@ def run(p: dict, n_threads: int | None = None, pid_begin: int = 0, n_packets: in
     return res
 
 
+def run_literal(p: dict, n_threads: int | None = None, n_packets: int | None = None,
+                class_tallies: bool = False, tabs: dict | None = None) -> dict:
+    """The paper's own procedure (Sec. II.B steps 2-7) on ``p``: fixed steps
+    of one layer thickness with a penetration test each (eq. 10), interaction
+    at the end of a step that is not crossed, polar angle by
+    acceptance-rejection.  Same outputs as ``run``; counts["flights"] holds
+    the steps taken.  Its own random stream: equal to ``run`` in
+    distribution only."""
+    if tabs is None:
+        tabs = set_tables(p)
+    if n_threads is None:
+        n_threads = os.cpu_count() or 1
+    nb = int(p["n_bins"])
+    cp, keep = _params(p, tabs, n_threads, 0, n_packets)
+    W, W2 = np.zeros(nb), np.zeros(nb)
+    out = _Out()
+    out.W, out.W2 = _dptr(W), _dptr(W2)
+    Ws = Wsf = None
+    if class_tallies:
+        Ws, Wsf = np.zeros(nb), np.zeros(nb)
+        out.W_single, out.W_surface = _dptr(Ws), _dptr(Wsf)
+    if lib().oracle_run_literal(ctypes.byref(cp), ctypes.byref(out)) != 0:
+        raise ValueError("oracle_run_literal rejected the parameters")
+    res = {
+        "W": W, "W2": W2,
+        "sinks": {n: float(out.sinks[i]) for i, n in enumerate(SINK_NAMES)},
+        "counts": {n: int(out.counts[i]) for i, n in enumerate(COUNT_NAMES)},
+        "albedo": tabs["albedo"], "g": tabs["g"],
+    }
+    res["sinks"]["detected"] = float(W.sum())
+    if class_tallies:
+        res["W_single"], res["W_surface"] = Ws, Wsf
+    return res
+
+
 def sample_scatter_cos(n: int, hg_g: float | None = None, cdf=None, seed: int = 7, stream: int = 0):
     """cos(Theta) from the oracle's scattering sampler alone (HG when
     ``hg_g`` is given, else the integer-CDF table), n draws."""
@@ -216,6 +262,27 @@ def sample_scatter_cos(n: int, hg_g: float | None = None, cdf=None, seed: int = 
     cp.stream = int(stream)
     out = np.zeros(int(n))
     if lib().oracle_sample_scatter(ctypes.byref(cp), int(n), _dptr(out)) != 0:
+        raise ValueError("bad sampler arguments")
+    return out
+
+
+def sample_scatter_cos_ar(n: int, hg_g: float | None = None, cdf=None, seed: int = 7, stream: int = 0):
+    """cos(Theta) from the acceptance-rejection sampler of the paper's own
+    procedure (Sec. II.B step 4), n draws."""
+    cp = _Params()
+    keep = None
+    if cdf is not None:
+        keep = np.ascontiguousarray(cdf, dtype=np.uint64)
+        cp.phase_kind = 1
+        cp.n_angles = len(keep)
+        cp.cdf = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+    else:
+        cp.phase_kind = 0
+        cp.hg_g = float(hg_g)
+    cp.seed = int(seed)
+    cp.stream = int(stream)
+    out = np.zeros(int(n))
+    if lib().oracle_sample_scatter_ar(ctypes.byref(cp), int(n), _dptr(out)) != 0:
         raise ValueError("bad sampler arguments")
     return out
 

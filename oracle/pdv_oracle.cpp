@@ -439,3 +439,298 @@ int oracle_scatter_direction(const oracle_params* p, double mu_in, uint64_t n, d
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// The paper's own procedure as a fidelity mode (Sec. II.B, steps 2-7).
+//
+// Where the estimator above samples each free flight exactly, the paper moves
+// every photon by a fixed step of one thousandth of the cloud height (one
+// layer thickness) along its direction and lets it cross that step with the
+// Beer-Lambert probability of eq. 10 (one random number per step); a photon
+// that does not cross interacts at the end of its step (eq. 11).  The polar
+// angle comes from acceptance-rejection against the phase function (step 4).
+// The surface, Doppler, weighting and detector rules are those above.
+//
+// This mode draws a variable number of random numbers, so it uses its own
+// stream (consecutive words of the packet's Philox blocks, counter word 3 =
+// stream with its top bit flipped) and agrees with the exact estimator in
+// distribution only: tests compare the two statistically.  Reading of the
+// step: its length is (v_top - v_bottom) / n_layers in the velocity
+// coordinate, cut at the slab's faces; a photon running parallel to the
+// layers sees the extinction of its layer along the whole step.
+// ===========================================================================
+namespace {
+
+struct WordStream {
+    uint32_t key[2];
+    uint32_t pid_lo, pid_hi, stream;
+    uint32_t k = 0, pos = 4;
+    uint32_t buf[4];
+    uint32_t next() {
+        if (pos == 4) {
+            const uint32_t ctr[4] = {k++, pid_lo, pid_hi, stream};
+            philox4x32_10(ctr, key, buf);
+            pos = 0;
+        }
+        return buf[pos++];
+    }
+    double uniform() { return uniform_from_word(next()); }
+};
+
+// Cumulative extinction depth from the top at velocity coordinate zeta
+// (linear inside each layer).
+double depth_at_zeta(const oracle_params& p, double zeta) {
+    const double dz = (p.v_top - p.v_bottom) / p.n_layers;
+    const double x = (p.v_top - zeta) / dz;
+    if (x <= 0.0) return 0.0;
+    if (x >= (double)p.n_layers) return p.T[p.n_layers];
+    int j = (int)std::floor(x);
+    if (j > p.n_layers - 1) j = p.n_layers - 1;
+    return p.T[j] + (x - (double)j) * (p.T[j + 1] - p.T[j]);
+}
+
+// Extinction per unit of the velocity coordinate in the layer holding zeta.
+double extinction_at_zeta(const oracle_params& p, double zeta) {
+    const double dz = (p.v_top - p.v_bottom) / p.n_layers;
+    int j = (int)std::floor((p.v_top - zeta) / dz);
+    if (j < 0) j = 0;
+    if (j > p.n_layers - 1) j = p.n_layers - 1;
+    return (p.T[j + 1] - p.T[j]) / dz;
+}
+
+// Acceptance-rejection sampler of the polar angle.  Table: the density in
+// theta is constant inside each cell and proportional to the cell's mass, so
+// theta is proposed uniform on [0, pi] and kept with probability
+// mass(cell) / max mass.  Henyey-Greenstein: cos(theta) is proposed uniform
+// on [-1, 1] and kept with probability p(cos) / p_max, p_max = p(sign g).
+struct ArSampler {
+    std::vector<double> mass;
+    double mass_max = 0.0;
+    explicit ArSampler(const oracle_params& p) {
+        if (p.phase_kind == PHASE_TABLE) {
+            mass.resize(p.n_angles - 1);
+            for (int j = 0; j + 1 < p.n_angles; ++j) {
+                mass[j] = (double)(p.cdf[j + 1] - p.cdf[j]);
+                if (mass[j] > mass_max) mass_max = mass[j];
+            }
+        }
+    }
+    void sample(const oracle_params& p, WordStream& rs, double* c, double* s) const {
+        if (p.phase_kind == PHASE_TABLE) {
+            const int n_cells = p.n_angles - 1;
+            for (;;) {
+                const double x = rs.uniform() * (double)n_cells;
+                int j = (int)x;
+                if (j > n_cells - 1) j = n_cells - 1;
+                if (rs.uniform() * mass_max < mass[j]) {
+                    const double theta = x * (PI / (double)n_cells);
+                    *c = std::cos(theta);
+                    *s = std::sin(theta);
+                    return;
+                }
+            }
+        }
+        const double g = p.hg_g;
+        const double pmax = g == 0.0 ? 1.0 : 1.0 / ((1.0 - std::fabs(g)) * (1.0 - std::fabs(g)) * (1.0 - std::fabs(g)));
+        for (;;) {
+            const double ct = 2.0 * rs.uniform() - 1.0;
+            const double base = 1.0 + g * g - 2.0 * g * ct;
+            const double dens = g == 0.0 ? 1.0 : 1.0 / (base * std::sqrt(base));
+            if (rs.uniform() * pmax < dens) {
+                *c = ct;
+                const double s2 = (1.0 - ct) * (1.0 + ct);
+                *s = std::sqrt(s2 > 0.0 ? s2 : 0.0);
+                return;
+            }
+        }
+    }
+};
+
+void tally_exit(const oracle_params& p, double w, double v, int n_sc, int n_surf, double mu, Tally& t) {
+    t.counts[CNT_EXITS] += 1;
+    if (mu < p.cos_cone) {
+        t.sinks[SINK_UNDETECTED] += w;
+        return;
+    }
+    t.counts[CNT_DETECTED] += 1;
+    const double dv = (p.v_hi - p.v_lo) / (double)p.n_bins;
+    const double b = std::floor((v - p.v_lo) / dv);
+    if (b < 0.0) {
+        t.sinks[SINK_UNDER] += w;
+    } else if (b >= (double)p.n_bins) {
+        t.sinks[SINK_OVER] += w;
+    } else {
+        const int ib = (int)b;
+        t.W[ib] += w;
+        t.W2[ib] += w * w;
+        if (!t.Ws.empty() && n_sc == 1 && n_surf == 0) t.Ws[ib] += w;
+        if (!t.Wsurf.empty() && n_sc == 0 && n_surf == 1) t.Wsurf[ib] += w;
+    }
+}
+
+void run_packet_literal(const oracle_params& p, const ArSampler& ar, uint64_t pid, Tally& t) {
+    WordStream rs;
+    rs.key[0] = (uint32_t)(p.seed & 0xffffffffu);
+    rs.key[1] = (uint32_t)(p.seed >> 32);
+    rs.pid_lo = (uint32_t)(pid & 0xffffffffu);
+    rs.pid_hi = (uint32_t)(pid >> 32);
+    rs.stream = p.stream ^ 0x80000000u;
+    const double step = (p.v_top - p.v_bottom) / p.n_layers;
+
+    double zeta = p.v_top, mu = -1.0, w = 1.0, big = 0.0, small = 0.0;
+    int n_sc = 0, n_surf = 0;
+    t.counts[CNT_PACKETS] += 1;
+    for (;;) {
+        t.counts[CNT_FLIGHTS] += 1;
+        // one step along the direction, cut at the faces of the slab
+        double zeta_end = zeta + step * mu;
+        int face = 0;
+        if (zeta_end <= p.v_bottom) { zeta_end = p.v_bottom; face = -1; }
+        else if (zeta_end >= p.v_top) { zeta_end = p.v_top; face = 1; }
+        const double tau_step = std::fabs(mu) > 1e-12
+            ? std::fabs(depth_at_zeta(p, zeta_end) - depth_at_zeta(p, zeta)) / std::fabs(mu)
+            : step * extinction_at_zeta(p, zeta);
+        const bool crosses = rs.uniform() < std::exp(-tau_step);
+        zeta = zeta_end;
+        if (crosses) {
+            if (face == 1) {
+                tally_exit(p, w, big - small, n_sc, n_surf, mu, t);
+                return;
+            }
+            if (face == -1) {
+                // diffuse reflection at the moving free surface
+                t.counts[CNT_SURFACE] += 1;
+                const double u1 = rs.uniform();
+                double mu_new, one_minus_mu_new;
+                if (p.surface_law == SURFACE_LAMBERT) {
+                    const double r = std::sqrt(u1);
+                    mu_new = r;
+                    one_minus_mu_new = (1.0 - u1) / (1.0 + r);
+                } else {
+                    const double psi = 0.5 * PI * u1;
+                    const double sh = std::sin(0.5 * psi);
+                    mu_new = std::cos(psi);
+                    one_minus_mu_new = 2.0 * sh * sh;
+                }
+                if (p.weighting == WEIGHT_ANALOG) {
+                    if (rs.uniform() >= p.surface_albedo) {
+                        t.sinks[SINK_ABSORBED_SURFACE] += w;
+                        return;
+                    }
+                } else {
+                    t.sinks[SINK_ABSORBED_SURFACE] += w * (1.0 - p.surface_albedo);
+                    w *= p.surface_albedo;
+                }
+                big += 0.5 * p.v_surface * (1.0 - mu);
+                small += 0.5 * p.v_surface * one_minus_mu_new;
+                mu = mu_new;
+                n_surf += 1;
+            }
+            continue;
+        }
+        // interaction at the end of the step
+        t.counts[CNT_COLLISIONS] += 1;
+        if (n_sc == p.max_orders) {
+            t.sinks[SINK_TRUNCATED] += w;
+            return;
+        }
+        if (p.weighting == WEIGHT_ANALOG) {
+            if (rs.uniform() >= p.albedo) {
+                t.sinks[SINK_ABSORBED_PARTICLE] += w;
+                return;
+            }
+        } else {
+            t.sinks[SINK_ABSORBED_PARTICLE] += w * (1.0 - p.albedo);
+            w *= p.albedo;
+        }
+        n_sc += 1;
+        double cth, sth;
+        ar.sample(p, rs, &cth, &sth);
+        const double cphi = std::cos(2.0 * PI * rs.uniform());
+        double mu_new = mu * cth + std::sqrt((1.0 - mu) * (1.0 + mu)) * sth * cphi;
+        if (mu_new > 1.0) mu_new = 1.0;
+        if (mu_new < -1.0) mu_new = -1.0;
+        const double V = zeta;
+        big += 0.5 * V * (1.0 - mu);
+        small += 0.5 * V * (1.0 - mu_new);
+        mu = mu_new;
+    }
+}
+
+void run_range_literal(const oracle_params* p, const ArSampler* ar, uint64_t begin, uint64_t end, Tally* t) {
+    for (uint64_t pid = begin; pid < end; ++pid) run_packet_literal(*p, *ar, pid, *t);
+}
+
+}  // namespace
+
+extern "C" {
+
+// The literal procedure over the requested packets; the same outputs as
+// oracle_run (no detected list; counts[flights] holds the steps taken).
+int oracle_run_literal(const oracle_params* p, oracle_out* out) {
+    if (!p || !out || p->n_bins < 1 || p->n_layers < 1 || !p->T || !out->W || !out->W2) return -1;
+    if (p->phase_kind == PHASE_TABLE && (!p->cdf || p->n_angles < 2)) return -1;
+    if (p->phase_kind == PHASE_HG && !(std::fabs(p->hg_g) < 1.0)) return -1;
+    if (!(p->v_top > p->v_bottom)) return -1;
+    const ArSampler ar(*p);
+    int nt = p->n_threads > 0 ? p->n_threads : 1;
+    if ((uint64_t)nt > p->n_packets && p->n_packets > 0) nt = (int)p->n_packets;
+    if (nt < 1) nt = 1;
+    std::vector<Tally> tallies(nt);
+    for (auto& t : tallies) {
+        t.W.assign(p->n_bins, 0.0);
+        t.W2.assign(p->n_bins, 0.0);
+        if (out->W_single) t.Ws.assign(p->n_bins, 0.0);
+        if (out->W_surface) t.Wsurf.assign(p->n_bins, 0.0);
+    }
+    std::vector<std::thread> threads;
+    for (int i = 0; i < nt; ++i) {
+        uint64_t b = p->pid_begin + p->n_packets * (uint64_t)i / (uint64_t)nt;
+        uint64_t e = p->pid_begin + p->n_packets * (uint64_t)(i + 1) / (uint64_t)nt;
+        threads.emplace_back(run_range_literal, p, &ar, b, e, &tallies[i]);
+    }
+    for (auto& th : threads) th.join();
+    for (int b = 0; b < p->n_bins; ++b) {
+        out->W[b] = 0.0; out->W2[b] = 0.0;
+        if (out->W_single) out->W_single[b] = 0.0;
+        if (out->W_surface) out->W_surface[b] = 0.0;
+    }
+    for (int s = 0; s < N_SINKS; ++s) out->sinks[s] = 0.0;
+    for (int c = 0; c < N_COUNTS; ++c) out->counts[c] = 0;
+    for (int i = 0; i < nt; ++i) {
+        const Tally& t = tallies[i];
+        for (int b = 0; b < p->n_bins; ++b) {
+            out->W[b] += t.W[b];
+            out->W2[b] += t.W2[b];
+            if (out->W_single) out->W_single[b] += t.Ws[b];
+            if (out->W_surface) out->W_surface[b] += t.Wsurf[b];
+        }
+        for (int s = 0; s < N_SINKS; ++s) out->sinks[s] += t.sinks[s];
+        for (int c = 0; c < N_COUNTS; ++c) out->counts[c] += t.counts[c];
+    }
+    out->list_count = 0;
+    return 0;
+}
+
+// Test hook: cos(Theta) from the acceptance-rejection sampler alone, n draws
+// from one word stream (packet id 0).
+int oracle_sample_scatter_ar(const oracle_params* p, uint64_t n, double* cos_out) {
+    if (!p || !cos_out) return -1;
+    if (p->phase_kind == PHASE_TABLE && (!p->cdf || p->n_angles < 2)) return -1;
+    if (p->phase_kind == PHASE_HG && !(std::fabs(p->hg_g) < 1.0)) return -1;
+    const ArSampler ar(*p);
+    WordStream rs;
+    rs.key[0] = (uint32_t)(p->seed & 0xffffffffu);
+    rs.key[1] = (uint32_t)(p->seed >> 32);
+    rs.pid_lo = 0;
+    rs.pid_hi = 0;
+    rs.stream = p->stream ^ 0x80000000u;
+    for (uint64_t i = 0; i < n; ++i) {
+        double c, s;
+        ar.sample(*p, rs, &c, &s);
+        cos_out[i] = c;
+    }
+    return 0;
+}
+
+}  // extern "C"
