@@ -377,6 +377,8 @@ void pdv::fill_desc(SetDesc& d, const pdv_params& p) {
     d.thr_surface = thr(p.surface_albedo);
     d.albedo_one = d.albedo >= 1.0;
     d.surface_one = p.surface_albedo >= 1.0;
+    d.albedo_f = (float)d.albedo;
+    d.surface_albedo_f = (float)p.surface_albedo;
     d.flags = (p.flags & PDV_FLAG_CLASS_TALLIES) ? SF_CLASS : 0u;
     d.n_layers = p.n_layers;
     d.phase_kind = p.phase_kind == PDV_PHASE_HG ? PH_HG : PH_TABLE;

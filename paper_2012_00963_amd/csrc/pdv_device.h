@@ -78,8 +78,11 @@ template <typename Real>
 __device__ __forceinline__ Real unit_open(uint32_t x) {
     if constexpr (sizeof(Real) == 4) {
         // 1 + m 2^-23 from the top 23 bits as the mantissa, minus (1 - 2^-24):
-        // exact (Sterbenz), and equal to (2m + 1) 2^-24
-        return __uint_as_float(0x3f800000u | (x >> 9)) - 0.99999994039535522461f;
+        // exact (Sterbenz), and equal to (2m + 1) 2^-24.  The exponent bits
+        // 0x3f800000 = 0x7f << 23 come in with the shift as the high word of
+        // a funnel shift (one v_alignbit_b32).
+        const uint32_t bits = __builtin_amdgcn_alignbit(0x7fu, x, 9u);
+        return __uint_as_float(bits) - 0.99999994039535522461f;
     } else {
         return (Real)(((x >> 9) << 1) | 1u) * (Real)5.9604644775390625e-08;
     }

@@ -89,6 +89,10 @@ struct alignas(16) SetDesc {
     int32_t albedo_one;         // (device for Mie) 1 if albedo >= 1
     int32_t surface_one;
     int32_t uniform_density;    // 1: zeta is linear in depth, no table search
+    // the two albedos rounded to FP32 (albedo_f: device for Mie): the FP32
+    // kernel selects between them per lane, from scalar registers
+    float albedo_f;
+    float surface_albedo_f;
 };
 
 struct WorkItem {

@@ -363,6 +363,7 @@ mie_phase_kernel(const PhaseJob* __restrict__ jobs, int n_jobs, int n_nodes, con
             SetDesc& d = descs[jobs[g0 + t].set];
             const double alb = sca / ext;
             d.albedo = alb;
+            d.albedo_f = (float)alb;
             d.albedo_one = alb >= 1.0;
             const double th = floor(alb * 4294967296.0);
             d.thr_albedo = (uint32_t)(th > 4294967295.0 ? 4294967295.0 : (th < 0.0 ? 0.0 : th));
@@ -496,6 +497,7 @@ __global__ void copy_desc_fields_kernel(SetDesc* d, const int* __restrict__ src,
     const int s = src[i];
     if (s == i) return;
     d[i].albedo = d[s].albedo;
+    d[i].albedo_f = d[s].albedo_f;
     d[i].thr_albedo = d[s].thr_albedo;
     d[i].albedo_one = d[s].albedo_one;
     d[i].g_mean = d[s].g_mean;

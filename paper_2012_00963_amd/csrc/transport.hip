@@ -99,8 +99,13 @@ __device__ __forceinline__ SetConst<Real> load_const(const SetDesc& d) {
     c.dzeta = (Real)d.dzeta;
     c.zeta_per_tau = (Real)d.zeta_per_tau;
     c.v_surface = (Real)d.v_surface;
-    c.surface_albedo = (Real)d.surface_albedo;
-    c.albedo = (Real)d.albedo;
+    if constexpr (sizeof(Real) == 4) {
+        c.surface_albedo = d.surface_albedo_f;
+        c.albedo = d.albedo_f;
+    } else {
+        c.surface_albedo = d.surface_albedo;
+        c.albedo = d.albedo;
+    }
     c.cos_cone = (Real)d.cos_cone;
     c.hg_a = (Real)d.hg_a;
     c.hg_b = (Real)d.hg_b;
