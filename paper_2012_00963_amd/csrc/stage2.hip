@@ -37,8 +37,40 @@ struct SynthFrame {
 constexpr int SYNTH_CHUNK = 1024;       // entries staged per block
 constexpr int SYNTH_THREADS = 256;
 
+// NQ samples per thread, spaced by the block size, over the staged entries.
+template <int NQ>
+__device__ __forceinline__ void synth_samples(const SynthFrame& F, int base, int ne, const double* s_r,
+                                              const double* s_ph, const float* s_a, float* out) {
+    double nn[NQ];
+    float acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        nn[q] = (double)(F.s_begin + base + threadIdx.x + q * SYNTH_THREADS);
+        acc[q] = 0.f;
+    }
+    for (int i = 0; i < ne; ++i) {
+        const double r = s_r[i], ph = s_ph[i];
+        const float a = s_a[i];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            // fractional cycles in one v_fract_f64 (x - floor(x), exact; its
+            // clamp below 1 only matters where the FP32 rounding gives 1 anyway)
+            const double cyc = __builtin_amdgcn_fract(fma(r, nn[q], ph));
+            acc[q] = fmaf(a, __builtin_amdgcn_cosf((float)cyc), acc[q]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int j = base + threadIdx.x + q * SYNTH_THREADS;
+        if (j < F.s_count) out[j] = acc[q];
+    }
+}
+
 // Accumulate sqrt(w) cos(2 pi frac(r n + phi)) for the frame's samples over
-// one chunk of entries; r = 2 v / (lambda fs) cycles per sample.
+// one chunk of entries; r = 2 v / (lambda fs) cycles per sample.  A thread
+// takes up to four samples (sharing each entry read); the count is cut to
+// what the frame's samples need, so a frame of a few hundred samples does
+// not compute discarded ones.
 __global__ void __launch_bounds__(SYNTH_THREADS)
 synth_partial_kernel(const SynthFrame* __restrict__ frames, const ListEntry* __restrict__ entries,
                      double two_over_lambda_fs, int n_chunks, int max_samples, float* __restrict__ partial) {
@@ -59,27 +91,13 @@ synth_partial_kernel(const SynthFrame* __restrict__ frames, const ListEntry* __r
     }
     __syncthreads();
     float* out = partial + ((uint64_t)f * n_chunks + ch) * (uint64_t)max_samples;
-    // each thread owns up to four samples of the frame, sharing entry reads
     for (int base = 0; base < F.s_count; base += 4 * SYNTH_THREADS) {
-        double nn[4];
-        float acc[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) nn[q] = (double)(F.s_begin + base + threadIdx.x + q * SYNTH_THREADS);
-        for (int i = 0; i < ne; ++i) {
-            const double r = s_r[i], ph = s_ph[i];
-            const float a = s_a[i];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                double cyc = fma(r, nn[q], ph);
-                cyc -= floor(cyc);
-                acc[q] = fmaf(a, __builtin_amdgcn_cosf((float)cyc), acc[q]);
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int j = base + threadIdx.x + q * SYNTH_THREADS;
-            if (j < F.s_count) out[j] = acc[q];
-        }
+        const int left = F.s_count - base;
+        const int nq = left >= 4 * SYNTH_THREADS ? 4 : (left + SYNTH_THREADS - 1) / SYNTH_THREADS;
+        if (nq == 4) synth_samples<4>(F, base, ne, s_r, s_ph, s_a, out);
+        else if (nq == 3) synth_samples<3>(F, base, ne, s_r, s_ph, s_a, out);
+        else if (nq == 2) synth_samples<2>(F, base, ne, s_r, s_ph, s_a, out);
+        else synth_samples<1>(F, base, ne, s_r, s_ph, s_a, out);
     }
 }
 
