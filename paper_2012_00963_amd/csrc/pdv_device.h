@@ -23,28 +23,13 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
 
-__device__ __forceinline__ Block4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                           uint32_t k0, uint32_t k1) {
-    constexpr uint32_t MUL_A = 0xD2511F53u, MUL_B = 0xCD9E8D57u;
-    constexpr uint32_t BUMP_A = 0x9E3779B9u, BUMP_B = 0xBB67AE85u;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        // one 32x32->64 multiply per product (a single v_mad_u64_u32)
-        const uint64_t pa = (uint64_t)MUL_A * c0;
-        const uint64_t pb = (uint64_t)MUL_B * c2;
-        const uint32_t n0 = xor3((uint32_t)(pb >> 32), c1, k0);
-        const uint32_t n2 = xor3((uint32_t)(pa >> 32), c3, k1);
-        c0 = n0; c1 = (uint32_t)pb; c2 = n2; c3 = (uint32_t)pa;
-        k0 += BUMP_A; k1 += BUMP_B;
-    }
-    return Block4{c0, c1, c2, c3};
-}
-
-// The same generator with its first round split: counter word 2 (the
-// packet id's high half) and word 1 (its low half) are fixed for a packet,
-// so the first-round product of word 2 and the words it feeds are computed
-// once per packet (philox_packet_words); per event only the product of the
-// event counter k remains.  s3 = counter word 3 ^ k1.
+// The transport draws the block with counter (k, pid low, pid high, stream)
+// for event k of a packet.  Counter words 1 and 2 (the packet id) are fixed
+// for a packet, so the first round's product of word 2 and the words it
+// feeds are formed once per packet (philox_packet_words); per event only the
+// first-round product of the event counter k remains (philox10_event,
+// s3 = stream ^ k1).  Each product is one 32x32->64 multiply
+// (v_mad_u64_u32).
 __device__ __forceinline__ void philox_packet_words(uint32_t pid_lo, uint32_t pid_hi, uint32_t k0, uint32_t& q0,
                                                     uint32_t& q1) {
     const uint64_t pb = (uint64_t)0xCD9E8D57u * pid_hi;
