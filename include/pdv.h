@@ -222,6 +222,27 @@ int pdv_device_count(int* count);
 int pdv_validate(struct pdv_ctx* ctx, const pdv_params* p);
 
 /*
+ * Set tables alone (Sec. II.B eq. 7-8, 11-14; Sec. II.C eq. 20-21): builds
+ * one parameter set's device tables -- the cumulative extinction depth of
+ * each layer, and the phase CDF with its guide (tabulated law) or the
+ * size-averaged Mie optics of the truncated log-normal -- and reports what
+ * they hold, without transporting packets (n_packets is ignored).  The
+ * tables are rebuilt by every spectrum call; this call is for inspecting
+ * them (albedo and mean cosine of a Mie cloud, the realised optical depth).
+ * info: caller-owned output.  Errors: PDV_EINVAL (invalid parameters, NULL
+ * pointers), PDV_ESTATE (context without a device), PDV_EDEVICE.
+ */
+typedef struct {
+    double albedo;        /* single-scattering albedo the transport uses (Mie: size-averaged K_sca/K_ext) */
+    double g;             /* mean cosine of the sampled scattering law */
+    double tau_total;     /* last cumulative layer depth of the FP64 table (equals p->tau_total up to rounding) */
+    double tau_total_f32; /* the same depth in the FP32 table the FP32 transport reads */
+    int32_t n_layers;
+    int32_t n_cells;      /* angle cells of the phase CDF (n_angles - 1); 0 for Henyey-Greenstein */
+} pdv_table_info;
+int pdv_prepare(struct pdv_ctx* ctx, const pdv_params* p, pdv_table_info* info);
+
+/*
  * One spectrum (blocking).  Builds the set's tables on the device (layer
  * depths; Mie size average and phase CDF, or HG constants), transports
  * n_packets packets and copies the tallies to `out`.

@@ -720,6 +720,39 @@ extern "C" int pdv_spectrum(pdv_ctx* ctx, const pdv_params* p, pdv_spectrum_out*
     return ctx->run_batch(p, 1, out, nullptr, 0, false);
 }
 
+// Set tables alone: the batch path with no packets builds the tables; the
+// realised depth is read back from the set's table block.
+extern "C" int pdv_prepare(pdv_ctx* ctx, const pdv_params* p, pdv_table_info* info) {
+    if (!ctx) return PDV_EINVAL;
+    if (ctx->serve) return ctx->fail(PDV_ESTATE, "context is serving: submit requests instead");
+    if (!p || !info) return ctx->fail(PDV_EINVAL, "NULL parameters or output");
+    pdv_params q = *p;
+    q.n_packets = 0;
+    if (q.n_bins < 1 || q.n_bins > MAX_BINS) return ctx->fail(PDV_EINVAL, "n_bins must be 1..%d", MAX_BINS);
+    std::vector<uint64_t> w((size_t)q.n_bins), w2((size_t)q.n_bins);
+    pdv_spectrum_out out;
+    std::memset(&out, 0, sizeof out);
+    out.w_fx = w.data();
+    out.w2_fx = w2.data();
+    if (int r = ctx->run_batch(&q, 1, &out, nullptr, 0, false)) return r;
+    const uint8_t* tb = (const uint8_t*)ctx->tables.ptr + ctx->h_desc[0].tab_offset;
+    double t64 = 0.0;
+    float t32 = 0.f;
+    if (int r = ctx->hip_check(hipMemcpy(&t64, tb + TableLayout::T64 + 8ull * q.n_layers, 8, hipMemcpyDeviceToHost),
+                               "read layer table"))
+        return r;
+    if (int r = ctx->hip_check(hipMemcpy(&t32, tb + TableLayout::T32 + 4ull * q.n_layers, 4, hipMemcpyDeviceToHost),
+                               "read layer table"))
+        return r;
+    info->albedo = out.albedo;
+    info->g = out.g;
+    info->tau_total = t64;
+    info->tau_total_f32 = t32;
+    info->n_layers = q.n_layers;
+    info->n_cells = q.phase_kind == PDV_PHASE_HG ? 0 : q.n_angles - 1;
+    return PDV_OK;
+}
+
 extern "C" int pdv_spectrum_batch(pdv_ctx* ctx, const pdv_params* sets, int32_t n, pdv_spectrum_out* outs,
                                   const pdv_launch_opts* opts) {
     if (!ctx) return PDV_EINVAL;

@@ -74,6 +74,11 @@ class SpectrumOut(ctypes.Structure):
     ]
 
 
+class TableInfo(ctypes.Structure):
+    _fields_ = [("albedo", ctypes.c_double), ("g", ctypes.c_double), ("tau_total", ctypes.c_double),
+                ("tau_total_f32", ctypes.c_double), ("n_layers", ctypes.c_int32), ("n_cells", ctypes.c_int32)]
+
+
 class LaunchOpts(ctypes.Structure):
     _fields_ = [("block_size", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("packets_per_item", ctypes.c_uint64), ("persistent", ctypes.c_int32),
@@ -117,6 +122,7 @@ def load():
     lib.pdv_device_count.argtypes = [P(ctypes.c_int)]
     lib.pdv_validate.argtypes = [V, P(Params)]
     lib.pdv_spectrum.argtypes = [V, P(Params), P(SpectrumOut)]
+    lib.pdv_prepare.argtypes = [V, P(Params), P(TableInfo)]
     lib.pdv_spectrum_batch.argtypes = [V, P(Params), ctypes.c_int32, P(SpectrumOut), P(LaunchOpts)]
     lib.pdv_spectrogram.argtypes = [V, P(Params), P(SgParams), P(SgOut)]
     lib.pdv_beat_synthesize.argtypes = [V, ctypes.c_int32, P(ctypes.c_uint64), P(ctypes.c_float),
@@ -246,6 +252,15 @@ class Context:
     def validate(self, p: dict) -> int:
         keep = []
         return self.lib.pdv_validate(self.h, ctypes.byref(make_params(p, keep)))
+
+    def prepare(self, p: dict) -> dict:
+        """The set's device tables alone: albedo, mean cosine, realised
+        optical depth (FP64 and FP32 tables), layer and angle-cell counts."""
+        keep = []
+        cp = make_params(p, keep)
+        info = TableInfo()
+        self._check(self.lib.pdv_prepare(self.h, ctypes.byref(cp), ctypes.byref(info)))
+        return {n: getattr(info, n) for n, _ in TableInfo._fields_}
 
     def spectrum(self, p: dict, class_tallies: bool = False) -> dict:
         return self.spectrum_batch([p], class_tallies=class_tallies)[0]
