@@ -68,6 +68,16 @@ enum { PDV_FP32 = 0, PDV_FP64 = 1 };
 
 /* Flags of pdv_params.flags */
 #define PDV_FLAG_CLASS_TALLIES 1u   /* also tally the single-scattering and surface-only classes */
+/* w_fx, w2_fx (and class_fx) of this set's pdv_spectrum_out are device
+ * pointers on the context's device, allocated through the HIP runtime this
+ * library links (a framework that bundles its own HIP runtime keeps its
+ * allocations there, where this library cannot see them): the library
+ * writes the bins there on its stream, device to device, and has finished
+ * when the call returns; the scalar fields of pdv_spectrum_out stay host
+ * memory.  Accepted by pdv_spectrum and pdv_spectrum_batch only
+ * (pdv_spectrogram and pdv_submit reject it); a pointer that is not device
+ * memory of the context's device gives PDV_EINVAL before any work. */
+#define PDV_FLAG_DEVICE_OUTPUT 2u
 
 /*
  * One parameter set: the problem statement of Sec. II.
@@ -163,7 +173,8 @@ typedef struct pdv_counters {
 
 /*
  * Output of one spectrum.  w_fx and w2_fx: caller-owned host arrays of
- * n_bins entries receiving sum(w) and sum(w^2) per bin (x 2^32).  class_fx:
+ * n_bins entries receiving sum(w) and sum(w^2) per bin (x 2^32); device
+ * arrays instead when the set has PDV_FLAG_DEVICE_OUTPUT.  class_fx:
  * nullable; if given and PDV_FLAG_CLASS_TALLIES is set, 2*n_bins entries:
  * [0, n_bins) single-scattering paths (one particle scattering, no surface
  * hit), [n_bins, 2 n_bins) surface-only paths.  Conservation holds exactly:
@@ -406,7 +417,8 @@ typedef struct pdv_serve_stats {
 /* Start the scheduler thread (opts nullable).  PDV_ESTATE if already serving. */
 int pdv_serve_start(struct pdv_ctx* ctx, const pdv_serve_opts* opts);
 /* Queue a request; *ticket identifies it.  Thread-safe.  PDV_EINVAL (bad
- * parameters or beyond the serving limits), PDV_ENOMEM (larger than the
+ * parameters, beyond the serving limits, or PDV_FLAG_DEVICE_OUTPUT: served
+ * results are host arrays), PDV_ENOMEM (larger than the
  * whole memory budget), PDV_ESTATE (not serving or stopping). */
 int pdv_submit(struct pdv_ctx* ctx, const pdv_request* req, uint64_t* ticket);
 /* Status of a request: PDV_PENDING, or its final status (PDV_OK, PDV_EOVERFLOW,

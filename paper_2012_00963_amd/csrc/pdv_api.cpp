@@ -32,6 +32,7 @@ void launch_mie_basis(hipStream_t s, int n, int nmax, int n_angles, const void* 
 void launch_phase_cdf(hipStream_t s, int n_jobs, const void* jobs, int n_nodes, const void* info,
                       const double* basis, uint8_t* tables, SetDesc* descs, int n_angles);
 void launch_zero_u64(hipStream_t s, uint64_t* p, uint64_t n);
+void launch_copy_jobs(hipStream_t s, int n_jobs, const void* jobs, const uint64_t* src);
 void launch_copy_desc_fields(hipStream_t s, SetDesc* descs, const int* src, int n);
 hipError_t plan_transport(TransportShape& sh, int precision, bool list, int want_bits, int lds_per_block,
                           int lds_per_cu);
@@ -251,10 +252,19 @@ extern "C" void pdv_destroy(pdv_ctx* ctx) {
     delete ctx;
 }
 
+bool pdv_ctx::on_device(const void* ptr) {
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, ptr) != hipSuccess) {
+        (void)hipGetLastError();   // clear the query's error so no later check sees it
+        return false;
+    }
+    return (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged) && a.device == device;
+}
+
 void pdv_ctx::release_all() {
     DevBuf* all[] = {&descs, &tables, &tallies, &items, &queue, &layer_jobs, &phase_jobs, &density, &lists,
                      &list_counts, &mie_info, &mie_a, &mie_b, &mie_d, &mie_basis, &mie_gx, &mie_gw, &sg_entries,
-                     &sg_offsets, &sg_signal, &sg_map, &sg_frames, &sg_partial, &sg_tab, &dup_src, &n_items_dev, &pk_in, &pk_smooth, &pk_out, &ej_out};
+                     &sg_offsets, &sg_signal, &sg_map, &sg_frames, &sg_partial, &sg_tab, &dup_src, &n_items_dev, &copy_jobs, &pk_in, &pk_smooth, &pk_out, &ej_out};
     if (batch_gexec) (void)hipGraphExecDestroy(batch_gexec);
     batch_gexec = nullptr;
     batch_key = BatchGraphKey{};
@@ -424,6 +434,12 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
         if (int r = validate_params(this, &sets[i])) return r;
         if (sets[i].precision != precision) return fail(PDV_EINVAL, "all sets of a batch need one precision");
         if (outs && (!outs[i].w_fx || !outs[i].w2_fx)) return fail(PDV_EINVAL, "set %d: NULL w_fx or w2_fx", i);
+        if (sets[i].flags & PDV_FLAG_DEVICE_OUTPUT) {
+            if (!outs || list_capacity) return fail(PDV_EINVAL, "set %d: device outputs need a spectrum call", i);
+            const bool cls = outs[i].class_fx && (sets[i].flags & PDV_FLAG_CLASS_TALLIES);
+            if (!on_device(outs[i].w_fx) || !on_device(outs[i].w2_fx) || (cls && !on_device(outs[i].class_fx)))
+                return fail(PDV_EINVAL, "set %d: PDV_FLAG_DEVICE_OUTPUT needs device arrays on device %d", i, device);
+        }
     }
     if (int r = hip_check(hipSetDevice(device), "hipSetDevice")) return r;
 
@@ -622,6 +638,26 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
     if ((r = hip_check(hipEventRecord(ev_b, s), "event"))) return r;
 
     // ---- results ----
+    // bins of sets with device outputs go device to device into the caller's arrays
+    h_copy.clear();
+    if (outs) {
+        for (int i = 0; i < n; ++i) {
+            if (!(sets[i].flags & PDV_FLAG_DEVICE_OUTPUT)) continue;
+            const int nb = sets[i].n_bins;
+            const uint64_t t0 = h_desc[i].tally_offset;
+            h_copy.push_back(CopyJob{t0 + tw_w(nb), (uint64_t)nb, outs[i].w_fx});
+            h_copy.push_back(CopyJob{t0 + tw_w2(nb), (uint64_t)nb, outs[i].w2_fx});
+            if (outs[i].class_fx && (sets[i].flags & PDV_FLAG_CLASS_TALLIES))
+                h_copy.push_back(CopyJob{t0 + tw_class(nb), 2ull * nb, outs[i].class_fx});
+        }
+    }
+    if (!h_copy.empty()) {
+        if ((r = ensure(copy_jobs, sizeof(CopyJob) * h_copy.size(), "output copy jobs"))) return r;
+        if ((r = hip_check(H2D(copy_jobs.ptr, h_copy.data(), sizeof(CopyJob) * h_copy.size()), "copy jobs")))
+            return r;
+        launch_copy_jobs(s, (int)h_copy.size(), copy_jobs.ptr, (const uint64_t*)tallies.ptr);
+        if ((r = hip_check(hipGetLastError(), "device output copies"))) return r;
+    }
     h_tally.resize(tally_words_total);
     if ((r = hip_check(hipMemcpyAsync(h_tally.data(), tallies.ptr, 8 * tally_words_total, hipMemcpyDeviceToHost, s),
                        "copy tallies")))
@@ -699,9 +735,11 @@ int pdv_ctx::launch_batch_graph(const TransportShape& sh, int precision, bool li
 
 void pdv_ctx::unpack(const pdv_params& p, const SetDesc& d, const uint64_t* t, pdv_spectrum_out& o) {
     const int nb = p.n_bins;
-    std::memcpy(o.w_fx, t + tw_w(nb), 8ull * nb);
-    std::memcpy(o.w2_fx, t + tw_w2(nb), 8ull * nb);
-    if (o.class_fx && (p.flags & PDV_FLAG_CLASS_TALLIES)) std::memcpy(o.class_fx, t + tw_class(nb), 16ull * nb);
+    if (!(p.flags & PDV_FLAG_DEVICE_OUTPUT)) {   // device outputs were filled on the device
+        std::memcpy(o.w_fx, t + tw_w(nb), 8ull * nb);
+        std::memcpy(o.w2_fx, t + tw_w2(nb), 8ull * nb);
+        if (o.class_fx && (p.flags & PDV_FLAG_CLASS_TALLIES)) std::memcpy(o.class_fx, t + tw_class(nb), 16ull * nb);
+    }
     for (int k = 0; k < PDV_N_SINKS; ++k) o.sinks_fx[k] = t[tw_sinks(nb) + k];
     const uint64_t* c = t + tw_counts(nb);
     o.counters.packets = c[C_PACKETS];
@@ -862,6 +900,8 @@ extern "C" int pdv_spectrogram(pdv_ctx* ctx, const pdv_params* p, const pdv_sg_p
 
 int pdv_spectrogram_internal(pdv_ctx* ctx, const pdv_params* p, const pdv_sg_params* sg, pdv_sg_out* out) {
     if (!out || !out->map) return ctx->fail(PDV_EINVAL, "NULL spectrogram output map");
+    if (p && (p->flags & PDV_FLAG_DEVICE_OUTPUT))
+        return ctx->fail(PDV_EINVAL, "PDV_FLAG_DEVICE_OUTPUT is for pdv_spectrum and pdv_spectrum_batch only");
     if (int r = check_sg(ctx, sg)) return r;
     if (int r = validate_params(ctx, p)) return r;
     if (!(p->wavelength > 0.0)) return ctx->fail(PDV_EINVAL, "wavelength must be > 0");

@@ -84,6 +84,7 @@ struct pdv_ctx {
     // batch buffers
     DevBuf descs, tables, tallies, items, queue, layer_jobs, phase_jobs, density, lists, list_counts, dup_src;
     DevBuf n_items_dev;                  // item count read by graph replays
+    DevBuf copy_jobs;                    // device-to-device output copies
     DevBuf pk_in, pk_smooth, pk_out;     // peak analysis
     DevBuf ej_out;                       // ejecta front end
     int h_n_items = 0;
@@ -102,6 +103,7 @@ struct pdv_ctx {
 
     // host staging
     std::vector<pdv::SetDesc> h_desc;
+    std::vector<pdv::CopyJob> h_copy;    // device-output copies of the last batch
     std::vector<pdv::LayerJob> h_layer;
     std::vector<int> h_src;              // first set with the same tables
     std::vector<pdv::PhaseJob> h_phase;
@@ -121,6 +123,8 @@ struct pdv_ctx {
     ~pdv_ctx();
     int fail(int code, const char* fmt, ...);
     int hip_check(hipError_t e, const char* what);
+    // true if ptr is device (or managed) memory of this context's device
+    bool on_device(const void* ptr);
     int ensure(DevBuf& b, size_t bytes, const char* what);
     int ensure_mie_basis(const pdv_params& p);
     void default_opts(pdv_launch_opts& o, uint64_t total_packets, int n_sets, bool fp64) const;

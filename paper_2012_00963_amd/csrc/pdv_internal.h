@@ -95,6 +95,13 @@ struct alignas(16) SetDesc {
     float surface_albedo_f;
 };
 
+// One device-to-device copy of tally words into a caller's array.
+struct CopyJob {
+    uint64_t src_word;          // first word in the tally arena
+    uint64_t n_words;
+    uint64_t* dst;              // caller's device array
+};
+
 struct WorkItem {
     uint32_t set;
     uint32_t pad;

@@ -509,6 +509,12 @@ __global__ void zero_u64_kernel(uint64_t* p, uint64_t n) {
         p[i] = 0ull;
 }
 
+// Copy tally words into callers' device arrays: one block per copy job.
+__global__ void copy_jobs_kernel(const CopyJob* __restrict__ jobs, const uint64_t* __restrict__ src) {
+    const CopyJob J = jobs[blockIdx.x];
+    for (uint64_t i = threadIdx.x; i < J.n_words; i += blockDim.x) J.dst[i] = src[J.src_word + i];
+}
+
 }  // namespace pdv
 
 // ---- host launchers ----
@@ -563,6 +569,11 @@ hipError_t launch_ejecta(hipStream_t s, int n_nodes, const void* info, const Eje
 void launch_copy_desc_fields(hipStream_t s, SetDesc* descs, const int* src, int n) {
     if (n <= 0) return;
     hipLaunchKernelGGL(copy_desc_fields_kernel, dim3((n + 255) / 256), dim3(256), 0, s, descs, src, n);
+}
+
+void launch_copy_jobs(hipStream_t s, int n_jobs, const void* jobs, const uint64_t* src) {
+    if (n_jobs <= 0) return;
+    hipLaunchKernelGGL(copy_jobs_kernel, dim3((unsigned)n_jobs), dim3(256), 0, s, (const CopyJob*)jobs, src);
 }
 
 void launch_zero_u64(hipStream_t s, uint64_t* p, uint64_t n) {

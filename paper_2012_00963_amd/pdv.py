@@ -25,6 +25,7 @@ STATUS = {0: "PDV_OK", 1: "PDV_PENDING", -1: "PDV_EINVAL", -2: "PDV_ENOMEM", -3:
 SINK_NAMES = ("under", "over", "undetected", "absorbed_particle", "absorbed_surface", "truncated")
 FP32, FP64 = 0, 1
 FLAG_CLASS_TALLIES = 1
+FLAG_DEVICE_OUTPUT = 2
 SCALE = 4294967296.0
 
 
@@ -262,6 +263,32 @@ class Context:
         self._check(self.lib.pdv_prepare(self.h, ctypes.byref(cp), ctypes.byref(info)))
         return {n: getattr(info, n) for n, _ in TableInfo._fields_}
 
+    def spectrum_batch_device(self, sets: list, outputs: list, opts: dict | None = None) -> list:
+        """Spectra whose bins go to device arrays: outputs[i] = (w_ptr, w2_ptr)
+        device addresses of n_bins uint64 each (e.g. tensor.data_ptr()).
+        Returns the host fields (sinks, counts, albedo, g) per set."""
+        keep = []
+        n = len(sets)
+        arr = (Params * n)()
+        outs = (SpectrumOut * n)()
+        for i, p in enumerate(sets):
+            arr[i] = make_params(dict(p, flags=int(p.get("flags", 0)) | FLAG_DEVICE_OUTPUT), keep)
+            outs[i].w_fx, outs[i].w2_fx = int(outputs[i][0]), int(outputs[i][1])
+        o = None
+        if opts:
+            o = LaunchOpts(int(opts.get("block_size", 0)), int(opts.get("blocks_per_cu", 0)),
+                           int(opts.get("packets_per_item", 0)), int(opts.get("persistent", -1)),
+                           int(opts.get("use_graph", 0)), int(opts.get("guide_bits", 0)),
+                           int(opts.get("retire_batch", 0)))
+        self._check(self.lib.pdv_spectrum_batch(self.h, arr, n, outs, ctypes.byref(o) if o else None))
+        res = []
+        for i in range(n):
+            sinks_fx = dict(zip(SINK_NAMES, outs[i].sinks_fx))
+            cnt = outs[i].counters
+            res.append({"sinks_fx": sinks_fx, "counts": {k: getattr(cnt, k) for k in COUNTER_NAMES},
+                        "albedo": outs[i].albedo, "g": outs[i].g})
+        return res
+
     def spectrum(self, p: dict, class_tallies: bool = False) -> dict:
         return self.spectrum_batch([p], class_tallies=class_tallies)[0]
 
@@ -485,7 +512,14 @@ class Server:
                 self.lib.pdv_destroy(self._own)
             raise PdvError(rc, msg)
 
+    def _handle(self):
+        # a stopped session that owned its host context has destroyed it
+        if self.h is None:
+            raise PdvError(-6, "serving session stopped")
+        return self.h
+
     def submit(self, p: dict, sg: dict | None = None) -> Ticket:
+        self._handle()
         keep = []
         req = Request()
         req.params = make_params(p, keep)
@@ -519,27 +553,29 @@ class Server:
     def poll(self, tk: Ticket, wait_ms: int = 0) -> int:
         if tk.status != PDV_PENDING:
             return tk.status
-        rc = self.lib.pdv_poll(self.h, tk.ticket, int(wait_ms))
+        rc = self.lib.pdv_poll(self._handle(), tk.ticket, int(wait_ms))
         if rc != PDV_PENDING:
             tk.status = rc
         return rc
 
     def cancel(self, tk: Ticket) -> int:
-        return self.lib.pdv_cancel(self.h, tk.ticket)
+        return self.lib.pdv_cancel(self._handle(), tk.ticket)
 
     def stats(self) -> dict:
         s = ServeStats()
-        rc = self.lib.pdv_serve_report(self.h, ctypes.byref(s))
+        rc = self.lib.pdv_serve_report(self._handle(), ctypes.byref(s))
         if rc != 0:
             raise PdvError(rc, "stats")
         return {n: getattr(s, n) for n, _ in ServeStats._fields_}
 
     def stop(self, drain: bool = True) -> int:
-        rc = self.lib.pdv_serve_stop(self.h, 1 if drain else 0)
-        self.last_error = self.lib.pdv_last_error(self.h).decode()
+        h = self._handle()
+        rc = self.lib.pdv_serve_stop(h, 1 if drain else 0)
+        self.last_error = self.lib.pdv_last_error(h).decode()
         if self._own:
             self.lib.pdv_destroy(self._own)
             self._own = None
+            self.h = None          # the handle died with the owned context
         return rc
 
 
