@@ -64,7 +64,7 @@ FP32_PEAK_TFLOPS = 157.3
 
 METRIC = "scatter events/s; spectra/s batched-FP32 vs plain-FP64 at <=1% error; p99 lat"
 KERNEL_SOURCES = ("paper_2012_00963_amd/csrc/transport.hip", "paper_2012_00963_amd/csrc/pdv_device.h",
-                  "paper_2012_00963_amd/csrc/pdv_internal.h")
+                  "paper_2012_00963_amd/csrc/pdv_internal.h", "paper_2012_00963_amd/build.py")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "transport_large_mie_hbm_traffic.txt")
 
 

@@ -445,6 +445,15 @@ int pdv_create_host(struct pdv_ctx** out);
  */
 int pdv_last_launch(const struct pdv_ctx* ctx, float* kernel_ms, int32_t* grid, int32_t* block,
                     int32_t* n_items, int32_t* guide_bits, int32_t* lds_bytes);
+/*
+ * Kernel kind of the last transport launch: -1 the generic kernel (reads
+ * each set's kind), 1 the FP32 kernel for tabulated or Mie laws on layered
+ * clouds, 2 the FP32 kernel for Henyey-Greenstein laws on uniform slabs
+ * (both with the paper's surface law, implicit capture and no class
+ * tallies).  A launch runs a specialised kernel when all its sets share
+ * that kind; every kernel gives the same tallies.  -1 for a NULL ctx.
+ */
+int pdv_last_launch_kind(const struct pdv_ctx* ctx);
 
 /*
  * ---------------------------------------------------------------------------

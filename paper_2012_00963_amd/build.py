@@ -29,7 +29,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-I" + 
 def build_id() -> str:
     """Hash of every source and header the library is built from."""
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)) + ["../../include/pdv.h"]:
+    for name in sorted(os.listdir(CSRC)) + ["../../include/pdv.h", "../build.py"]:
         path = os.path.normpath(os.path.join(CSRC, name))
         if os.path.isfile(path):
             with open(path, "rb") as f:
@@ -44,9 +44,21 @@ def hipcc() -> str:
     return exe
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), "-c"] + COMMON + DEVICE + ['-DPDV_BUILD_ID="' + build_id() + '"', os.path.join(CSRC, src), "-o", obj]
+# Compilation units: (source, object, extra flags).  transport.hip is built
+# twice: its FP32 kernels and the host dispatch without implicit
+# floating-point contraction (the fused operations are written out, so every
+# specialised FP32 kernel performs the same roundings and gives bit-identical
+# tallies), and its FP64 kernels with the compiler's usual contraction.
+UNITS = [("transport.hip", "transport.o", ["-ffp-contract=off"]),
+         ("transport.hip", "transport_fp64.o", ["-DPDV_TRANSPORT_FP64"])] + \
+        [(s, os.path.splitext(s)[0] + ".o", []) for s in SOURCES if s != "transport.hip"]
+
+
+def _compile(unit) -> str:
+    src, obj_name, extra = unit
+    obj = os.path.join(BUILD_DIR, obj_name)
+    cmd = ([hipcc(), "-c"] + COMMON + DEVICE + extra + ['-DPDV_BUILD_ID="' + build_id() + '"',
+           os.path.join(CSRC, src), "-o", obj])
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -61,8 +73,8 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(UNITS))) as ex:
+        objs = list(ex.map(_compile, UNITS))
     tmp = OUT + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + ["-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)

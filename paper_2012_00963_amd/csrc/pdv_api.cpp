@@ -605,6 +605,15 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
     sh.max_cells = max_cells;
     sh.max_bins = max_bins;
     sh.retire_min = o.retire_batch;
+    // FP32 sets that all share a specialised kind run that kind's kernel
+    sh.kind = KIND_GENERIC;
+    if (precision == PDV_FP32) {
+        const int k0 = set_kind(h_desc[0]);
+        bool same = true;
+        for (int i = 1; i < n && same; ++i) same = set_kind(h_desc[i]) == k0;
+        if (same && (k0 == KIND_TABLE_LAYERED || k0 == KIND_HG_UNIFORM)) sh.kind = k0;
+    }
+    last_kind = sh.kind;
     {
         hipError_t e = plan_transport(sh, precision, list_capacity > 0, o.guide_bits, lds_per_block, lds_per_cu);
         if (e == hipErrorInvalidValue)
@@ -688,6 +697,7 @@ int pdv_ctx::launch_batch_graph(const TransportShape& sh, int precision, bool li
     k.lds = sh.lds_bytes;
     k.guide_bits = sh.guide_bits;
     k.retire_min = sh.retire_min;
+    k.kind = sh.kind;
     k.max_layers = sh.max_layers;
     k.max_cells = sh.max_cells;
     k.max_bins = sh.max_bins;
@@ -797,6 +807,8 @@ extern "C" int pdv_spectrum_batch(pdv_ctx* ctx, const pdv_params* sets, int32_t 
     if (ctx->serve) return ctx->fail(PDV_ESTATE, "context is serving: submit requests instead");
     return ctx->run_batch(sets, n, outs, opts, 0, false);
 }
+
+extern "C" int pdv_last_launch_kind(const pdv_ctx* ctx) { return ctx ? ctx->last_kind : -1; }
 
 // Timing of the last transport launch (HIP events around the kernel on the
 // context stream), its grid and block, for benchmarks.

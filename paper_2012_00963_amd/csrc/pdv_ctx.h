@@ -48,11 +48,13 @@ struct TunedLaunch {
 // What a captured batch graph was recorded with.
 struct BatchGraphKey {
     int precision = -1, list = 0, persistent = 0, grid = 0, block = 0, lds = 0, guide_bits = 0, retire_min = 0;
+    int kind = -1;
     int max_layers = 0, max_cells = 0, max_bins = 0;
     void* ptr[8] = {};
     bool operator==(const BatchGraphKey& o) const {
         if (precision != o.precision || list != o.list || persistent != o.persistent || grid != o.grid ||
             block != o.block || lds != o.lds || guide_bits != o.guide_bits || retire_min != o.retire_min ||
+            kind != o.kind ||
             max_layers != o.max_layers || max_cells != o.max_cells || max_bins != o.max_bins)
             return false;
         for (int i = 0; i < 8; ++i)
@@ -113,7 +115,7 @@ struct pdv_ctx {
 
     // last launch (benchmarks)
     float last_kernel_ms = 0.f;
-    int32_t last_grid = 0, last_block = 0, last_items = 0, last_guide_bits = 0, last_lds = 0;
+    int32_t last_grid = 0, last_block = 0, last_items = 0, last_guide_bits = 0, last_lds = 0, last_kind = -1;
     TunedLaunch tuned;
 
     // serving

@@ -82,6 +82,10 @@ __device__ __forceinline__ Real unit_open(uint32_t x) {
 template <typename Real> struct M;
 
 template <> struct M<float> {
+    // a * b + c with one rounding; the transport is compiled without
+    // implicit contraction, so every fused operation is written out and the
+    // arithmetic does not depend on how the compiler arranges the code
+    static __device__ __forceinline__ float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
     static __device__ __forceinline__ float neg_log(float u) {
         return -0.693147180559945309f * __builtin_amdgcn_logf(u);
     }
@@ -97,6 +101,9 @@ template <> struct M<float> {
 
 template <> struct M<double> {
     static constexpr double PI = 3.14159265358979323846;
+    // the FP64 kernels are compiled with contraction, which fuses this (an
+    // explicit ::fma call there cost scalar registers and spills)
+    static __device__ __forceinline__ double fma(double a, double b, double c) { return a * b + c; }
     static __device__ __forceinline__ double neg_log(double u) { return -::log(u); }
     static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
     static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }

@@ -118,6 +118,20 @@ struct alignas(16) ListEntry {
 
 enum SetFlags : uint32_t { SF_CLASS = 1u, SF_LIST = 2u };
 
+// Set kinds.  A launch whose sets all share one of the specialised kinds
+// runs a transport kernel with the kind's tests resolved at compile time
+// (fewer branches and scalar registers); any other launch runs the generic
+// kernel, which reads them from each set.  Both perform the same arithmetic.
+enum KindBits : int { KB_TABLE = 1, KB_UNIFORM = 2, KB_LAMBERT = 4, KB_ANALOG = 8, KB_CLASS = 16 };
+constexpr int KIND_GENERIC = -1;
+constexpr int KIND_TABLE_LAYERED = KB_TABLE;      // tabulated or Mie law, layered cloud, paper surface law, implicit
+constexpr int KIND_HG_UNIFORM = KB_UNIFORM;       // Henyey-Greenstein law, uniform slab, paper surface law, implicit
+inline int set_kind(const SetDesc& d) {
+    return (d.phase_kind == PH_TABLE ? KB_TABLE : 0) | (d.uniform_density ? KB_UNIFORM : 0) |
+           (d.surface_law == 1 ? KB_LAMBERT : 0) | (d.weighting == 1 ? KB_ANALOG : 0) |
+           ((d.flags & SF_CLASS) ? KB_CLASS : 0);
+}
+
 // Launch shape of the transport kernel (host side).
 struct TransportShape {
     int grid = 1, block = 512;
@@ -125,6 +139,7 @@ struct TransportShape {
     int guide_bits = GUIDE_BITS;                        // staged guide resolution
     int lds_bytes = 0;
     int retire_min = 12;                                // finished lanes per retire round
+    int kind = KIND_GENERIC;                            // kernel specialisation (FP32 only)
 };
 
 // Peak analysis (host-packed constants of one call) and its per-spectrum result.

@@ -138,16 +138,37 @@ __device__ __forceinline__ SetConst<Real> load_const(const SetDesc& d) {
     return c;
 }
 
+// Tests of the set's kind: read from the set (KIND < 0) or fixed at compile
+// time for a launch whose sets all share the kind.
+template <int KIND>
+struct Kind {
+    template <typename C> static __device__ __forceinline__ bool table(const C& c) {
+        if constexpr (KIND < 0) return c.phase_kind == PH_TABLE; else return (KIND & KB_TABLE) != 0;
+    }
+    template <typename C> static __device__ __forceinline__ bool uniform(const C& c) {
+        if constexpr (KIND < 0) return c.uniform_density != 0; else return (KIND & KB_UNIFORM) != 0;
+    }
+    template <typename C> static __device__ __forceinline__ bool lambert(const C& c) {
+        if constexpr (KIND < 0) return c.surface_law == 1; else return (KIND & KB_LAMBERT) != 0;
+    }
+    template <typename C> static __device__ __forceinline__ bool analog(const C& c) {
+        if constexpr (KIND < 0) return c.weighting == 1; else return (KIND & KB_ANALOG) != 0;
+    }
+    template <typename C> static __device__ __forceinline__ bool cls(const C& c) {
+        if constexpr (KIND < 0) return (c.flags & SF_CLASS) != 0; else return (KIND & KB_CLASS) != 0;
+    }
+};
+
 // Velocity coordinate at depth t.  Uniform density: zeta is linear in depth.
 // Otherwise the layer j with T[j] <= t < T[j+1] lies between the guide
 // entries of the cells just below and just above t x scale (padded by
 // GUIDE_MARGIN); the staged guide keeps every 2^gshift-th cell, so the
 // lower cell index rounds down and the upper one up.  zeta is linear inside
 // the layer.
-template <typename Real>
+template <typename Real, int KIND>
 __device__ __forceinline__ Real zeta_at(const SetConst<Real>& c, const Real* T, const uint16_t* lg, int gshift,
                                         Real t) {
-    if (c.uniform_density) return c.v_top - t * c.zeta_per_tau;
+    if (Kind<KIND>::uniform(c)) return M<Real>::fma(-t, c.zeta_per_tau, c.v_top);
     const Real x = t * c.lg_scale;
     int a = (int)(x - (Real)GUIDE_MARGIN);
     int b = (int)(x + (Real)GUIDE_MARGIN) + 1;
@@ -163,7 +184,7 @@ __device__ __forceinline__ Real zeta_at(const SetConst<Real>& c, const Real* T, 
         hi = le ? hi : mid - 1;
     }
     const Real frac = M<Real>::div(t - T[lo], T[lo + 1] - T[lo]);
-    return c.v_top - ((Real)lo + frac) * c.dzeta;
+    return M<Real>::fma(-((Real)lo + frac), c.dzeta, c.v_top);
 }
 
 // Scattering angle (cos, sin) from the integer CDF: the cell is the last j
@@ -202,11 +223,11 @@ template <typename Real>
 __device__ __forceinline__ void hg_angle(const SetConst<Real>& c, Real u, Real& ct, Real& st) {
     Real x;
     if (c.hg_zero) {
-        x = (Real)2.0 * u - (Real)1.0;
+        x = M<Real>::fma((Real)2.0, u, (Real)-1.0);
     } else {
-        const Real q = M<Real>::div(c.hg_b, c.hg_c0 + c.hg_c1 * u);
-        if constexpr (sizeof(Real) == 4) x = (c.hg_a - q * q) * c.hg_inv2g;
-        else x = (c.hg_a - q * q) / c.hg_c1;
+        const Real q = M<Real>::div(c.hg_b, M<Real>::fma(c.hg_c1, u, c.hg_c0));
+        if constexpr (sizeof(Real) == 4) x = M<Real>::fma(-q, q, c.hg_a) * c.hg_inv2g;
+        else x = M<Real>::fma(-q, q, c.hg_a) / c.hg_c1;
     }
     x = M<Real>::clamp1(x);
     ct = x;
@@ -246,7 +267,7 @@ __device__ __forceinline__ void flush_acc(LaneAcc& a, WaveAcc& w, uint64_t* tall
     w = WaveAcc{0, 0, 0};
 }
 
-template <typename Real, bool LIST>
+template <typename Real, bool LIST, int KIND>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 6 : 4, 8)))
 transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ tables,
                  uint64_t* __restrict__ tallies, const WorkItem* __restrict__ items, int n_items,
@@ -381,7 +402,7 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                     atomicAdd(&sW[slot], (unsigned long long)fw);
                     if (slot < nb) {
                         atomicAdd(&sW2[slot], (unsigned long long)to_fixed32<Real>(w * w));
-                        if (c.flags & SF_CLASS) {
+                        if (Kind<KIND>::cls(c)) {
                             unsigned long long* gcl =
                                 (unsigned long long*)(tallies + descs[set].tally_offset + tw_class(nb));
                             if (n_sc == 1 && n_surf == 0) atomicAdd(gcl + slot, (unsigned long long)fw);
@@ -412,7 +433,7 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                     }
                     // implicit capture: the packet's 2^32 units are split exactly
                     // between its terminal slot and the two absorption sinks
-                    if (c.weighting == 0) {
+                    if (!Kind<KIND>::analog(c)) {
                         const uint64_t fs = to_fixed32<Real>(abs_s);
                         acc.abs_surface += fs;
                         acc.abs_particle += (4294967296ull - fw) - fs;
@@ -463,7 +484,7 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
             const Real u0 = unit_open<Real>(X.x);
             const Real u1 = unit_open<Real>(X.y);
             const Real u2 = unit_open<Real>(X.z);
-            const Real Tn = T - M<Real>::neg_log(u0) * mu;
+            const Real Tn = M<Real>::fma(-M<Real>::neg_log(u0), mu, T);
             const bool leave = mu > (Real)0 && Tn <= (Real)0;
             const bool surf = mu < (Real)0 && Tn >= c.tau;
             const bool coll = !leave && !surf;
@@ -471,20 +492,20 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
             // particle interaction: scatterer speed, new direction
             Real Vc = 0, mu_c = 0, omc_c = 0;
             if (coll) {
-                Vc = zeta_at<Real>(c, sT, sLG, gshift, Tn);
+                Vc = zeta_at<Real, KIND>(c, sT, sLG, gshift, Tn);
                 Real ct, st_;
-                if (c.phase_kind == PH_TABLE) table_angle<Real>(c, sC, sCG, guide_bits, X.y, ct, st_);
+                if (Kind<KIND>::table(c)) table_angle<Real>(c, sC, sCG, guide_bits, X.y, ct, st_);
                 else hg_angle<Real>(c, u1, ct, st_);
                 const Real cphi = M<Real>::cos_rev(u2);
                 const Real sm2 = ((Real)1.0 - mu) * ((Real)1.0 + mu);
-                Real m2 = mu * ct + M<Real>::sqrt(sm2 > (Real)0 ? sm2 : (Real)0) * st_ * cphi;
+                Real m2 = M<Real>::fma(mu, ct, M<Real>::sqrt(sm2 > (Real)0 ? sm2 : (Real)0) * st_ * cphi);
                 m2 = M<Real>::clamp1(m2);
                 mu_c = m2;
                 omc_c = (Real)1.0 - m2;
             }
             // free-surface reflection (computed for every lane, selected below)
             Real mu_s, omc_s;
-            if (c.surface_law == 1) {
+            if (Kind<KIND>::lambert(c)) {
                 const Real r = M<Real>::sqrt(u1);
                 mu_s = r;
                 omc_s = M<Real>::div((Real)1.0 - u1, (Real)1.0 + r);
@@ -507,7 +528,7 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
 
             const bool trunc = coll && n_sc == c.max_orders;
             bool absorbed = false;
-            if (c.weighting == 1) {
+            if (Kind<KIND>::analog(c)) {
                 const uint32_t thr = surf ? c.thr_surface : c.thr_albedo;
                 const bool one = surf ? (bool)c.surface_one : (bool)c.albedo_one;
                 absorbed = !leave && !trunc && !one && X.w >= thr;
@@ -517,13 +538,13 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
             n_surf += surf ? 1 : 0;
             n_sc += coll ? 1 : 0;
             if (!(leave || trunc || absorbed)) {
-                if (c.weighting == 0) {
+                if (!Kind<KIND>::analog(c)) {
                     const Real lost = w * ((Real)1.0 - a);
                     abs_s += surf ? lost : (Real)0;
                     w *= a;
                 }
-                big += (Real)0.5 * V * ((Real)1.0 - mu);
-                small += (Real)0.5 * V * omc;
+                big = M<Real>::fma((Real)0.5 * V, (Real)1.0 - mu, big);
+                small = M<Real>::fma((Real)0.5 * V, omc, small);
                 mu = mu_new;
                 T = surf ? c.tau : Tn;
             } else {
@@ -539,16 +560,63 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
 }  // namespace pdv
 
 // ---- host launchers ----
+//
+// This file is compiled twice.  The default pass builds the FP32 kernels
+// without implicit floating-point contraction (every kind of FP32 kernel then
+// performs the same roundings) together with the host dispatch; the pass with
+// PDV_TRANSPORT_FP64 builds the FP64 kernels, which only exist in the generic
+// kind, with the compiler's usual contraction.
 namespace pdv {
 
-template <typename Real, bool LIST>
+template <typename Real, bool LIST, int KIND>
 static const void* kernel_ptr() {
-    return reinterpret_cast<const void*>(&transport_kernel<Real, LIST>);
+    return reinterpret_cast<const void*>(&transport_kernel<Real, LIST, KIND>);
 }
 
-static const void* select_kernel(int precision, bool list) {
-    if (precision == 1) return list ? kernel_ptr<double, true>() : kernel_ptr<double, false>();
-    return list ? kernel_ptr<float, true>() : kernel_ptr<float, false>();
+template <typename Real, bool LIST, int KIND>
+static hipError_t launch_kind(hipStream_t s, const TransportShape& sh, const SetDesc* descs, const uint8_t* tables,
+                              uint64_t* tallies, const WorkItem* items, int n_items, const int* n_items_dev,
+                              uint32_t* queue, int persistent, ListEntry* lists, uint64_t* list_counts) {
+    hipLaunchKernelGGL((transport_kernel<Real, LIST, KIND>), dim3(sh.grid), dim3(sh.block), sh.lds_bytes, s, descs,
+                       tables, tallies, items, n_items, queue, persistent, sh.max_layers, sh.max_cells, sh.max_bins,
+                       lists, list_counts, n_items_dev, sh.guide_bits, sh.retire_min);
+    return hipGetLastError();
+}
+
+#if defined(PDV_TRANSPORT_FP64)
+
+const void* select_kernel_fp64(bool list) {
+    return list ? kernel_ptr<double, true, KIND_GENERIC>() : kernel_ptr<double, false, KIND_GENERIC>();
+}
+
+hipError_t launch_transport_fp64(hipStream_t s, bool list, const TransportShape& sh, const SetDesc* descs,
+                                 const uint8_t* tables, uint64_t* tallies, const WorkItem* items, int n_items,
+                                 const int* n_items_dev, uint32_t* queue, int persistent, ListEntry* lists,
+                                 uint64_t* list_counts) {
+    return list ? launch_kind<double, true, KIND_GENERIC>(s, sh, descs, tables, tallies, items, n_items, n_items_dev,
+                                                          queue, persistent, lists, list_counts)
+                : launch_kind<double, false, KIND_GENERIC>(s, sh, descs, tables, tallies, items, n_items,
+                                                           n_items_dev, queue, persistent, lists, list_counts);
+}
+
+#else
+
+// FP64 kernels (the other compilation pass)
+const void* select_kernel_fp64(bool list);
+hipError_t launch_transport_fp64(hipStream_t s, bool list, const TransportShape& sh, const SetDesc* descs,
+                                 const uint8_t* tables, uint64_t* tallies, const WorkItem* items, int n_items,
+                                 const int* n_items_dev, uint32_t* queue, int persistent, ListEntry* lists,
+                                 uint64_t* list_counts);
+
+// FP32 launches of one specialised kind get their own kernel; FP64 (the
+// plain baseline) always runs the generic one.
+static const void* select_kernel(int precision, bool list, int kind) {
+    if (precision == 1) return select_kernel_fp64(list);
+    if (kind == KIND_TABLE_LAYERED)
+        return list ? kernel_ptr<float, true, KIND_TABLE_LAYERED>() : kernel_ptr<float, false, KIND_TABLE_LAYERED>();
+    if (kind == KIND_HG_UNIFORM)
+        return list ? kernel_ptr<float, true, KIND_HG_UNIFORM>() : kernel_ptr<float, false, KIND_HG_UNIFORM>();
+    return list ? kernel_ptr<float, true, KIND_GENERIC>() : kernel_ptr<float, false, KIND_GENERIC>();
 }
 
 static hipError_t allow_lds(const void* k, int bytes) {
@@ -574,7 +642,7 @@ hipError_t plan_transport(TransportShape& sh, int precision, bool list, int want
         sh.guide_bits = want_bits;
     } else {
         int resident = 1;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, select_kernel(precision, list),
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, select_kernel(precision, list, sh.kind),
                                                                     sh.block, 0);
         if (e != hipSuccess) return e;
         if (resident < 1) resident = 1;
@@ -585,17 +653,21 @@ hipError_t plan_transport(TransportShape& sh, int precision, bool list, int want
     }
     sh.lds_bytes = bytes(sh.guide_bits);
     if (sh.lds_bytes > lds_per_block) return hipErrorInvalidValue;
-    return allow_lds(select_kernel(precision, list), sh.lds_bytes);
+    return allow_lds(select_kernel(precision, list, sh.kind), sh.lds_bytes);
 }
 
-template <typename Real, bool LIST>
-static hipError_t launch_one(hipStream_t s, const TransportShape& sh, const SetDesc* descs, const uint8_t* tables,
-                             uint64_t* tallies, const WorkItem* items, int n_items, const int* n_items_dev,
-                             uint32_t* queue, int persistent, ListEntry* lists, uint64_t* list_counts) {
-    hipLaunchKernelGGL((transport_kernel<Real, LIST>), dim3(sh.grid), dim3(sh.block), sh.lds_bytes, s, descs,
-                       tables, tallies, items, n_items, queue, persistent, sh.max_layers, sh.max_cells, sh.max_bins,
-                       lists, list_counts, n_items_dev, sh.guide_bits, sh.retire_min);
-    return hipGetLastError();
+template <bool LIST>
+static hipError_t launch_fp32(hipStream_t s, const TransportShape& sh, const SetDesc* descs, const uint8_t* tables,
+                              uint64_t* tallies, const WorkItem* items, int n_items, const int* n_items_dev,
+                              uint32_t* queue, int persistent, ListEntry* lists, uint64_t* list_counts) {
+    if (sh.kind == KIND_TABLE_LAYERED)
+        return launch_kind<float, LIST, KIND_TABLE_LAYERED>(s, sh, descs, tables, tallies, items, n_items,
+                                                            n_items_dev, queue, persistent, lists, list_counts);
+    if (sh.kind == KIND_HG_UNIFORM)
+        return launch_kind<float, LIST, KIND_HG_UNIFORM>(s, sh, descs, tables, tallies, items, n_items, n_items_dev,
+                                                         queue, persistent, lists, list_counts);
+    return launch_kind<float, LIST, KIND_GENERIC>(s, sh, descs, tables, tallies, items, n_items, n_items_dev, queue,
+                                                  persistent, lists, list_counts);
 }
 
 // Persistent launch whose item count is read from device memory, so a
@@ -604,10 +676,9 @@ hipError_t launch_transport_dev(hipStream_t s, int precision, const TransportSha
                                 const uint8_t* tables, uint64_t* tallies, const WorkItem* items,
                                 const int* n_items_dev, uint32_t* queue) {
     if (precision == 1)
-        return launch_one<double, false>(s, sh, descs, tables, tallies, items, 0, n_items_dev, queue, 1, nullptr,
-                                         nullptr);
-    return launch_one<float, false>(s, sh, descs, tables, tallies, items, 0, n_items_dev, queue, 1, nullptr,
-                                    nullptr);
+        return launch_transport_fp64(s, false, sh, descs, tables, tallies, items, 0, n_items_dev, queue, 1, nullptr,
+                                     nullptr);
+    return launch_fp32<false>(s, sh, descs, tables, tallies, items, 0, n_items_dev, queue, 1, nullptr, nullptr);
 }
 
 // n_items_dev (nullable): read the item count from device memory instead of
@@ -616,16 +687,15 @@ hipError_t launch_transport(hipStream_t s, int precision, bool list, const Trans
                             const SetDesc* descs, const uint8_t* tables, uint64_t* tallies, const WorkItem* items,
                             int n_items, const int* n_items_dev, uint32_t* queue, int persistent, ListEntry* lists,
                             uint64_t* list_counts) {
-    if (precision == 1) {
-        return list ? launch_one<double, true>(s, sh, descs, tables, tallies, items, n_items, n_items_dev, queue,
-                                               persistent, lists, list_counts)
-                    : launch_one<double, false>(s, sh, descs, tables, tallies, items, n_items, n_items_dev, queue,
-                                                persistent, lists, list_counts);
-    }
-    return list ? launch_one<float, true>(s, sh, descs, tables, tallies, items, n_items, n_items_dev, queue,
-                                          persistent, lists, list_counts)
-                : launch_one<float, false>(s, sh, descs, tables, tallies, items, n_items, n_items_dev, queue,
-                                           persistent, lists, list_counts);
+    if (precision == 1)
+        return launch_transport_fp64(s, list, sh, descs, tables, tallies, items, n_items, n_items_dev, queue,
+                                     persistent, lists, list_counts);
+    return list ? launch_fp32<true>(s, sh, descs, tables, tallies, items, n_items, n_items_dev, queue, persistent,
+                                    lists, list_counts)
+                : launch_fp32<false>(s, sh, descs, tables, tallies, items, n_items, n_items_dev, queue, persistent,
+                                     lists, list_counts);
 }
+
+#endif  // PDV_TRANSPORT_FP64
 
 }  // namespace pdv

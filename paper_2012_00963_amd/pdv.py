@@ -124,6 +124,7 @@ def load():
     lib.pdv_validate.argtypes = [V, P(Params)]
     lib.pdv_spectrum.argtypes = [V, P(Params), P(SpectrumOut)]
     lib.pdv_prepare.argtypes = [V, P(Params), P(TableInfo)]
+    lib.pdv_last_launch_kind.argtypes = [V]
     lib.pdv_spectrum_batch.argtypes = [V, P(Params), ctypes.c_int32, P(SpectrumOut), P(LaunchOpts)]
     lib.pdv_spectrogram.argtypes = [V, P(Params), P(SgParams), P(SgOut)]
     lib.pdv_beat_synthesize.argtypes = [V, ctypes.c_int32, P(ctypes.c_uint64), P(ctypes.c_float),
@@ -334,7 +335,7 @@ class Context:
         self.lib.pdv_last_launch(self.h, ctypes.byref(ms), ctypes.byref(g), ctypes.byref(b), ctypes.byref(it),
                                  ctypes.byref(gb), ctypes.byref(lds))
         return {"kernel_ms": float(ms.value), "grid": g.value, "block": b.value, "items": it.value,
-                "guide_bits": gb.value, "lds_bytes": lds.value}
+                "guide_bits": gb.value, "lds_bytes": lds.value, "kind": int(self.lib.pdv_last_launch_kind(self.h))}
 
 
 def _fptr(a):

@@ -169,6 +169,26 @@ def test_batch_equals_alone(ctx):
         assert np.array_equal(a["w_fx"], b["w_fx"]) and a["sinks_fx"] == b["sinks_fx"]
 
 
+def test_specialised_kernels_equal_generic(ctx):
+    # a Mie set on a layered cloud and an HG set on a uniform slab each run a
+    # specialised FP32 kernel alone and the generic one together: the
+    # tallies are bit-identical
+    mie = dict(wl.large_mie(120_000), seed=21)
+    hg = dict(wl.small_hg(), n_packets=150_000, seed=22)
+    alone = []
+    for p, kind in ((mie, 1), (hg, 2)):
+        alone.append(ctx.spectrum(p))
+        assert ctx.last_launch()["kind"] == kind
+    mixed = ctx.spectrum_batch([mie, hg])
+    assert ctx.last_launch()["kind"] == -1
+    for a, b in zip(alone, mixed):
+        assert np.array_equal(a["w_fx"], b["w_fx"]) and np.array_equal(a["w2_fx"], b["w2_fx"])
+        assert a["sinks_fx"] == b["sinks_fx"] and a["counts"] == b["counts"]
+    # FP64 always runs the generic kernel
+    ctx.spectrum(dict(mie, precision=1, n_packets=20_000))
+    assert ctx.last_launch()["kind"] == -1
+
+
 def test_batch_graph_replays(ctx):
     # captured batch launches replayed for several item lists, with eager
     # batches in between: every replay equals the eager result
