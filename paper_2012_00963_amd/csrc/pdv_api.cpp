@@ -34,6 +34,7 @@ void launch_phase_cdf(hipStream_t s, int n_jobs, const void* jobs, int n_nodes, 
 void launch_zero_u64(hipStream_t s, uint64_t* p, uint64_t n);
 void launch_copy_jobs(hipStream_t s, int n_jobs, const void* jobs, const uint64_t* src);
 void launch_copy_desc_fields(hipStream_t s, SetDesc* descs, const int* src, int n);
+int launch_kind_of(const pdv_params* sets, int n);
 hipError_t plan_transport(TransportShape& sh, int precision, bool list, int want_bits, int lds_per_block,
                           int lds_per_cu);
 hipError_t launch_synth(hipStream_t s, int n_frames, const void* frames, const ListEntry* entries, double r_scale,
@@ -399,12 +400,32 @@ void pdv::fill_desc(SetDesc& d, const pdv_params& p) {
     d.n_bins = p.n_bins;
 }
 
-void pdv_ctx::default_opts(pdv_launch_opts& o, uint64_t total_packets, int n_sets, bool fp64) const {
+// Kind of a parameter set (KindBits), and of a launch: the specialised kind
+// all its FP32 sets share, else KIND_GENERIC.
+static int params_kind(const pdv_params& p) {
+    return (p.phase_kind != PDV_PHASE_HG ? KB_TABLE : 0) | (p.density_kind == PDV_DENSITY_UNIFORM ? KB_UNIFORM : 0) |
+           (p.surface_law == 1 ? KB_LAMBERT : 0) | (p.weighting == 1 ? KB_ANALOG : 0) |
+           ((p.flags & PDV_FLAG_CLASS_TALLIES) ? KB_CLASS : 0);
+}
+
+int pdv::launch_kind_of(const pdv_params* sets, int n) {
+    if (n < 1 || sets[0].precision != PDV_FP32) return KIND_GENERIC;
+    const int k0 = params_kind(sets[0]);
+    for (int i = 1; i < n; ++i)
+        if (params_kind(sets[i]) != k0) return KIND_GENERIC;
+    return (k0 == KIND_TABLE_LAYERED || k0 == KIND_HG_UNIFORM) ? k0 : KIND_GENERIC;
+}
+
+void pdv_ctx::default_opts(pdv_launch_opts& o, uint64_t total_packets, int n_sets, bool fp64, int kind) const {
     (void)n_sets;
-    // measured on the large case: FP32 runs best as two 768-thread blocks
-    // per CU (six waves per SIMD), FP64 as one 1024-thread block per CU
-    if (o.block_size <= 0) o.block_size = tuned.block_size > 0 ? tuned.block_size : (fp64 ? 1024 : 768);
-    if (o.blocks_per_cu <= 0) o.blocks_per_cu = tuned.blocks_per_cu > 0 ? tuned.blocks_per_cu : (fp64 ? 1 : 2);
+    // measured on the large case: the specialised FP32 kernels run best as
+    // two 1024-thread blocks per CU (eight waves per SIMD), the generic FP32
+    // kernel as two 768-thread blocks (six waves), FP64 as one 1024-thread
+    // block per CU
+    const int def_block = fp64 ? 1024 : (kind != KIND_GENERIC ? 1024 : 768);
+    const int def_bpc = fp64 ? 1 : 2;
+    if (o.block_size <= 0) o.block_size = tuned.block_size > 0 ? tuned.block_size : def_block;
+    if (o.blocks_per_cu <= 0) o.blocks_per_cu = tuned.blocks_per_cu > 0 ? tuned.blocks_per_cu : def_bpc;
     if (o.persistent < 0) o.persistent = tuned.persistent >= 0 ? tuned.persistent : 1;
     if (o.guide_bits == 0) o.guide_bits = tuned.guide_bits;
     // measured on the large case: 12 for FP32 transport; FP64 is fastest
@@ -447,7 +468,8 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
     if (opts_in) o = *opts_in;
     uint64_t total = 0;
     for (int i = 0; i < n; ++i) total += sets[i].n_packets;
-    default_opts(o, total, n, precision == PDV_FP64);
+    const int kind = launch_kind_of(sets, n);
+    default_opts(o, total, n, precision == PDV_FP64, kind);
     if (o.block_size != 256 && o.block_size != 512 && o.block_size != 768 && o.block_size != 1024)
         return fail(PDV_EINVAL, "block_size must be 256, 512, 768 or 1024");
     if (o.guide_bits != 0 && (o.guide_bits < MIN_GUIDE_BITS || o.guide_bits > GUIDE_BITS))
@@ -606,13 +628,7 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
     sh.max_bins = max_bins;
     sh.retire_min = o.retire_batch;
     // FP32 sets that all share a specialised kind run that kind's kernel
-    sh.kind = KIND_GENERIC;
-    if (precision == PDV_FP32) {
-        const int k0 = set_kind(h_desc[0]);
-        bool same = true;
-        for (int i = 1; i < n && same; ++i) same = set_kind(h_desc[i]) == k0;
-        if (same && (k0 == KIND_TABLE_LAYERED || k0 == KIND_HG_UNIFORM)) sh.kind = k0;
-    }
+    sh.kind = kind;
     last_kind = sh.kind;
     {
         hipError_t e = plan_transport(sh, precision, list_capacity > 0, o.guide_bits, lds_per_block, lds_per_cu);
@@ -1123,7 +1139,7 @@ extern "C" int pdv_autotune(pdv_ctx* ctx, const pdv_params* sets, int32_t n, int
     {
         uint64_t total = 0;
         for (int i = 0; i < n; ++i) total += sets[i].n_packets;
-        ctx->default_opts(def, total, n, sets[0].precision == PDV_FP64);
+        ctx->default_opts(def, total, n, sets[0].precision == PDV_FP64, launch_kind_of(sets, n));
     }
     float ms = 0;
     if (int r = run(def, &ms)) return r;

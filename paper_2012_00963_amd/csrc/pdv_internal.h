@@ -126,11 +126,6 @@ enum KindBits : int { KB_TABLE = 1, KB_UNIFORM = 2, KB_LAMBERT = 4, KB_ANALOG = 
 constexpr int KIND_GENERIC = -1;
 constexpr int KIND_TABLE_LAYERED = KB_TABLE;      // tabulated or Mie law, layered cloud, paper surface law, implicit
 constexpr int KIND_HG_UNIFORM = KB_UNIFORM;       // Henyey-Greenstein law, uniform slab, paper surface law, implicit
-inline int set_kind(const SetDesc& d) {
-    return (d.phase_kind == PH_TABLE ? KB_TABLE : 0) | (d.uniform_density ? KB_UNIFORM : 0) |
-           (d.surface_law == 1 ? KB_LAMBERT : 0) | (d.weighting == 1 ? KB_ANALOG : 0) |
-           ((d.flags & SF_CLASS) ? KB_CLASS : 0);
-}
 
 // Launch shape of the transport kernel (host side).
 struct TransportShape {

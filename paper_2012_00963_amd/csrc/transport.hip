@@ -267,8 +267,12 @@ __device__ __forceinline__ void flush_acc(LaneAcc& a, WaveAcc& w, uint64_t* tall
     w = WaveAcc{0, 0, 0};
 }
 
+// Occupancy targets: the specialised FP32 kernels fit eight waves per SIMD
+// (64 VGPRs, run as two 1024-thread blocks per CU), the generic FP32 kernel
+// six, the FP64 kernel four.
 template <typename Real, bool LIST, int KIND>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 6 : 4, 8)))
+__global__ void __launch_bounds__(1024)
+__attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? (KIND >= 0 ? 8 : 6) : 4, 8)))
 transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ tables,
                  uint64_t* __restrict__ tallies, const WorkItem* __restrict__ items, int n_items,
                  uint32_t* __restrict__ queue, int persistent, int max_layers, int max_cells, int max_bins,
