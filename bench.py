@@ -398,7 +398,7 @@ def main(argv=None):
             "unit": "T lane-op slots/s",
             "frac": achieved_tops / VALU_PEAK_TOPS,
             "traffic": committed_traffic(),
-            "kernel": "transport_kernel<float,false>",
+            "kernel": "transport_kernel<float,false,%d>" % launch.get("kind", -1),
             "kernel_ms": k_ms,
             "slots_per_event": SLOTS_PER_EVENT,
             "fp32_flop_frac": events * FP32_FLOPS_PER_EVENT / (k_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
