@@ -72,6 +72,30 @@ int pdv_ctx::hip_check(hipError_t e, const char* what) {
     return fail(PDV_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+// Grow-only pinned host buffer (hipHostMalloc); the stream is synchronised
+// before an old buffer is freed.
+int pdv_ctx::ensure_pinned(HostPinned& b, size_t bytes, const char* what) {
+    if (b.cap >= bytes) return PDV_OK;
+    size_t want = std::max(bytes, b.cap + b.cap / 2);
+    want = (want + 4095) & ~(size_t)4095;
+    if (b.ptr) {
+        hipError_t e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_check(e, "synchronize before realloc");
+        (void)hipHostFree(b.ptr);
+        b.ptr = nullptr;
+        b.cap = 0;
+    }
+    void* p = nullptr;
+    hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(PDV_ENOMEM, "%s: hipHostMalloc(%zu) failed: %s", what, want, hipGetErrorString(e));
+    }
+    b.ptr = p;
+    b.cap = want;
+    return PDV_OK;
+}
+
 int pdv_ctx::ensure(DevBuf& b, size_t bytes, const char* what) {
     if (b.cap >= bytes) return PDV_OK;
     size_t want = std::max(bytes, b.cap + b.cap / 2);
@@ -276,6 +300,8 @@ void pdv_ctx::release_all() {
     }
     for (auto& h : host_pinned) (void)hipHostFree(h.ptr);
     host_pinned.clear();
+    if (tally_pinned.ptr) (void)hipHostFree(tally_pinned.ptr);
+    tally_pinned = HostPinned{};
     mem_used = 0;
     mie_key_valid = false;
     stft_nfft = 0;
@@ -683,8 +709,11 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
         launch_copy_jobs(s, (int)h_copy.size(), copy_jobs.ptr, (const uint64_t*)tallies.ptr);
         if ((r = hip_check(hipGetLastError(), "device output copies"))) return r;
     }
-    h_tally.resize(tally_words_total);
-    if ((r = hip_check(hipMemcpyAsync(h_tally.data(), tallies.ptr, 8 * tally_words_total, hipMemcpyDeviceToHost, s),
+    // tallies come back through pinned staging (a pageable copy of the
+    // 16 MB of a 512-set batch ran at a fraction of the link rate)
+    if ((r = ensure_pinned(tally_pinned, 8 * std::max<uint64_t>(1, tally_words_total), "tally staging"))) return r;
+    uint64_t* ht = (uint64_t*)tally_pinned.ptr;
+    if ((r = hip_check(hipMemcpyAsync(ht, tallies.ptr, 8 * tally_words_total, hipMemcpyDeviceToHost, s),
                        "copy tallies")))
         return r;
     if ((r = hip_check(hipMemcpyAsync(h_desc.data(), descs.ptr, sizeof(SetDesc) * n, hipMemcpyDeviceToHost, s),
@@ -694,7 +723,7 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, ev_a, ev_b) == hipSuccess) last_kernel_ms = ms;
     if (outs) {
-        for (int i = 0; i < n; ++i) unpack(sets[i], h_desc[i], h_tally.data() + h_desc[i].tally_offset, outs[i]);
+        for (int i = 0; i < n; ++i) unpack(sets[i], h_desc[i], ht + h_desc[i].tally_offset, outs[i]);
     }
     return PDV_OK;
 }

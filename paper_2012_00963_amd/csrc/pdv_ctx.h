@@ -111,7 +111,7 @@ struct pdv_ctx {
     std::vector<pdv::PhaseJob> h_phase;
     std::vector<double> h_density;
     std::vector<pdv::WorkItem> h_items;
-    std::vector<uint64_t> h_tally;
+    HostPinned tally_pinned;             // pinned staging of a batch's tallies (grow-only)
 
     // last launch (benchmarks)
     float last_kernel_ms = 0.f;
@@ -128,6 +128,7 @@ struct pdv_ctx {
     // true if ptr is device (or managed) memory of this context's device
     bool on_device(const void* ptr);
     int ensure(DevBuf& b, size_t bytes, const char* what);
+    int ensure_pinned(HostPinned& b, size_t bytes, const char* what);
     int ensure_mie_basis(const pdv_params& p);
     void default_opts(pdv_launch_opts& o, uint64_t total_packets, int n_sets, bool fp64, int kind) const;
     int run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, const pdv_launch_opts* opts,
