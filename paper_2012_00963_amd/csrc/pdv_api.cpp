@@ -442,7 +442,8 @@ int pdv::launch_kind_of(const pdv_params* sets, int n) {
     return (k0 == KIND_TABLE_LAYERED || k0 == KIND_HG_UNIFORM) ? k0 : KIND_GENERIC;
 }
 
-void pdv_ctx::default_opts(pdv_launch_opts& o, uint64_t total_packets, int n_sets, bool fp64, int kind) const {
+void pdv_ctx::default_opts(pdv_launch_opts& o, uint64_t total_packets, int n_sets, bool fp64, int kind,
+                           bool list) const {
     (void)n_sets;
     // measured on the large case: the specialised FP32 kernels run best as
     // two 1024-thread blocks per CU (eight waves per SIMD), the generic FP32
@@ -454,9 +455,13 @@ void pdv_ctx::default_opts(pdv_launch_opts& o, uint64_t total_packets, int n_set
     if (o.blocks_per_cu <= 0) o.blocks_per_cu = tuned.blocks_per_cu > 0 ? tuned.blocks_per_cu : def_bpc;
     if (o.persistent < 0) o.persistent = tuned.persistent >= 0 ? tuned.persistent : 1;
     if (o.guide_bits == 0) o.guide_bits = tuned.guide_bits;
-    // measured on the large case: 12 for FP32 transport; FP64 is fastest
-    // tallying every round
-    if (o.retire_batch == 0) o.retire_batch = tuned.retire_batch > 0 ? tuned.retire_batch : (fp64 ? 1 : 12);
+    // measured: 12 for FP32 spectra of the large case; 48 when detected
+    // packets are also appended to lists (each retire round with a detection
+    // takes a global atomic on the frame's list counter, so fewer, fuller
+    // rounds pay: the 256-frame spectrogram's transport 14.0 -> 8.8 ms);
+    // FP64 is fastest tallying every round
+    if (o.retire_batch == 0)
+        o.retire_batch = tuned.retire_batch > 0 ? tuned.retire_batch : (fp64 ? 1 : (list ? 48 : 12));
     if (o.packets_per_item == 0) {
         // three large items per block, rounded up so that the item count
         // does not spill into a further round: every item ends with a block
@@ -495,7 +500,7 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
     uint64_t total = 0;
     for (int i = 0; i < n; ++i) total += sets[i].n_packets;
     const int kind = launch_kind_of(sets, n);
-    default_opts(o, total, n, precision == PDV_FP64, kind);
+    default_opts(o, total, n, precision == PDV_FP64, kind, list_capacity > 0);
     if (o.block_size != 256 && o.block_size != 512 && o.block_size != 768 && o.block_size != 1024)
         return fail(PDV_EINVAL, "block_size must be 256, 512, 768 or 1024");
     if (o.guide_bits != 0 && (o.guide_bits < MIN_GUIDE_BITS || o.guide_bits > GUIDE_BITS))
@@ -1168,7 +1173,7 @@ extern "C" int pdv_autotune(pdv_ctx* ctx, const pdv_params* sets, int32_t n, int
     {
         uint64_t total = 0;
         for (int i = 0; i < n; ++i) total += sets[i].n_packets;
-        ctx->default_opts(def, total, n, sets[0].precision == PDV_FP64, launch_kind_of(sets, n));
+        ctx->default_opts(def, total, n, sets[0].precision == PDV_FP64, launch_kind_of(sets, n), false);
     }
     float ms = 0;
     if (int r = run(def, &ms)) return r;

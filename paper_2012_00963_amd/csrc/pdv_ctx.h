@@ -130,7 +130,8 @@ struct pdv_ctx {
     int ensure(DevBuf& b, size_t bytes, const char* what);
     int ensure_pinned(HostPinned& b, size_t bytes, const char* what);
     int ensure_mie_basis(const pdv_params& p);
-    void default_opts(pdv_launch_opts& o, uint64_t total_packets, int n_sets, bool fp64, int kind) const;
+    void default_opts(pdv_launch_opts& o, uint64_t total_packets, int n_sets, bool fp64, int kind,
+                      bool list) const;
     int run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, const pdv_launch_opts* opts,
                   uint64_t list_capacity, bool keep_device);
     int synthesize(int n_frames, const uint64_t* entry_begin, const uint64_t* n_entries, const ListEntry_* entries,
