@@ -45,7 +45,7 @@
 namespace pdv {
 
 struct LdsLayout {
-    uint32_t t_off, lg_off, cdf_off, cg_off, hist_off, hist2_off, bytes;
+    uint32_t t_off, lg_off, cdf_off, cg_off, hist_off, hist2_off, list_off, bytes;
 };
 
 // A guide cell's margin (in finest cells) around the scaled depth: covers
@@ -66,8 +66,13 @@ enum LaneState : int { ST_EMPTY = 0, ST_ALIVE = 1, ST_EXIT = 2, ST_TRUNC = 3, ST
 constexpr int REFILL_CHUNK = 128;
 constexpr int REFILL_CHUNK_MIN = 32;
 
+// Detected-list staging: each wave of a list-writing launch gathers up to
+// LIST_STAGE entries in LDS and appends them to the frame's list with one
+// global atomic, instead of one per retire round.
+constexpr int LIST_STAGE = 64;
+
 __host__ __device__ inline LdsLayout lds_layout(int real_bytes, int max_layers, int max_cells, int max_bins,
-                                                int guide_bits) {
+                                                int guide_bits, int list_waves) {
     const uint32_t guide_entries = (1u << guide_bits) + 1u;
     LdsLayout L;
     L.t_off = 0;
@@ -76,7 +81,8 @@ __host__ __device__ inline LdsLayout lds_layout(int real_bytes, int max_layers, 
     L.cg_off = align16(L.cdf_off + 4u * (uint32_t)(max_cells + 1));
     L.hist_off = align16(L.cg_off + 2u * guide_entries);
     L.hist2_off = align16(L.hist_off + 8u * (uint32_t)(max_bins + N_SINK_SLOTS));
-    L.bytes = align16(L.hist2_off + 8u * (uint32_t)max_bins);
+    L.list_off = align16(L.hist2_off + 8u * (uint32_t)max_bins);
+    L.bytes = align16(L.list_off + (uint32_t)sizeof(ListEntry) * LIST_STAGE * (uint32_t)list_waves);
     return L;
 }
 
@@ -284,7 +290,8 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
     __shared__ int s_item_idx;
     __shared__ uint32_t s_next;
 
-    const LdsLayout L = lds_layout((int)sizeof(Real), max_layers, max_cells, max_bins, guide_bits);
+    const LdsLayout L = lds_layout((int)sizeof(Real), max_layers, max_cells, max_bins, guide_bits,
+                                   LIST ? (int)(blockDim.x >> 6) : 0);
     const int gshift = GUIDE_BITS - guide_bits;
     const int n_guide = 1 << guide_bits;
     Real* sT = (Real*)(lds + L.t_off);
@@ -297,6 +304,28 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
     const int lane = lane_id();
+    // this wave's list staging (list-writing launches) and its fill, which
+    // is wave-uniform
+    ListEntry* sL = (ListEntry*)(lds + L.list_off) + (uint32_t)(tid >> 6) * LIST_STAGE;
+    uint32_t l_fill = 0;
+    // append the staged entries to set's list: one atomic reserves the slots,
+    // lane i copies entry i (entries past the list's capacity are counted,
+    // not stored)
+    auto flush_list = [&](int set) {
+        if (l_fill == 0) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const SetDesc& d = descs[set];
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd((unsigned long long*)(list_counts + set), (unsigned long long)l_fill);
+        base = __shfl(base, 0, 64);
+        if ((uint32_t)lane < l_fill) {
+            const unsigned long long slot = base + (unsigned long long)lane;
+            if (slot < d.list_capacity) lists[d.list_offset + slot] = sL[lane];
+        }
+        __builtin_amdgcn_wave_barrier();
+        l_fill = 0;
+    };
     int cur_set = -1;
     LaneAcc acc = LaneAcc{0, 0, 0, 0};
     WaveAcc wacc = WaveAcc{0, 0, 0};
@@ -385,6 +414,10 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                 wacc.packets += (uint64_t)__popcll(__ballot(st >= ST_EXIT));
                 wacc.exits += (uint64_t)__popcll(__ballot(st == ST_EXIT));
                 wacc.detected += (uint64_t)__popcll(__ballot(st == ST_EXIT && mu >= c.cos_cone));
+                bool det_now = false;        // this lane's packet goes to the detected list
+                float e_w = 0.f;
+                uint32_t e_phase = 0;
+                double e_v = 0.0;
                 if (st >= ST_EXIT) {
                     // ---- the packet's tally: one terminal slot of the LDS histogram ----
                     const bool detected = st == ST_EXIT && mu >= c.cos_cone;
@@ -416,23 +449,10 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                     if constexpr (LIST) {
                         if (detected) {
                             const Block4 P = philox10_event(0xffffffffu, q0, q1, c.stream ^ c.k1, c.k0, c.k1);
-                            const SetDesc& d = descs[set];
-                            const uint64_t m = __ballot(1);
-                            const int leader = __ffsll((unsigned long long)m) - 1;
-                            const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-                            unsigned long long lbase = 0;
-                            if (lane == leader)
-                                lbase = atomicAdd((unsigned long long*)(list_counts + set),
-                                                  (unsigned long long)__popcll(m));
-                            lbase = __shfl(lbase, leader, 64);
-                            const unsigned long long lslot = lbase + rank;
-                            if (lslot < d.list_capacity) {
-                                ListEntry e;
-                                e.w = (float)w;
-                                e.phase = P.x;
-                                e.v = vt;
-                                lists[d.list_offset + lslot] = e;
-                            }
+                            det_now = true;
+                            e_w = (float)w;
+                            e_phase = P.x;
+                            e_v = vt;
                         }
                     }
                     // implicit capture: the packet's 2^32 units are split exactly
@@ -445,6 +465,25 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                     acc.collisions += (uint32_t)n_sc;
                     acc.surface += (uint32_t)n_surf;
                     st = ST_EMPTY;
+                }
+                if constexpr (LIST) {
+                    // stage this round's detections (the wave's whole set of
+                    // lanes takes part, so the staging fill stays uniform)
+                    const uint64_t dm = __ballot(det_now);
+                    if (dm != 0ull) {
+                        const uint32_t n_new = (uint32_t)__popcll(dm);
+                        if (l_fill + n_new > (uint32_t)LIST_STAGE) flush_list(set);
+                        if (det_now) {
+                            const uint32_t r = __builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(dm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)dm, 0u));
+                            ListEntry e;
+                            e.w = e_w;
+                            e.phase = e_phase;
+                            e.v = e_v;
+                            sL[l_fill + r] = e;
+                        }
+                        l_fill += n_new;
+                    }
                 }
                 uint64_t empty = __ballot(st == ST_EMPTY);
                 while (empty != 0ull && !exhausted) {
@@ -556,6 +595,9 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
             }
             }  // alive
         }
+        // the item's staged detections go out before the next item (which
+        // may belong to another set)
+        if constexpr (LIST) flush_list(set);
         __syncthreads();
     }
     if (cur_set >= 0) flush_set(cur_set);
@@ -639,7 +681,7 @@ hipError_t plan_transport(TransportShape& sh, int precision, bool list, int want
                           int lds_per_cu) {
     const int rb = precision == 1 ? 8 : 4;
     auto bytes = [&](int bits) {
-        return (int)lds_layout(rb, sh.max_layers, sh.max_cells, sh.max_bins, bits).bytes;
+        return (int)lds_layout(rb, sh.max_layers, sh.max_cells, sh.max_bins, bits, list ? sh.block / 64 : 0).bytes;
     };
     if (want_bits != 0) {
         if (want_bits < MIN_GUIDE_BITS || want_bits > GUIDE_BITS) return hipErrorInvalidValue;
