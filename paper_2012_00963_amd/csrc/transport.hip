@@ -193,12 +193,12 @@ __device__ __forceinline__ Real zeta_at(const SetConst<Real>& c, const Real* T, 
     return M<Real>::fma(-((Real)lo + frac), c.dzeta, c.v_top);
 }
 
-// Scattering angle (cos, sin) from the integer CDF: the cell is the last j
-// with C[j] <= x; it lies between the guide entries of the top guide_bits
-// bits of x; the angle is uniform inside the cell.
-template <typename Real>
-__device__ __forceinline__ void table_angle(const SetConst<Real>& c, const uint32_t* C, const uint16_t* cg,
-                                            int guide_bits, uint32_t x, Real& ct, Real& st) {
+// Scattering angle from the integer CDF: the cell is the last j with
+// C[j] <= x; it lies between the guide entries of the top guide_bits bits of
+// x; the angle is uniform inside the cell.  Returned in units of the cell
+// grid (cell index plus the fraction inside it).
+__device__ __forceinline__ int table_cell(const uint32_t* C, const uint16_t* cg, int guide_bits, uint32_t x,
+                                          uint32_t& cj, uint32_t& dw) {
     const uint32_t gi = x >> (32 - guide_bits);
     int lo = cg[gi];
     int hi = cg[gi + 1];
@@ -210,19 +210,17 @@ __device__ __forceinline__ void table_angle(const SetConst<Real>& c, const uint3
     }
     // C[n_cells] holds 0, so the last cell's width 2^32 - C[j] comes from the
     // unsigned wrap; a zero difference can only mean one cell holding all mass
-    const uint32_t cj = C[lo];
-    const uint32_t dw = C[lo + 1] - cj;
+    cj = C[lo];
+    dw = C[lo + 1] - cj;
+    return lo;
+}
+
+template <typename Real>
+__device__ __forceinline__ Real table_cells(const uint32_t* C, const uint16_t* cg, int guide_bits, uint32_t x) {
+    uint32_t cj, dw;
+    const int lo = table_cell(C, cg, guide_bits, x, cj, dw);
     const Real width = dw != 0u ? (Real)dw : (Real)4294967296.0;
-    const Real f = M<Real>::div((Real)(x - cj) + (Real)0.5, width);
-    if constexpr (sizeof(Real) == 4) {
-        const Real rev = ((Real)lo + f) * c.rev_per_cell;
-        ct = M<Real>::cos_rev(rev);
-        st = M<Real>::sin_rev(rev);
-    } else {
-        const Real theta = ((Real)lo + f) * c.dtheta;
-        ct = ::cos(theta);
-        st = ::sin(theta);
-    }
+    return (Real)lo + M<Real>::div((Real)(x - cj) + (Real)0.5, width);
 }
 
 template <typename Real>
@@ -532,31 +530,49 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
             const bool surf = mu < (Real)0 && Tn >= c.tau;
             const bool coll = !leave && !surf;
 
-            // particle interaction: scatterer speed, new direction
-            Real Vc = 0, mu_c = 0, omc_c = 0;
+            // particle interaction: scatterer speed, scattering angle
+            Real Vc = 0, cells = 0, ct = 0, st_ = 0;
             if (coll) {
                 Vc = zeta_at<Real, KIND>(c, sT, sLG, gshift, Tn);
-                Real ct, st_;
-                if (Kind<KIND>::table(c)) table_angle<Real>(c, sC, sCG, guide_bits, X.y, ct, st_);
+                if (Kind<KIND>::table(c)) cells = table_cells<Real>(sC, sCG, guide_bits, X.y);
                 else hg_angle<Real>(c, u1, ct, st_);
-                const Real cphi = M<Real>::cos_rev(u2);
-                const Real sm2 = ((Real)1.0 - mu) * ((Real)1.0 + mu);
-                Real m2 = M<Real>::fma(mu, ct, M<Real>::sqrt(sm2 > (Real)0 ? sm2 : (Real)0) * st_ * cphi);
-                m2 = M<Real>::clamp1(m2);
-                mu_c = m2;
-                omc_c = (Real)1.0 - m2;
             }
             // free-surface reflection (computed for every lane, selected below)
             Real mu_s, omc_s;
-            if (Kind<KIND>::lambert(c)) {
-                const Real r = M<Real>::sqrt(u1);
-                mu_s = r;
-                omc_s = M<Real>::div((Real)1.0 - u1, (Real)1.0 + r);
-            } else {
-                if constexpr (sizeof(Real) == 4) {
-                    mu_s = M<Real>::cos_rev((Real)0.25 * u1);
-                    const Real sh = M<Real>::sin_rev((Real)0.125 * u1);
+            if constexpr (sizeof(Real) == 4) {
+                // under the paper's surface law a lane needs one sine either
+                // way: of the scattering angle if it collides, of half the
+                // reflection angle if it reaches the surface
+                const bool paper_law = !Kind<KIND>::lambert(c);
+                Real sh = 0;
+                if (Kind<KIND>::table(c)) {
+                    const Real rev = cells * c.rev_per_cell;
+                    const Real sv = M<Real>::sin_rev(paper_law && surf ? (Real)0.125 * u1 : rev);
+                    ct = M<Real>::cos_rev(rev);
+                    st_ = sv;
+                    sh = sv;
+                } else if (paper_law) {
+                    sh = M<Real>::sin_rev((Real)0.125 * u1);
+                }
+                if (paper_law) {
+                    // cos(psi) = 1 - 2 sin^2(psi/2)
                     omc_s = (Real)2.0 * sh * sh;
+                    mu_s = (Real)1.0 - omc_s;
+                } else {
+                    const Real r = M<Real>::sqrt(u1);
+                    mu_s = r;
+                    omc_s = M<Real>::div((Real)1.0 - u1, (Real)1.0 + r);
+                }
+            } else {
+                if (Kind<KIND>::table(c)) {
+                    const Real theta = cells * c.dtheta;
+                    ct = ::cos(theta);
+                    st_ = ::sin(theta);
+                }
+                if (Kind<KIND>::lambert(c)) {
+                    const Real r = M<Real>::sqrt(u1);
+                    mu_s = r;
+                    omc_s = M<Real>::div((Real)1.0 - u1, (Real)1.0 + r);
                 } else {
                     const Real psi = (Real)0.5 * M<Real>::PI * u1;
                     const Real sh = ::sin((Real)0.5 * psi);
@@ -564,6 +580,12 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                     omc_s = (Real)2.0 * sh * sh;
                 }
             }
+            // new direction of a colliding lane (eq. 16)
+            const Real cphi = M<Real>::cos_rev(u2);
+            const Real sm2 = ((Real)1.0 - mu) * ((Real)1.0 + mu);
+            const Real mu_c = M<Real>::clamp1(
+                M<Real>::fma(mu, ct, M<Real>::sqrt(sm2 > (Real)0 ? sm2 : (Real)0) * st_ * cphi));
+            const Real omc_c = (Real)1.0 - mu_c;
             const Real V = surf ? c.v_surface : Vc;
             const Real mu_new = surf ? mu_s : mu_c;
             const Real omc = surf ? omc_s : omc_c;
