@@ -75,10 +75,14 @@ __host__ __device__ inline LdsLayout lds_layout(int real_bytes, int max_layers, 
                                                 int guide_bits, int list_waves) {
     const uint32_t guide_entries = (1u << guide_bits) + 1u;
     LdsLayout L;
+    // FP32 launches stage each layer depth and CDF entry beside the inverse
+    // width of its layer or cell (8-byte entries); FP64 launches stage the
+    // plain tables
+    const uint32_t t_entry = 8u, c_entry = real_bytes == 4 ? 8u : 4u;
     L.t_off = 0;
-    L.lg_off = align16(L.t_off + (uint32_t)real_bytes * (uint32_t)(max_layers + 1));
+    L.lg_off = align16(L.t_off + t_entry * (uint32_t)(max_layers + 1));
     L.cdf_off = align16(L.lg_off + 2u * guide_entries);
-    L.cg_off = align16(L.cdf_off + 4u * (uint32_t)(max_cells + 1));
+    L.cg_off = align16(L.cdf_off + c_entry * (uint32_t)(max_cells + 1));
     L.hist_off = align16(L.cg_off + 2u * guide_entries);
     L.hist2_off = align16(L.hist_off + 8u * (uint32_t)(max_bins + N_SINK_SLOTS));
     L.list_off = align16(L.hist2_off + 8u * (uint32_t)max_bins);
@@ -165,6 +169,24 @@ struct Kind {
     }
 };
 
+// Staged table entries: FP32 launches pair each layer depth T[j] with
+// 1/(T[j+1] - T[j]) and each CDF entry C[j] with 1/(C[j+1] - C[j]), so the
+// interpolation inside the found layer or cell reads one entry and
+// multiplies instead of dividing; FP64 launches divide, as the oracle does.
+template <typename Real> struct Staged;
+template <> struct Staged<float> {
+    using TE = float2;
+    using CE = uint2;
+};
+template <> struct Staged<double> {
+    using TE = double;
+    using CE = uint32_t;
+};
+__device__ __forceinline__ float key_of(const float2& e) { return e.x; }
+__device__ __forceinline__ double key_of(const double& e) { return e; }
+__device__ __forceinline__ uint32_t key_of(const uint2& e) { return e.x; }
+__device__ __forceinline__ uint32_t key_of(const uint32_t& e) { return e; }
+
 // Velocity coordinate at depth t.  Uniform density: zeta is linear in depth.
 // Otherwise the layer j with T[j] <= t < T[j+1] lies between the guide
 // entries of the cells just below and just above t x scale (padded by
@@ -172,8 +194,8 @@ struct Kind {
 // lower cell index rounds down and the upper one up.  zeta is linear inside
 // the layer.
 template <typename Real, int KIND>
-__device__ __forceinline__ Real zeta_at(const SetConst<Real>& c, const Real* T, const uint16_t* lg, int gshift,
-                                        Real t) {
+__device__ __forceinline__ Real zeta_at(const SetConst<Real>& c, const typename Staged<Real>::TE* T,
+                                        const uint16_t* lg, int gshift, Real t) {
     if (Kind<KIND>::uniform(c)) return M<Real>::fma(-t, c.zeta_per_tau, c.v_top);
     const Real x = t * c.lg_scale;
     int a = (int)(x - (Real)GUIDE_MARGIN);
@@ -185,11 +207,17 @@ __device__ __forceinline__ Real zeta_at(const SetConst<Real>& c, const Real* T, 
     hi = hi > c.n_layers - 1 ? c.n_layers - 1 : hi;
     while (__ballot(lo < hi) != 0ull) {
         const int mid = (lo + hi + 1) >> 1;
-        const bool le = T[mid] <= t;
+        const bool le = key_of(T[mid]) <= t;
         lo = le ? mid : lo;
         hi = le ? hi : mid - 1;
     }
-    const Real frac = M<Real>::div(t - T[lo], T[lo + 1] - T[lo]);
+    Real frac;
+    if constexpr (sizeof(Real) == 4) {
+        const float2 e = T[lo];
+        frac = (t - e.x) * e.y;
+    } else {
+        frac = M<Real>::div(t - T[lo], T[lo + 1] - T[lo]);
+    }
     return M<Real>::fma(-((Real)lo + frac), c.dzeta, c.v_top);
 }
 
@@ -197,30 +225,30 @@ __device__ __forceinline__ Real zeta_at(const SetConst<Real>& c, const Real* T, 
 // C[j] <= x; it lies between the guide entries of the top guide_bits bits of
 // x; the angle is uniform inside the cell.  Returned in units of the cell
 // grid (cell index plus the fraction inside it).
-__device__ __forceinline__ int table_cell(const uint32_t* C, const uint16_t* cg, int guide_bits, uint32_t x,
-                                          uint32_t& cj, uint32_t& dw) {
+template <typename Real>
+__device__ __forceinline__ Real table_cells(const typename Staged<Real>::CE* C, const uint16_t* cg, int guide_bits,
+                                            uint32_t x) {
     const uint32_t gi = x >> (32 - guide_bits);
     int lo = cg[gi];
     int hi = cg[gi + 1];
     while (__ballot(lo < hi) != 0ull) {
         const int mid = (lo + hi + 1) >> 1;
-        const bool le = C[mid] <= x;
+        const bool le = key_of(C[mid]) <= x;
         lo = le ? mid : lo;
         hi = le ? hi : mid - 1;
     }
-    // C[n_cells] holds 0, so the last cell's width 2^32 - C[j] comes from the
-    // unsigned wrap; a zero difference can only mean one cell holding all mass
-    cj = C[lo];
-    dw = C[lo + 1] - cj;
-    return lo;
-}
-
-template <typename Real>
-__device__ __forceinline__ Real table_cells(const uint32_t* C, const uint16_t* cg, int guide_bits, uint32_t x) {
-    uint32_t cj, dw;
-    const int lo = table_cell(C, cg, guide_bits, x, cj, dw);
-    const Real width = dw != 0u ? (Real)dw : (Real)4294967296.0;
-    return (Real)lo + M<Real>::div((Real)(x - cj) + (Real)0.5, width);
+    if constexpr (sizeof(Real) == 4) {
+        const uint2 e = C[lo];
+        return (Real)lo + ((Real)(x - e.x) + (Real)0.5) * __uint_as_float(e.y);
+    } else {
+        // C[n_cells] holds 0, so the last cell's width 2^32 - C[j] comes from
+        // the unsigned wrap; a zero difference can only mean one cell holding
+        // all mass
+        const uint32_t cj = C[lo];
+        const uint32_t dw = C[lo + 1] - cj;
+        const Real width = dw != 0u ? (Real)dw : (Real)4294967296.0;
+        return (Real)lo + M<Real>::div((Real)(x - cj) + (Real)0.5, width);
+    }
 }
 
 template <typename Real>
@@ -292,9 +320,11 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                                    LIST ? (int)(blockDim.x >> 6) : 0);
     const int gshift = GUIDE_BITS - guide_bits;
     const int n_guide = 1 << guide_bits;
-    Real* sT = (Real*)(lds + L.t_off);
+    using TE = typename Staged<Real>::TE;
+    using CE = typename Staged<Real>::CE;
+    TE* sT = (TE*)(lds + L.t_off);
     uint16_t* sLG = (uint16_t*)(lds + L.lg_off);
-    uint32_t* sC = (uint32_t*)(lds + L.cdf_off);
+    CE* sC = (CE*)(lds + L.cdf_off);
     uint16_t* sCG = (uint16_t*)(lds + L.cg_off);
     unsigned long long* sW = (unsigned long long*)(lds + L.hist_off);     // bins, then sink slots
     unsigned long long* sW2 = (unsigned long long*)(lds + L.hist2_off);
@@ -367,15 +397,38 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
             const SetDesc& d = descs[set];
             const uint8_t* tb = tables + d.tab_offset;
             if (!d.uniform_density) {
-                const Real* gT = (const Real*)(tb + (sizeof(Real) == 4 ? TableLayout::T32 : TableLayout::T64));
-                for (int i = tid; i <= d.n_layers; i += nthr) sT[i] = gT[i];
+                const double* gT64 = (const double*)(tb + TableLayout::T64);
+                if constexpr (sizeof(Real) == 4) {
+                    // the inverse widths come from the FP64 depths (an empty
+                    // layer, which no search returns, gets 0)
+                    const float* gT = (const float*)(tb + TableLayout::T32);
+                    for (int i = tid; i <= d.n_layers; i += nthr) {
+                        const double w = i < d.n_layers ? gT64[i + 1] - gT64[i] : 0.0;
+                        sT[i] = make_float2(gT[i], w > 0.0 ? (float)(1.0 / w) : 0.0f);
+                    }
+                } else {
+                    for (int i = tid; i <= d.n_layers; i += nthr) sT[i] = gT64[i];
+                }
                 const uint16_t* gLG = (const uint16_t*)(tb + TableLayout::LGUIDE);
                 for (int i = tid; i <= n_guide; i += nthr) sLG[i] = gLG[i << gshift];
             }
             if (d.phase_kind == PH_TABLE) {
                 const uint32_t* gC = (const uint32_t*)(tb + TableLayout::CDF);
-                for (int i = tid; i < d.n_cells; i += nthr) sC[i] = gC[i];
-                if (tid == 0) sC[d.n_cells] = 0u;
+                if constexpr (sizeof(Real) == 4) {
+                    // a cell's width is the next entry minus its own; the last
+                    // cell ends at 2^32 (a zero width can only mean one cell
+                    // holding all mass)
+                    for (int i = tid; i < d.n_cells; i += nthr) {
+                        const uint32_t cj = gC[i];
+                        const uint32_t dw = (i + 1 < d.n_cells ? gC[i + 1] : 0u) - cj;
+                        const double width = dw != 0u ? (double)dw : 4294967296.0;
+                        sC[i] = make_uint2(cj, __float_as_uint((float)(1.0 / width)));
+                    }
+                    if (tid == 0) sC[d.n_cells] = make_uint2(0u, 0u);
+                } else {
+                    for (int i = tid; i < d.n_cells; i += nthr) sC[i] = gC[i];
+                    if (tid == 0) sC[d.n_cells] = 0u;
+                }
                 const uint16_t* gCG = (const uint16_t*)(tb + TableLayout::CGUIDE);
                 for (int i = tid; i <= n_guide; i += nthr) sCG[i] = gCG[i << gshift];
             }
