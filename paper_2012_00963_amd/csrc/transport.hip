@@ -22,7 +22,9 @@
 // the azimuth, word 3 the analog absorption test.
 //
 // Execution shape: one packet per lane.  A block stages one parameter set's
-// tables (layer depths + uniform-depth guide, integer phase CDF + guide) and
+// tables (layer depths + uniform-depth guide, integer phase CDF + guide; in
+// FP32 each depth and CDF entry beside the inverse width of its layer or
+// cell) and
 // a private histogram in LDS; the histogram carries the velocity bins and
 // one slot per terminal sink, so every finished packet costs one LDS atomic
 // (two for a binned detection).  A finished lane keeps its packet's final
