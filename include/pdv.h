@@ -201,7 +201,7 @@ typedef struct pdv_launch_opts {
                                     that keeps the launch's blocks resident (a table layout: results are
                                     bitwise the same for every value) */
     int32_t retire_batch;        /* finished lanes a wave collects before it tallies and refills them,
-                                    1..64; 0 = default (FP32: 12, or 24 when detected lists are
+                                    1..64; 0 = default (FP32: 16, or 24 when detected lists are
                                     written; FP64: 1); results do not depend on it */
 } pdv_launch_opts;
 

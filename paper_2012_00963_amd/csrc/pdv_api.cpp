@@ -455,13 +455,14 @@ void pdv_ctx::default_opts(pdv_launch_opts& o, uint64_t total_packets, int n_set
     if (o.blocks_per_cu <= 0) o.blocks_per_cu = tuned.blocks_per_cu > 0 ? tuned.blocks_per_cu : def_bpc;
     if (o.persistent < 0) o.persistent = tuned.persistent >= 0 ? tuned.persistent : 1;
     if (o.guide_bits == 0) o.guide_bits = tuned.guide_bits;
-    // measured: 12 for FP32 spectra of the large case; 24 when detected
+    // measured: 16 for FP32 spectra (12-16 equal on the large Mie case, 16
+    // best by 2 % on the HG slab); 24 when detected
     // packets are also appended to lists (a retire round then also stages
     // its detections: 12 / 24 / 48 / 64 gave 3.57 / 3.03 / 3.15 / 4.54 ms
     // for the 256-frame spectrogram's transport); FP64 is fastest tallying
     // every round
     if (o.retire_batch == 0)
-        o.retire_batch = tuned.retire_batch > 0 ? tuned.retire_batch : (fp64 ? 1 : (list ? 24 : 12));
+        o.retire_batch = tuned.retire_batch > 0 ? tuned.retire_batch : (fp64 ? 1 : (list ? 24 : 16));
     if (o.packets_per_item == 0) {
         // three large items per block, rounded up so that the item count
         // does not spill into a further round: every item ends with a block
