@@ -12,11 +12,15 @@
 //
 // Kernels:
 //   synth_partial   one block per (frame, chunk of list entries): entries are
-//                   staged in LDS and every thread accumulates its samples;
-//                   the phase f n / fs + phi0 is formed with an FP64 fused
-//                   multiply-add and reduced to [0,1) in FP64 (records reach
-//                   tens of thousands of cycles), the cosine is taken in FP32
-//                   on the revolution-argument hardware unit;
+//                   staged in LDS and every thread accumulates a run of
+//                   consecutive samples; at the run's first sample the phase
+//                   f n / fs + phi0 is formed with an FP64 fused multiply-add
+//                   and reduced to [0,1) in FP64 (records reach tens of
+//                   thousands of cycles), its cosine and sine taken in FP32
+//                   on the revolution-argument hardware unit; each further
+//                   sample of the run rotates that pair by the entry's phase
+//                   step per sample (cos and sin of 2 pi frac(f / fs), formed
+//                   in FP64 when the entry is staged);
 //   synth_reduce    sums the per-chunk partials in fixed order (deterministic);
 //   stft_kernel     one block per window: real FFT of nfft points through an
 //                   nfft/2-point complex Stockham FFT in LDS (radix 4, one
@@ -35,48 +39,59 @@ struct SynthFrame {
 };
 
 constexpr int SYNTH_CHUNK = 1024;       // entries staged per block
-constexpr int SYNTH_THREADS = 256;
+constexpr int SYNTH_THREADS = 128;
+constexpr int SYNTH_RUN = 4;            // consecutive samples per thread and pass
 
-// NQ samples per thread, spaced by the block size, over the staged entries.
+// NQ consecutive samples per thread, starting at base + NQ x thread, over
+// the staged entries; a thread whose run starts past the frame's samples
+// has nothing to do.
 template <int NQ>
 __device__ __forceinline__ void synth_samples(const SynthFrame& F, int base, int ne, const double* s_r,
-                                              const double* s_ph, const float* s_a, float* out) {
-    double nn[NQ];
+                                              const double* s_ph, const float* s_a, const float2* s_rot,
+                                              float* out) {
+    const int j0 = base + (int)threadIdx.x * NQ;
+    if (j0 >= F.s_count) return;
+    const double n0 = (double)(F.s_begin + j0);
     float acc[NQ];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        nn[q] = (double)(F.s_begin + base + threadIdx.x + q * SYNTH_THREADS);
-        acc[q] = 0.f;
-    }
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.f;
     for (int i = 0; i < ne; ++i) {
-        const double r = s_r[i], ph = s_ph[i];
+        // fractional cycles in one v_fract_f64 (x - floor(x), exact; its
+        // clamp below 1 only matters where the FP32 rounding gives 1 anyway)
+        const float cyc = (float)__builtin_amdgcn_fract(fma(s_r[i], n0, s_ph[i]));
         const float a = s_a[i];
+        float c = __builtin_amdgcn_cosf(cyc);
+        acc[0] = fmaf(a, c, acc[0]);
+        if constexpr (NQ > 1) {
+            float sn = __builtin_amdgcn_sinf(cyc);
+            const float2 rot = s_rot[i];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            // fractional cycles in one v_fract_f64 (x - floor(x), exact; its
-            // clamp below 1 only matters where the FP32 rounding gives 1 anyway)
-            const double cyc = __builtin_amdgcn_fract(fma(r, nn[q], ph));
-            acc[q] = fmaf(a, __builtin_amdgcn_cosf((float)cyc), acc[q]);
+            for (int q = 1; q < NQ; ++q) {
+                const float c2 = fmaf(c, rot.x, -sn * rot.y);
+                sn = fmaf(c, rot.y, sn * rot.x);
+                c = c2;
+                acc[q] = fmaf(a, c, acc[q]);
+            }
         }
     }
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        const int j = base + threadIdx.x + q * SYNTH_THREADS;
-        if (j < F.s_count) out[j] = acc[q];
+        if (j0 + q < F.s_count) out[j0 + q] = acc[q];
     }
 }
 
 // Accumulate sqrt(w) cos(2 pi frac(r n + phi)) for the frame's samples over
 // one chunk of entries; r = 2 v / (lambda fs) cycles per sample.  A thread
-// takes up to four samples (sharing each entry read); the count is cut to
-// what the frame's samples need, so a frame of a few hundred samples does
-// not compute discarded ones.
+// takes a run of up to SYNTH_RUN consecutive samples per pass (sharing each
+// entry read and one exact phase); the run length is cut to what the frame's
+// remaining samples need.
 __global__ void __launch_bounds__(SYNTH_THREADS)
 synth_partial_kernel(const SynthFrame* __restrict__ frames, const ListEntry* __restrict__ entries,
                      double two_over_lambda_fs, int n_chunks, int max_samples, float* __restrict__ partial) {
     __shared__ double s_r[SYNTH_CHUNK];
     __shared__ double s_ph[SYNTH_CHUNK];
     __shared__ float s_a[SYNTH_CHUNK];
+    __shared__ float2 s_rot[SYNTH_CHUNK];
     const int f = blockIdx.x;
     const int ch = blockIdx.y;
     const SynthFrame F = frames[f];
@@ -85,19 +100,23 @@ synth_partial_kernel(const SynthFrame* __restrict__ frames, const ListEntry* __r
     ne = ne < 0 ? 0 : (ne > SYNTH_CHUNK ? SYNTH_CHUNK : ne);
     for (int i = threadIdx.x; i < ne; i += blockDim.x) {
         const ListEntry E = entries[F.entry_begin + (uint64_t)(e0 + i)];
-        s_r[i] = E.v * two_over_lambda_fs;
+        const double r = E.v * two_over_lambda_fs;
+        s_r[i] = r;
+        double sn, cs;
+        sincospi(2.0 * (r - floor(r)), &sn, &cs);
+        s_rot[i] = make_float2((float)cs, (float)sn);
         s_ph[i] = (double)E.phase * 2.3283064365386963e-10;   // 2^-32
         s_a[i] = sqrtf(E.w);
     }
     __syncthreads();
     float* out = partial + ((uint64_t)f * n_chunks + ch) * (uint64_t)max_samples;
-    for (int base = 0; base < F.s_count; base += 4 * SYNTH_THREADS) {
+    for (int base = 0; base < F.s_count; base += SYNTH_RUN * SYNTH_THREADS) {
         const int left = F.s_count - base;
-        const int nq = left >= 4 * SYNTH_THREADS ? 4 : (left + SYNTH_THREADS - 1) / SYNTH_THREADS;
-        if (nq == 4) synth_samples<4>(F, base, ne, s_r, s_ph, s_a, out);
-        else if (nq == 3) synth_samples<3>(F, base, ne, s_r, s_ph, s_a, out);
-        else if (nq == 2) synth_samples<2>(F, base, ne, s_r, s_ph, s_a, out);
-        else synth_samples<1>(F, base, ne, s_r, s_ph, s_a, out);
+        const int nq = left >= SYNTH_RUN * SYNTH_THREADS ? SYNTH_RUN : (left + SYNTH_THREADS - 1) / SYNTH_THREADS;
+        if (nq == 4) synth_samples<4>(F, base, ne, s_r, s_ph, s_a, s_rot, out);
+        else if (nq == 3) synth_samples<3>(F, base, ne, s_r, s_ph, s_a, s_rot, out);
+        else if (nq == 2) synth_samples<2>(F, base, ne, s_r, s_ph, s_a, s_rot, out);
+        else synth_samples<1>(F, base, ne, s_r, s_ph, s_a, s_rot, out);
     }
 }
 
