@@ -61,6 +61,35 @@ def test_beat_synthesis_matches_oracle(ctx):
     assert rel_l2(g, o) <= 1e-4, rel_l2(g, o)
 
 
+# frame lengths whose sample runs per thread are 1, 3, and 4 with a ragged
+# tail; the last case is a long record (4e5 samples per frame, phases up to
+# ~1e5 cycles) where only the FP64 phase at each run's start keeps the
+# carried phase exact
+@pytest.mark.parametrize("n_frames,ns,max_m", [(9, 9 * 100 + 4, 400), (6, 6 * 300 + 1, 400),
+                                               (4, 4 * 1537, 400), (5, 2_000_003, 40)])
+def test_beat_synthesis_sample_runs(ctx, n_frames, ns, max_m):
+    print("case beat runs", n_frames, ns, max_m, flush=True)
+    rng = np.random.Generator(np.random.PCG64(ns))
+    fs, lam = 20e9, 1550e-9
+    lists_o, lists_g = [], []
+    for k in range(n_frames):
+        m = int(rng.integers(1, max_m + 1))
+        w = rng.uniform(0.01, 1.0, m).astype(np.float32)
+        v = rng.uniform(0.0, 4000.0, m)
+        ph = rng.integers(0, 2**32, m, dtype=np.uint64).astype(np.uint32)
+        lists_g.append({"w": w, "v": v, "phase_u32": ph})
+        lists_o.append({"w": w.astype(np.float64), "v": v, "phase": ph.astype(np.float64) / 2**32})
+    g = ctx.beat_synthesize(lists_g, lam, fs, ns)
+    o = ostage2.beat_signal(lists_o, ns, fs, lam)
+    assert g.shape == o.shape
+    assert rel_l2(g, o) <= 1e-4, rel_l2(g, o)
+    # every frame's samples, the last of each run included, carry signal
+    b = ostage2.frame_bounds(ns, n_frames)
+    for k in range(n_frames):
+        seg_g, seg_o = g[b[k]:b[k + 1]], o[b[k]:b[k + 1]]
+        assert rel_l2(seg_g, seg_o) <= 1e-4, (k, rel_l2(seg_g, seg_o))
+
+
 def _oracle_frames(oracle_mc, p, sg):
     tabs = oracle_mc.set_tables(p)
     lists, spec = [], np.zeros(p["n_bins"])
