@@ -96,3 +96,68 @@ def test_ensemble_tables_large_case():
     cdf = tables.phase_cdf(ens["phase"])
     m1 = tables.table_moments(cdf, 1)
     assert abs(m1 - ens["g"]) < 3e-3, (m1, ens["g"])
+
+
+# ---- size-averaged optics (eq. 11 with the cross-sections of eq. 8, 12) ----
+# A particle of diameter d has C_sca = (pi d^2 / 4) Q_sca and
+# C_ext = (pi d^2 / 4) Q_ext; the ensemble albedo is sum n C_sca / sum n C_ext
+# and the ensemble intensity is the number-weighted sum of |S1|^2 + |S2|^2
+# (all sizes share the wavenumber).
+
+LAM = 1550e-9
+
+
+def test_ensemble_monodisperse_limit():
+    # a log-normal truncated to a relative width of 2e-6 around d0 is one size
+    d0 = 3.7e-6
+    d, w = tables.lognormal_nodes(d0, 0.5, d0 * math.exp(-1e-6), d0 * math.exp(1e-6), 16)
+    ens = tables.mie_ensemble(M_C2, LAM, d, w, 181)
+    x0 = np.array([math.pi * d0 / LAM])
+    q_ext, q_sca, g = mie.efficiencies(M_C2, x0)
+    assert abs(ens["albedo"] - q_sca[0] / q_ext[0]) < 1e-8
+    assert abs(ens["g"] - g[0]) < 1e-8
+    th = tables.angle_grid(181)
+    S1, S2 = mie.amplitudes(M_C2, x0, th)
+    i0 = np.abs(S1[0]) ** 2 + np.abs(S2[0]) ** 2
+    shape = ens["phase"] / ens["phase"][0]
+    assert np.allclose(shape, i0 / i0[0], rtol=1e-7, atol=0)
+
+
+def test_ensemble_two_size_mixture_by_hand():
+    # a small absorbing sphere (low albedo) and a large one, 40 : 1 in number
+    d = np.array([0.25e-6, 6.0e-6])
+    n = np.array([40.0, 1.0])
+    ens = tables.mie_ensemble(M_C2, LAM, d, n, 721)
+    x = math.pi * d / LAM
+    q_ext, q_sca, g = mie.efficiencies(M_C2, x)
+    area = math.pi * d * d / 4.0
+    c_sca = n * area * q_sca
+    c_ext = n * area * q_ext
+    albedo = c_sca.sum() / c_ext.sum()
+    assert abs(ens["albedo"] - albedo) < 1e-12
+    assert abs(ens["g"] - (c_sca * g).sum() / c_sca.sum()) < 1e-12
+    # the two sizes' albedos differ widely, so a cross-section weighted by d
+    # instead of d^2 moves the mixture's albedo far outside the tolerance
+    area_d = math.pi * d / 4.0
+    wrong = (n * area_d * q_sca).sum() / (n * area_d * q_ext).sum()
+    assert abs(wrong - albedo) > 1e-2
+    # the ensemble intensity integrates to the scattering cross-section sum:
+    # int (|S1|^2+|S2|^2) sin(theta) dtheta = x^2 Q_sca per particle
+    th = tables.angle_grid(721)
+    integral = integrate.simpson(ens["phase"] * np.sin(th), x=th)
+    assert abs(integral / (n * x * x * q_sca).sum() - 1.0) < 1e-5
+
+
+def test_ensemble_albedo_against_direct_size_integral():
+    # eq. 21's number density over d itself (not ln d), trapezoid rule on a
+    # fine linear grid, cross-sections pi d^2 / 4: an independent route to
+    # the size average that the Gauss-Legendre nodes in ln d must reproduce
+    d_m, s, a, b = 3e-6, 0.5, 0.5e-6, 20e-6
+    dg = np.linspace(a, b, 6001)
+    f = np.exp(-(np.log(dg / d_m) ** 2) / (2 * s * s)) / (math.sqrt(2 * math.pi) * s * dg)
+    q_ext, q_sca, _ = mie.efficiencies(M_C2, math.pi * dg / LAM)
+    area = math.pi * dg * dg / 4.0
+    ref = np.trapezoid(f * area * q_sca, dg) / np.trapezoid(f * area * q_ext, dg)
+    dn, wn = tables.lognormal_nodes(d_m, s, a, b, 256)
+    ens = tables.mie_ensemble(M_C2, LAM, dn, wn, 64)
+    assert abs(ens["albedo"] - ref) < 2e-6 * ref, (ens["albedo"], ref)
