@@ -65,6 +65,7 @@ class _Out(ctypes.Structure):
         ("list_capacity", ctypes.c_uint64), ("list_count", ctypes.c_uint64),
         ("list_w", ctypes.POINTER(ctypes.c_double)), ("list_v", ctypes.POINTER(ctypes.c_double)),
         ("list_phase", ctypes.POINTER(ctypes.c_double)), ("list_pid", ctypes.POINTER(ctypes.c_uint64)),
+        ("list_err32", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -189,8 +190,10 @@ def run(p: dict, n_threads: int | None = None, pid_begin: int = 0, n_packets: in
     if list_capacity:
         lw, lv, lph = np.zeros(list_capacity), np.zeros(list_capacity), np.zeros(list_capacity)
         lpid = np.zeros(list_capacity, dtype=np.uint64)
+        lerr = np.zeros(list_capacity)
         out.list_w, out.list_v, out.list_phase = _dptr(lw), _dptr(lv), _dptr(lph)
         out.list_pid = lpid.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+        out.list_err32 = _dptr(lerr)
     rc = lib().oracle_run(ctypes.byref(cp), ctypes.byref(out))
     if rc != 0:
         raise ValueError("oracle_run rejected the parameters")
@@ -205,7 +208,9 @@ def run(p: dict, n_threads: int | None = None, pid_begin: int = 0, n_packets: in
         res["W_single"], res["W_surface"] = Ws, Wsf
     if list_capacity:
         n = min(int(out.list_count), list_capacity)
-        res["list"] = {"w": lw[:n], "v": lv[:n], "phase": lph[:n], "pid": lpid[:n]}
+        # err32: first-order bound on an FP32 evaluation's deviation of v
+        # along the same path (see Fp32Bound in pdv_oracle.cpp)
+        res["list"] = {"w": lw[:n], "v": lv[:n], "phase": lph[:n], "pid": lpid[:n], "err32": lerr[:n]}
         res["list_count"] = int(out.list_count)
     return res
 

@@ -131,6 +131,9 @@ typedef struct {
     double* list_v;
     double* list_phase;
     uint64_t* list_pid;
+    /* nullable: first-order bound on how far an FP32 evaluation of the same
+     * path (same branch decisions) can move the apparent velocity */
+    double* list_err32;
 } oracle_out;
 
 void oracle_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
@@ -146,8 +149,67 @@ struct Tally {
     double sinks[N_SINKS] = {0};
     uint64_t counts[N_COUNTS] = {0};
     bool keep_list = false;
-    std::vector<double> lw, lv, lph;
+    std::vector<double> lw, lv, lph, lerr;
     std::vector<uint64_t> lpid;
+};
+
+// ---------------------------------------------------------------------------
+// First-order rounding bound of an FP32 evaluation of one packet's path.
+//
+// Carried beside the FP64 path only when detected lists are kept: absolute
+// bounds on the FP32 depth (eT), direction cosine (eMu) and the two Doppler
+// accumulators (eBig, eSmall), given that every branch decision (flight end,
+// cell, exit, cone, bin) comes out the same.  U = 2^-24 is the FP32 unit
+// roundoff; each formula adds the inputs' propagated errors (partial
+// derivative times input error) and the roundings of the operations, with a
+// few U for the hardware transcendental units (log, sin, cos, sqrt, rcp).
+// The apparent velocity is the FP64 difference of the two FP32
+// accumulators, so its bound is eBig + eSmall.
+// ---------------------------------------------------------------------------
+struct Fp32Bound {
+    static constexpr double U = 5.9604644775390625e-08;   // 2^-24
+    double eT = 0.0, eMu = 0.0, eBig = 0.0, eSmall = 0.0;
+
+    // free path s = -ln u0 and the new depth T + s (-mu)
+    double flight(double s, double mu, double Tn) const {
+        const double es = 4.0 * U * (s + 1.0);
+        return eT + std::fabs(mu) * es + s * eMu + U * std::fabs(Tn);
+    }
+    // accumulator update acc += term with the term's own error e_term
+    static double acc(double e_acc, double e_term, double term, double acc_new) {
+        return e_acc + e_term + 2.0 * U * std::fabs(term) + U * std::fabs(acc_new);
+    }
+    // collision at depth Tn (error eTn) in a layer of slope dzeta/dT, new
+    // cosine from the polar angle (cosine x, sine sn, their errors ex, es)
+    // and the azimuth cosine cphi
+    void collision(double eTn, double Tn, double slope, double V, double mu, double x, double sn, double ex,
+                   double es, double cphi, double mu_new, double big_new, double small_new) {
+        const double eV = slope * (eTn + 2.0 * U * std::fabs(Tn)) + 4.0 * U * std::fabs(V);
+        const double r = std::sqrt(std::fmax(0.0, (1.0 - mu) * (1.0 + mu)));
+        const double er = std::fabs(mu) * eMu / std::fmax(r, std::sqrt(2.0 * eMu + 2.0 * U)) + 2.0 * U;
+        const double ecphi = 4.0 * U;
+        const double eMu_new = std::fabs(x) * eMu + std::fabs(mu) * ex + std::fabs(sn * cphi) * er +
+                               std::fabs(r * cphi) * es + std::fabs(r * sn) * ecphi + 3.0 * U;
+        const double tb = 0.5 * V * (1.0 - mu), ts = 0.5 * V * (1.0 - mu_new);
+        eBig = acc(eBig, 0.5 * ((1.0 - mu) * eV + V * (eMu + U)), tb, big_new);
+        eSmall = acc(eSmall, 0.5 * ((1.0 - mu_new) * eV + V * (eMu_new + U)), ts, small_new);
+        eMu = eMu_new;
+        eT = eTn;
+    }
+    // reflection off the surface at speed vs: new cosine 1 - omc with its
+    // complement omc computed directly (error eOmc)
+    void surface(double vs, double mu, double omc, double eOmc, double eMu_new, double tau, double big_new,
+                 double small_new) {
+        const double tb = 0.5 * vs * (1.0 - mu), ts = 0.5 * vs * omc;
+        eBig = acc(eBig, 0.5 * vs * (eMu + U), tb, big_new);
+        eSmall = acc(eSmall, 0.5 * vs * eOmc, ts, small_new);
+        eMu = eMu_new;
+        eT = U * tau;                 // the depth is reset to the FP32 slab depth
+    }
+    // error of a sine formed as sqrt((1 - x)(1 + x)) from a cosine of error ex
+    static double sine_err(double x, double sn, double ex) {
+        return std::fabs(x) * ex / std::fmax(sn, std::sqrt(2.0 * ex)) + 2.0 * U;
+    }
 };
 
 // Layer holding depth t, searched by bisection: T[j] <= t < T[j+1].
@@ -206,11 +268,17 @@ void hg_angle(double g, double u, double* c, double* s) {
 // New vertical direction cosine after a particle scattering: polar angle
 // from the phase function, azimuth uniform (eq. 15), and the third line of the
 // direction update (eq. 16), clamped to [-1, 1].
-double scattered_mu(const oracle_params& p, double mu, uint32_t x1, double u1, double u2) {
+// cth, sth, cphi (nullable) receive the polar angle's cosine and sine and
+// the azimuth's cosine.
+double scattered_mu(const oracle_params& p, double mu, uint32_t x1, double u1, double u2,
+                    double* cth_out = nullptr, double* sth_out = nullptr, double* cphi_out = nullptr) {
     double cth, sth;
     if (p.phase_kind == PHASE_TABLE) table_angle(p, x1, &cth, &sth);
     else hg_angle(p.hg_g, u1, &cth, &sth);
     const double cphi = std::cos(2.0 * PI * u2);
+    if (cth_out) *cth_out = cth;
+    if (sth_out) *sth_out = sth;
+    if (cphi_out) *cphi_out = cphi;
     double mu_new = mu * cth + std::sqrt((1.0 - mu) * (1.0 + mu)) * sth * cphi;
     if (mu_new > 1.0) mu_new = 1.0;
     if (mu_new < -1.0) mu_new = -1.0;
@@ -228,6 +296,7 @@ void run_packet(const oracle_params& p, uint64_t pid, Tally& t) {
     double big = 0.0, small = 0.0;   // apparent velocity = big - small
     int n_sc = 0, n_surf = 0;
     t.counts[CNT_PACKETS] += 1;
+    Fp32Bound fb;                    // kept only for detected lists
 
     for (uint32_t k = 0;; ++k) {
         const uint32_t ctr[4] = {k, pid_lo, pid_hi, p.stream};
@@ -266,6 +335,14 @@ void run_packet(const oracle_params& p, uint64_t pid, Tally& t) {
                 t.sinks[SINK_ABSORBED_SURFACE] += w * (1.0 - p.surface_albedo);
                 w *= p.surface_albedo;
             }
+            if (t.keep_list) {
+                const double U = Fp32Bound::U;
+                const bool lambert = p.surface_law == SURFACE_LAMBERT;
+                const double e_omc = (lambert ? 6.0 : 9.0) * U * one_minus_mu_new;
+                const double e_mu = lambert ? 2.0 * U * mu_new : e_omc + U;
+                fb.surface(p.v_surface, mu, one_minus_mu_new, e_omc, e_mu, p.tau_total,
+                           big + 0.5 * p.v_surface * (1.0 - mu), small + 0.5 * p.v_surface * one_minus_mu_new);
+            }
             big += 0.5 * p.v_surface * (1.0 - mu);
             small += 0.5 * p.v_surface * one_minus_mu_new;
             mu = mu_new;
@@ -301,6 +378,7 @@ void run_packet(const oracle_params& p, uint64_t pid, Tally& t) {
                     t.lv.push_back(v);
                     t.lph.push_back((double)P[0] * (1.0 / 4294967296.0));
                     t.lpid.push_back(pid);
+                    t.lerr.push_back(fb.eBig + fb.eSmall);
                 }
             } else {
                 t.sinks[SINK_UNDETECTED] += w;
@@ -326,7 +404,34 @@ void run_packet(const oracle_params& p, uint64_t pid, Tally& t) {
         }
         n_sc += 1;
 
-        const double mu_new = scattered_mu(p, mu, X[1], u1, u2);
+        double cth = 0.0, sth = 0.0, cphi = 0.0;
+        const double mu_new = scattered_mu(p, mu, X[1], u1, u2, &cth, &sth, &cphi);
+        if (t.keep_list) {
+            // FP32 errors of the polar angle's cosine and sine: a tabulated
+            // angle comes from the hardware cosine and sine of the cell
+            // position; the HG cosine from its inversion (expanded form
+            // below |g| = 0.1, direct form above, whose rounding is divided
+            // by 2|g|), its sine as sqrt((1 - x)(1 + x))
+            const double U = Fp32Bound::U;
+            double ex, es;
+            if (p.phase_kind == PHASE_TABLE) {
+                ex = es = 4.0 * U * std::acos(cth) + 4.0 * U;
+            } else {
+                const double g = p.hg_g;
+                if (std::fabs(g) < 0.1) {
+                    ex = 8.0 * U;
+                } else {
+                    const double q = (1.0 - g * g) / (1.0 - g + 2.0 * g * u1);
+                    ex = (6.0 * U * q * q + U * (1.0 + g * g) + U * std::fabs(1.0 + g * g - q * q)) /
+                         (2.0 * std::fabs(g)) + 2.0 * U;
+                }
+                es = Fp32Bound::sine_err(cth, sth, ex);
+            }
+            const int j = find_layer(p, Tn);
+            const double slope = (p.v_top - p.v_bottom) / p.n_layers / (p.T[j + 1] - p.T[j]);
+            fb.collision(fb.flight(-std::log(u0), mu, Tn), Tn, slope, V, mu, cth, sth, ex, es, cphi, mu_new,
+                         big + 0.5 * V * (1.0 - mu), small + 0.5 * V * (1.0 - mu_new));
+        }
         big += 0.5 * V * (1.0 - mu);
         small += 0.5 * V * (1.0 - mu_new);
         mu = mu_new;
@@ -389,6 +494,7 @@ int oracle_run(const oracle_params* p, oracle_out* out) {
                 if (out->list_v) out->list_v[n_list] = t.lv[j];
                 if (out->list_phase) out->list_phase[n_list] = t.lph[j];
                 if (out->list_pid) out->list_pid[n_list] = t.lpid[j];
+                if (out->list_err32) out->list_err32[n_list] = t.lerr[j];
             }
         }
     }

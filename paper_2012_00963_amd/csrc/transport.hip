@@ -55,6 +55,10 @@ struct LdsLayout {
 // FP64 depths the guide was built from (both below 2^-8 of a cell).
 constexpr float GUIDE_MARGIN = 1.0f / 32.0f;
 
+// Henyey-Greenstein asymmetries below this magnitude take the expanded,
+// cancellation-free inversion in FP32 (hg_angle)
+constexpr double HG_SMALL_G = 0.1;
+
 __host__ __device__ inline uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
 
 // terminal-sink slots follow the velocity bins in the LDS histogram
@@ -95,12 +99,12 @@ __host__ __device__ inline LdsLayout lds_layout(int real_bytes, int max_layers, 
 template <typename Real>
 struct SetConst {            // wave-uniform per-set constants (kept in SGPRs)
     Real tau, v_top, dzeta, zeta_per_tau, v_surface, surface_albedo, albedo, cos_cone;
-    Real hg_a, hg_b, hg_c0, hg_c1, hg_inv2g;
+    Real hg_a, hg_b, hg_c0, hg_c1, hg_inv2g, hg_g;
     Real lg_scale, rev_per_cell, dtheta;
     double v_lo, dv, inv_dv;
     uint32_t k0, k1, stream, thr_albedo, thr_surface, flags;
     int n_layers, n_cells, n_bins, max_orders, phase_kind, surface_law, weighting;
-    int albedo_one, surface_one, hg_zero, uniform_density;
+    int albedo_one, surface_one, hg_zero, hg_small, uniform_density;
 };
 
 template <typename Real>
@@ -124,7 +128,9 @@ __device__ __forceinline__ SetConst<Real> load_const(const SetDesc& d) {
     c.hg_c0 = (Real)d.hg_c0;
     c.hg_c1 = (Real)d.hg_c1;
     c.hg_inv2g = (Real)d.hg_inv2g;
+    c.hg_g = (Real)d.hg_g;
     c.hg_zero = d.hg_g == 0.0;
+    c.hg_small = d.hg_g > -HG_SMALL_G && d.hg_g < HG_SMALL_G;
     c.lg_scale = (Real)d.lg_scale;
     c.rev_per_cell = (Real)d.rev_per_cell;
     c.dtheta = (Real)d.dtheta;
@@ -253,10 +259,30 @@ __device__ __forceinline__ Real table_cells(const typename Staged<Real>::CE* C, 
     }
 }
 
+// Henyey-Greenstein polar cosine by inversion of its cumulative
+// distribution (eq. 13's phase function replaced by the HG law):
+//   cos = (1 + g^2 - q^2) / (2g),  q = (1 - g^2) / (1 + g s),  s = 2u - 1.
+// Written this way the FP32 numerator cancels to O(g) while its rounding
+// stays O(2^-24), so the cosine's error grows as 2^-24/|g| (about 1e-3 at
+// g = 1e-4).  Expanding the numerator and dividing out the common factor 2g
+// gives the same function without the cancellation,
+//   cos = [s + g (s^2 + 3)/2 + g^2 s + g^3 (s^2 - 1)/2] / (1 + g s)^2,
+// which the FP32 kernels use for |g| < HG_SMALL_G (exactly 2u - 1 at g = 0);
+// beyond it the direct form is the better conditioned one (the expanded
+// numerator cancels for back-scattering at large g).  FP64 keeps the direct
+// form, whose error 2^-53/|g| stays below 1e-12 for |g| >= 1e-4.
+
 template <typename Real>
 __device__ __forceinline__ void hg_angle(const SetConst<Real>& c, Real u, Real& ct, Real& st) {
     Real x;
-    if (c.hg_zero) {
+    if (sizeof(Real) == 4 && c.hg_small) {
+        const Real s = M<Real>::fma((Real)2.0, u, (Real)-1.0);       // exact
+        const Real t = M<Real>::fma(c.hg_g, s, (Real)1.0);
+        const Real s2 = s * s;
+        const Real inner = M<Real>::fma((Real)0.5 * c.hg_g, s2 - (Real)1.0, s);
+        const Real mid = M<Real>::fma(c.hg_g, inner, M<Real>::fma((Real)0.5, s2, (Real)1.5));
+        x = M<Real>::fma(c.hg_g, mid, s) * M<Real>::rcp(t * t);
+    } else if (c.hg_zero) {
         x = M<Real>::fma((Real)2.0, u, (Real)-1.0);
     } else {
         const Real q = M<Real>::div(c.hg_b, M<Real>::fma(c.hg_c1, u, c.hg_c0));

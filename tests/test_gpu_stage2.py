@@ -109,8 +109,14 @@ def test_spectrogram_end_to_end(ctx, oracle_mc, precision):
     g = ctx.spectrogram(p, sg, want_signal=True, want_spectrum=True, want_lists=True)
     assert not g["overflow"]
     lists_o, spec_o = _oracle_frames(oracle_mc, p, sg)
-    # detected lists, matched entry by entry through their random phase word
+    # detected lists, matched entry by entry through their random phase word.
+    # Velocity tolerance: FP64 follows the oracle's arithmetic (1e-8 m/s);
+    # in FP32 each entry must lie within the first-order bound of an FP32
+    # evaluation of its own path that the oracle carries (list "err32":
+    # depth, direction and accumulator roundings propagated event by event,
+    # pinned on the CPU by float32 replays of detected paths)
     unmatched = 0
+    ratios = []
     for k, (Lg, Lo) in enumerate(zip(g["lists"], lists_o)):
         po = np.round(Lo["phase"] * 2**32).astype(np.uint64)
         ko = {int(x): i for i, x in enumerate(po)}
@@ -119,13 +125,19 @@ def test_spectrogram_end_to_end(ctx, oracle_mc, precision):
             if i is None:
                 unmatched += 1
                 continue
-            # FP32 accumulation over a multiply scattered path: a few 1e-3 m/s
-            # (bins are 7.8 m/s); FP64 follows the oracle's arithmetic
-            vtol = 4e-2 if precision == 0 else 1e-8
-            assert abs(Lg["v"][j] - Lo["v"][i]) <= vtol, (k, j, Lg["v"][j], Lo["v"][i])
+            dv = abs(Lg["v"][j] - Lo["v"][i])
+            if precision == 0:
+                ratios.append(dv / Lo["err32"][i])
+            else:
+                assert dv <= 1e-8, (k, j, Lg["v"][j], Lo["v"][i])
             assert abs(Lg["w"][j] - Lo["w"][i]) <= 1e-6 * Lo["w"][i] + 1e-9
         unmatched += max(0, len(Lo["w"]) - len(Lg["w"]))
     assert unmatched <= (3 if precision == 0 else 0), unmatched
+    if precision == 0:
+        r = np.array(ratios)
+        print("list velocity error / FP32 bound: max %.3g, p99 %.3g, p50 %.3g over %d entries"
+              % (r.max(), np.percentile(r, 99), np.median(r), len(r)), flush=True)
+        assert r.max() <= 1.0, r.max()
     # synthesis of the GPU's own lists matches the FP64 oracle synthesis
     lg64 = [{"w": L["w"].astype(np.float64), "v": L["v"], "phase": L["phase_u32"].astype(np.float64) / 2**32}
             for L in g["lists"]]
