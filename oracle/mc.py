@@ -54,6 +54,7 @@ class _Params(ctypes.Structure):
         ("n_bins", ctypes.c_int), ("max_orders", ctypes.c_int), ("weighting", ctypes.c_int),
         ("pid_begin", ctypes.c_uint64), ("n_packets", ctypes.c_uint64),
         ("seed", ctypes.c_uint64), ("stream", ctypes.c_uint32), ("n_threads", ctypes.c_int),
+        ("peel", ctypes.c_int),
     ]
 
 
@@ -66,6 +67,9 @@ class _Out(ctypes.Structure):
         ("list_w", ctypes.POINTER(ctypes.c_double)), ("list_v", ctypes.POINTER(ctypes.c_double)),
         ("list_phase", ctypes.POINTER(ctypes.c_double)), ("list_pid", ctypes.POINTER(ctypes.c_uint64)),
         ("list_err32", ctypes.POINTER(ctypes.c_double)),
+        ("P", ctypes.POINTER(ctypes.c_double)), ("P2", ctypes.POINTER(ctypes.c_double)),
+        ("P_single", ctypes.POINTER(ctypes.c_double)), ("P_surface", ctypes.POINTER(ctypes.c_double)),
+        ("peel_sinks", ctypes.c_double * 2),
     ]
 
 
@@ -92,6 +96,10 @@ def lib():
         _lib.oracle_sample_scatter_ar.argtypes = [ctypes.POINTER(_Params), ctypes.c_uint64,
                                                   ctypes.POINTER(ctypes.c_double)]
         _lib.oracle_sample_scatter_ar.restype = ctypes.c_int
+        _lib.oracle_peel_draws.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_uint64, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double)]
+        _lib.oracle_peel_draws.restype = ctypes.c_int
     return _lib
 
 
@@ -167,9 +175,12 @@ def _params(p: dict, tabs: dict, n_threads: int, pid_begin: int, n_packets):
 
 
 def run(p: dict, n_threads: int | None = None, pid_begin: int = 0, n_packets: int | None = None,
-        class_tallies: bool = False, list_capacity: int = 0, tabs: dict | None = None) -> dict:
+        class_tallies: bool = False, list_capacity: int = 0, tabs: dict | None = None,
+        peel: bool = False) -> dict:
     """Run the FP64 oracle on parameter dict ``p``; returns tallies in
-    weight units (sums of packet weights)."""
+    weight units (sums of packet weights).  With ``peel`` also the
+    next-event estimate of the detector tally (P, P2, peel_sinks; with
+    class tallies P_single, P_surface)."""
     if tabs is None:
         tabs = set_tables(p)
     if n_threads is None:
@@ -194,6 +205,14 @@ def run(p: dict, n_threads: int | None = None, pid_begin: int = 0, n_packets: in
         out.list_w, out.list_v, out.list_phase = _dptr(lw), _dptr(lv), _dptr(lph)
         out.list_pid = lpid.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
         out.list_err32 = _dptr(lerr)
+    P = P2 = Ps = Psf = None
+    if peel:
+        cp.peel = 1
+        P, P2 = np.zeros(nb), np.zeros(nb)
+        out.P, out.P2 = _dptr(P), _dptr(P2)
+        if class_tallies:
+            Ps, Psf = np.zeros(nb), np.zeros(nb)
+            out.P_single, out.P_surface = _dptr(Ps), _dptr(Psf)
     rc = lib().oracle_run(ctypes.byref(cp), ctypes.byref(out))
     if rc != 0:
         raise ValueError("oracle_run rejected the parameters")
@@ -206,6 +225,11 @@ def run(p: dict, n_threads: int | None = None, pid_begin: int = 0, n_packets: in
     res["sinks"]["detected"] = float(W.sum())
     if class_tallies:
         res["W_single"], res["W_surface"] = Ws, Wsf
+    if peel:
+        res["P"], res["P2"] = P, P2
+        res["peel_sinks"] = {"under": float(out.peel_sinks[0]), "over": float(out.peel_sinks[1])}
+        if class_tallies:
+            res["P_single"], res["P_surface"] = Ps, Psf
     if list_capacity:
         n = min(int(out.list_count), list_capacity)
         # err32: first-order bound on an FP32 evaluation's deviation of v
@@ -311,3 +335,31 @@ def scatter_direction(mu_in: float, n: int, hg_g: float | None = None, cdf=None,
     if lib().oracle_scatter_direction(ctypes.byref(cp), float(mu_in), int(n), _dptr(out)) != 0:
         raise ValueError("bad direction arguments")
     return out
+
+
+def peel_draws(mu_in: float, T: float, n: int, hg_g: float | None = None, cdf=None, cone_half_angle: float = 0.1,
+               surface: bool = False, surface_law: int = 0, tau_total: float = 0.0, seed: int = 7, stream: int = 0):
+    """n next-event draws after one particle scattering (or, with
+    ``surface``, one reflection at depth tau_total) of a photon with cosine
+    mu_in at depth T: (weights, new cosines)."""
+    cp = _Params()
+    keep = None
+    if cdf is not None:
+        keep = np.ascontiguousarray(cdf, dtype=np.uint64)
+        cp.phase_kind = 1
+        cp.n_angles = len(keep)
+        cp.cdf = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+    else:
+        cp.phase_kind = 0
+        cp.hg_g = float(hg_g if hg_g is not None else 0.0)
+    cp.cos_cone = math.cos(float(cone_half_angle))
+    cp.surface_law = int(surface_law)
+    cp.tau_total = float(tau_total)
+    cp.seed = int(seed)
+    cp.stream = int(stream)
+    w = np.zeros(int(n))
+    mu = np.zeros(int(n))
+    if lib().oracle_peel_draws(ctypes.byref(cp), 1 if surface else 0, float(mu_in), float(T), int(n), _dptr(w),
+                               _dptr(mu)) != 0:
+        raise ValueError("bad next-event arguments")
+    return w, mu

@@ -115,6 +115,8 @@ typedef struct {
     uint64_t seed;
     uint32_t stream;
     int n_threads;
+    /* 1: also score the next-event (peel-off) estimate of the cone tally */
+    int peel;
 } oracle_params;
 
 typedef struct {
@@ -134,6 +136,17 @@ typedef struct {
     /* nullable: first-order bound on how far an FP32 evaluation of the same
      * path (same branch decisions) can move the apparent velocity */
     double* list_err32;
+    /* next-event estimate (peel != 0): per bin the sum of the expected
+     * direct-exit weights scored at every scattering and reflection, and the
+     * sum of their squares; nullable class arrays for scores at a packet's
+     * first particle scattering (no surface hit before) and at its first
+     * surface hit (no particle scattering before); scores outside the bin
+     * range (under, over) */
+    double* P;
+    double* P2;
+    double* P_single;
+    double* P_surface;
+    double peel_sinks[2];
 } oracle_out;
 
 void oracle_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
@@ -146,6 +159,8 @@ namespace {
 
 struct Tally {
     std::vector<double> W, W2, Ws, Wsurf;
+    std::vector<double> P, P2, Ps, Psurf;   // next-event estimate (empty if off)
+    double peel_sinks[2] = {0};
     double sinks[N_SINKS] = {0};
     uint64_t counts[N_COUNTS] = {0};
     bool keep_list = false;
@@ -285,6 +300,168 @@ double scattered_mu(const oracle_params& p, double mu, uint32_t x1, double u1, d
     return mu_new;
 }
 
+// ---------------------------------------------------------------------------
+// Next-event (peel-off) estimate of the detector tally.
+//
+// The detector of eq. 19 counts photons that leave the top inside the cone
+// mu >= cos(alpha).  A photon leaving a scattering or reflection at depth T
+// with direction cosine mu' > 0 escapes without further interaction with
+// probability exp(-T/mu') (Beer-Lambert, eq. 7), so the expected detected
+// weight of that event's outgoing flight is
+//     w a E[ 1(mu' >= cos alpha) exp(-T/mu') ],
+// a the albedo of the event, the expectation over the new direction (the
+// phase function with a uniform azimuth, eq. 13-16, or the surface law).
+// Summed over all events of all packets this has the expectation of the
+// detector tally, because every detected photon left its last event that
+// way.  Its apparent velocity is the path's value after the event, eq. 4.
+//
+// The expectation is estimated with one draw restricted to the directions
+// that can reach the cone, each with its probability as weight:
+//   surface, uniform polar angle: psi uniform on [0, alpha], weight
+//     alpha / (pi/2);
+//   surface, Lambert: u = mu'^2 uniform on [cos^2 alpha, 1], weight
+//     sin^2 alpha;
+//   particle: the cone lies within alpha of the vertical, so the scattering
+//     angle Theta (measured from the incoming direction, at angle
+//     Theta_0 = acos(mu) from the vertical) lies in
+//     [max(0, Theta_0 - alpha), min(pi, Theta_0 + alpha)].  Theta is drawn
+//     from the phase function restricted to that range (weight: its
+//     probability M), then the azimuth from the arc where the new direction
+//     is inside the cone: mu' = mu cos Theta + sqrt(1-mu^2) sin Theta cos phi
+//     >= cos alpha  <=>  |phi| <= phi_c, phi_c = acos(kappa),
+//     kappa = (cos alpha - mu cos Theta) / (sqrt(1-mu^2) sin Theta)
+//     (weight phi_c / pi).
+// Every weight lies in [0, 1], so the variance stays bounded.  The draw uses
+// its own Philox block, counter word 0 = event index with the top bit set,
+// so the analog or implicit transport is untouched.
+// ---------------------------------------------------------------------------
+
+// Henyey-Greenstein P(cos Theta <= x), written without cancellation:
+// (1-g)(1+x) / (r (1 + g + r)), r = sqrt(1 + g^2 - 2 g x).  Equals the
+// inverse of hg_angle's map from u to cos Theta.
+double hg_cdf(double g, double x) {
+    const double D = 1.0 + g * g - 2.0 * g * x;
+    const double r = std::sqrt(D > 0.0 ? D : 0.0);
+    const double den = r * (1.0 + g + r);
+    return den > 0.0 ? (1.0 - g) * (1.0 + x) / den : 1.0;
+}
+
+// Table law: probability that the angle lies below theta (the CDF of the
+// uniform-in-cell law, in units of 2^32).
+double table_cdf32(const oracle_params& p, double theta) {
+    const int n_cells = p.n_angles - 1;
+    const double x = theta / (PI / (double)n_cells);
+    if (x <= 0.0) return 0.0;
+    if (x >= (double)n_cells) return 4294967296.0;
+    int j = (int)std::floor(x);
+    if (j > n_cells - 1) j = n_cells - 1;
+    return (double)p.cdf[j] + (x - (double)j) * (double)(p.cdf[j + 1] - p.cdf[j]);
+}
+
+// Angle of the table law at CDF value y (units of 2^32): inside the cell
+// holding y the angle is linear in y.
+double table_theta_at(const oracle_params& p, double y) {
+    int lo = 0, hi = p.n_angles - 2;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) / 2;
+        if ((double)p.cdf[mid] <= y) lo = mid; else hi = mid - 1;
+    }
+    const double width = (double)(p.cdf[lo + 1] - p.cdf[lo]);
+    const double f = width > 0.0 ? (y - (double)p.cdf[lo]) / width : 0.0;
+    return ((double)lo + f) * (PI / (double)(p.n_angles - 1));
+}
+
+// One restricted draw after a particle scattering of a photon with direction
+// cosine mu at depth T; returns the weight (probability times attenuation)
+// and the new cosine.
+double peel_particle(const oracle_params& p, double mu, double T, double ur, double uphi, double* mu_out) {
+    const double cos_a = p.cos_cone;
+    const double alpha = std::acos(cos_a);
+    const double theta0 = std::acos(mu);
+    const double th_lo = std::fmax(0.0, theta0 - alpha), th_hi = std::fmin(PI, theta0 + alpha);
+    double cth, sth, M;
+    if (p.phase_kind == PHASE_TABLE) {
+        const double y_lo = table_cdf32(p, th_lo), y_hi = table_cdf32(p, th_hi);
+        M = (y_hi - y_lo) / 4294967296.0;
+        const double th = table_theta_at(p, y_lo + (y_hi - y_lo) * ur);
+        cth = std::cos(th);
+        sth = std::sin(th);
+    } else {
+        const double g = p.hg_g;
+        const double u_lo = hg_cdf(g, std::cos(th_hi)), u_hi = hg_cdf(g, std::cos(th_lo));
+        M = u_hi - u_lo;
+        hg_angle(g, u_lo + (u_hi - u_lo) * ur, &cth, &sth);
+    }
+    const double sm = std::sqrt(std::fmax(0.0, (1.0 - mu) * (1.0 + mu)));
+    const double den = sm * sth;
+    double phi_c;
+    if (den <= 1e-300) {
+        phi_c = PI;                       // every azimuth gives mu' = mu cos Theta
+    } else {
+        const double kappa = (cos_a - mu * cth) / den;
+        phi_c = kappa <= -1.0 ? PI : (kappa >= 1.0 ? 0.0 : std::acos(kappa));
+    }
+    double mu_new = mu * cth + den * std::cos(phi_c * uphi);
+    if (mu_new > 1.0) mu_new = 1.0;
+    *mu_out = mu_new;
+    if (!(M > 0.0) || phi_c <= 0.0 || mu_new <= 0.0) return 0.0;
+    return M * (phi_c / PI) * std::exp(-T / mu_new);
+}
+
+// One restricted draw after a surface reflection (depth tau_total); returns
+// the weight and the new cosine with its complement 1 - mu'.
+double peel_surface(const oracle_params& p, double ur, double* mu_out, double* omc_out) {
+    const double cos_a = p.cos_cone;
+    double mu_new, omc, M;
+    if (p.surface_law == SURFACE_LAMBERT) {
+        const double s2 = (1.0 - cos_a) * (1.0 + cos_a);       // sin^2 alpha
+        const double u = 1.0 - s2 * (1.0 - ur);
+        mu_new = std::sqrt(u);
+        omc = s2 * (1.0 - ur) / (1.0 + mu_new);
+        M = s2;
+    } else {
+        const double alpha = std::acos(cos_a);
+        const double psi = alpha * ur;
+        const double sh = std::sin(0.5 * psi);
+        mu_new = std::cos(psi);
+        omc = 2.0 * sh * sh;
+        M = alpha / (0.5 * PI);
+    }
+    *mu_out = mu_new;
+    *omc_out = omc;
+    if (mu_new <= 0.0) return 0.0;
+    return M * std::exp(-p.tau_total / mu_new);
+}
+
+// Score a next-event estimate c at apparent velocity v (first_kind: 1 for a
+// packet's first particle scattering with no surface hit before, 2 for its
+// first surface hit with no scattering before, 0 otherwise).
+void score_peel(const oracle_params& p, double c, double v, int first_kind, Tally& t) {
+    const double dv = (p.v_hi - p.v_lo) / (double)p.n_bins;
+    const double b = std::floor((v - p.v_lo) / dv);
+    if (b < 0.0) {
+        t.peel_sinks[0] += c;
+    } else if (b >= (double)p.n_bins) {
+        t.peel_sinks[1] += c;
+    } else {
+        const int ib = (int)b;
+        t.P[ib] += c;
+        t.P2[ib] += c * c;
+        if (first_kind == 1 && !t.Ps.empty()) t.Ps[ib] += c;
+        if (first_kind == 2 && !t.Psurf.empty()) t.Psurf[ib] += c;
+    }
+}
+
+// The two uniforms of event k's next-event draw.
+void peel_uniforms(const oracle_params& p, uint32_t k, uint32_t pid_lo, uint32_t pid_hi, double* ur, double* uphi) {
+    const uint32_t key[2] = {(uint32_t)(p.seed & 0xffffffffu), (uint32_t)(p.seed >> 32)};
+    const uint32_t ctr[4] = {k | 0x80000000u, pid_lo, pid_hi, p.stream};
+    uint32_t X[4];
+    philox4x32_10(ctr, key, X);
+    *ur = uniform_from_word(X[0]);
+    *uphi = uniform_from_word(X[1]);
+}
+
 void run_packet(const oracle_params& p, uint64_t pid, Tally& t) {
     const uint32_t key[2] = {(uint32_t)(p.seed & 0xffffffffu), (uint32_t)(p.seed >> 32)};
     const uint32_t pid_lo = (uint32_t)(pid & 0xffffffffu), pid_hi = (uint32_t)(pid >> 32);
@@ -325,6 +502,13 @@ void run_packet(const oracle_params& p, uint64_t pid, Tally& t) {
                 double sh = std::sin(0.5 * psi);
                 mu_new = std::cos(psi);
                 one_minus_mu_new = 2.0 * sh * sh;
+            }
+            if (p.peel) {
+                double ur, uphi, mp, omc_p;
+                peel_uniforms(p, k, pid_lo, pid_hi, &ur, &uphi);
+                const double c = w * p.surface_albedo * peel_surface(p, ur, &mp, &omc_p);
+                const double v = (big + 0.5 * p.v_surface * (1.0 - mu)) - (small + 0.5 * p.v_surface * omc_p);
+                score_peel(p, c, v, (n_sc == 0 && n_surf == 0) ? 2 : 0, t);
             }
             if (p.weighting == WEIGHT_ANALOG) {
                 if (!surface_one && X[3] >= thr_surface) {
@@ -393,6 +577,13 @@ void run_packet(const oracle_params& p, uint64_t pid, Tally& t) {
             t.sinks[SINK_TRUNCATED] += w;
             return;
         }
+        if (p.peel) {
+            double ur, uphi, mp;
+            peel_uniforms(p, k, pid_lo, pid_hi, &ur, &uphi);
+            const double c = w * p.albedo * peel_particle(p, mu, Tn, ur, uphi, &mp);
+            const double v = (big + 0.5 * V * (1.0 - mu)) - (small + 0.5 * V * (1.0 - mp));
+            score_peel(p, c, v, (n_sc == 0 && n_surf == 0) ? 1 : 0, t);
+        }
         if (p.weighting == WEIGHT_ANALOG) {
             if (!albedo_one && X[3] >= thr_albedo) {
                 t.sinks[SINK_ABSORBED_PARTICLE] += w;
@@ -451,6 +642,7 @@ extern "C" {
 int oracle_run(const oracle_params* p, oracle_out* out) {
     if (!p || !out || p->n_bins < 1 || p->n_layers < 1 || !p->T || !out->W || !out->W2) return -1;
     if (p->phase_kind == PHASE_TABLE && (!p->cdf || p->n_angles < 2)) return -1;
+    if (p->peel && (!out->P || !out->P2)) return -1;
     int nt = p->n_threads > 0 ? p->n_threads : 1;
     if ((uint64_t)nt > p->n_packets && p->n_packets > 0) nt = (int)p->n_packets;
     if (nt < 1) nt = 1;
@@ -461,6 +653,12 @@ int oracle_run(const oracle_params* p, oracle_out* out) {
         if (out->W_single) t.Ws.assign(p->n_bins, 0.0);
         if (out->W_surface) t.Wsurf.assign(p->n_bins, 0.0);
         t.keep_list = out->list_capacity > 0;
+        if (p->peel) {
+            t.P.assign(p->n_bins, 0.0);
+            t.P2.assign(p->n_bins, 0.0);
+            if (out->P_single) t.Ps.assign(p->n_bins, 0.0);
+            if (out->P_surface) t.Psurf.assign(p->n_bins, 0.0);
+        }
     }
     std::vector<std::thread> threads;
     for (int i = 0; i < nt; ++i) {
@@ -477,6 +675,15 @@ int oracle_run(const oracle_params* p, oracle_out* out) {
     }
     for (int s = 0; s < N_SINKS; ++s) out->sinks[s] = 0.0;
     for (int c = 0; c < N_COUNTS; ++c) out->counts[c] = 0;
+    if (p->peel) {
+        for (int b = 0; b < p->n_bins; ++b) {
+            out->P[b] = 0.0;
+            out->P2[b] = 0.0;
+            if (out->P_single) out->P_single[b] = 0.0;
+            if (out->P_surface) out->P_surface[b] = 0.0;
+        }
+        out->peel_sinks[0] = out->peel_sinks[1] = 0.0;
+    }
     uint64_t n_list = 0;
     for (int i = 0; i < nt; ++i) {
         const Tally& t = tallies[i];
@@ -485,6 +692,16 @@ int oracle_run(const oracle_params* p, oracle_out* out) {
             out->W2[b] += t.W2[b];
             if (out->W_single) out->W_single[b] += t.Ws[b];
             if (out->W_surface) out->W_surface[b] += t.Wsurf[b];
+        }
+        if (p->peel) {
+            for (int b = 0; b < p->n_bins; ++b) {
+                out->P[b] += t.P[b];
+                out->P2[b] += t.P2[b];
+                if (out->P_single) out->P_single[b] += t.Ps[b];
+                if (out->P_surface) out->P_surface[b] += t.Psurf[b];
+            }
+            out->peel_sinks[0] += t.peel_sinks[0];
+            out->peel_sinks[1] += t.peel_sinks[1];
         }
         for (int s = 0; s < N_SINKS; ++s) out->sinks[s] += t.sinks[s];
         for (int c = 0; c < N_COUNTS; ++c) out->counts[c] += t.counts[c];
@@ -540,6 +757,35 @@ int oracle_scatter_direction(const oracle_params* p, double mu_in, uint64_t n, d
         uint32_t X[4];
         philox4x32_10(ctr, key, X);
         mu_out[i] = scattered_mu(*p, mu_in, X[1], uniform_from_word(X[1]), uniform_from_word(X[2]));
+    }
+    return 0;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+// Test hook: n next-event draws after a particle scattering (surface != 0:
+// a surface reflection) of a photon with direction cosine mu_in at depth T;
+// draw i uses the Philox block with counter (i, 2, 0, stream).  w_out[i]
+// receives the draw's weight (probability times attenuation, before the
+// albedo), mu_out[i] its new cosine.
+int oracle_peel_draws(const oracle_params* p, int surface, double mu_in, double T, uint64_t n, double* w_out,
+                      double* mu_out) {
+    if (!p || !w_out || !mu_out || mu_in < -1.0 || mu_in > 1.0) return -1;
+    if (p->phase_kind == PHASE_TABLE && (!p->cdf || p->n_angles < 2)) return -1;
+    const uint32_t key[2] = {(uint32_t)(p->seed & 0xffffffffu), (uint32_t)(p->seed >> 32)};
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint32_t ctr[4] = {(uint32_t)i, 2u, (uint32_t)(i >> 32), p->stream};
+        uint32_t X[4];
+        philox4x32_10(ctr, key, X);
+        const double ur = uniform_from_word(X[0]), uphi = uniform_from_word(X[1]);
+        if (surface) {
+            double omc;
+            w_out[i] = peel_surface(*p, ur, &mu_out[i], &omc);
+        } else {
+            w_out[i] = peel_particle(*p, mu_in, T, ur, uphi, &mu_out[i]);
+        }
     }
     return 0;
 }

@@ -76,17 +76,35 @@ def angle_grid(n_angles: int) -> np.ndarray:
     return np.arange(n_angles, dtype=np.float64) * math.pi / (n_angles - 1)
 
 
+_NODE_CACHE: dict = {}
+
+
+def _node_optics(m: complex, wavelength: float, d: np.ndarray, n_angles: int):
+    """Efficiencies and angular intensity |S1|^2+|S2|^2 of each size node.
+    They depend on the optics and the nodes only (not on the size law's
+    median or width), so sets that share them reuse one evaluation."""
+    key = (complex(m), float(wavelength), d.tobytes(), int(n_angles))
+    hit = _NODE_CACHE.get(key)
+    if hit is not None:
+        return hit
+    x = math.pi * d / wavelength
+    q_ext, q_sca, g = mie.efficiencies(m, x)
+    theta = angle_grid(n_angles)
+    S1, S2 = mie.amplitudes(m, x, theta)
+    intensity = np.abs(S1) ** 2 + np.abs(S2) ** 2
+    if len(_NODE_CACHE) >= 8:
+        _NODE_CACHE.clear()
+    _NODE_CACHE[key] = (x, q_ext, q_sca, g, intensity)
+    return _NODE_CACHE[key]
+
+
 def mie_ensemble(m: complex, wavelength: float, diameters, weights, n_angles: int):
     """Size-averaged optics.  Returns dict with the unnormalised phase
     intensity <|S1|^2+|S2|^2>(theta_j), albedo, asymmetry g and mean
     efficiencies."""
     d = np.asarray(diameters, dtype=np.float64)
     q = np.asarray(weights, dtype=np.float64)
-    x = math.pi * d / wavelength
-    q_ext, q_sca, g = mie.efficiencies(m, x)
-    theta = angle_grid(n_angles)
-    S1, S2 = mie.amplitudes(m, x, theta)
-    intensity = np.abs(S1) ** 2 + np.abs(S2) ** 2
+    x, q_ext, q_sca, g, intensity = _node_optics(m, wavelength, d, n_angles)
     phase = q @ intensity
     c_sca = q * x * x * q_sca
     c_ext = q * x * x * q_ext
