@@ -69,12 +69,12 @@ enum { PDV_FP32 = 0, PDV_FP64 = 1 };
 /* Flags of pdv_params.flags */
 #define PDV_FLAG_CLASS_TALLIES 1u   /* also tally the single-scattering and surface-only classes */
 /* w_fx, w2_fx (and class_fx) of this set's pdv_spectrum_out are device
- * pointers on the context's device, allocated through the HIP runtime this
- * library links (a framework that bundles its own HIP runtime keeps its
- * allocations there, where this library cannot see them): the library
- * writes the bins there on its stream, device to device, and has finished
- * when the call returns; the scalar fields of pdv_spectrum_out stay host
- * memory.  Accepted by pdv_spectrum and pdv_spectrum_batch only
+ * pointers on the context's device (for example a torch tensor's data_ptr,
+ * with the library loaded into the HIP runtime PyTorch uses, as the Python
+ * binding does): the library writes the bins there on the context's stream
+ * (the caller's, when one was given to pdv_create), device to device, and
+ * has finished when the call returns; the scalar fields of pdv_spectrum_out
+ * stay host memory.  Accepted by pdv_spectrum and pdv_spectrum_batch only
  * (pdv_spectrogram and pdv_submit reject it); a pointer that is not device
  * memory of the context's device gives PDV_EINVAL before any work. */
 #define PDV_FLAG_DEVICE_OUTPUT 2u
@@ -315,7 +315,14 @@ int pdv_spectrogram(struct pdv_ctx* ctx, const pdv_params* p, const pdv_sg_param
  * the caller provides.  Frame k's entries are [offsets[k], offsets[k+1]) of
  * w (float), v (double, apparent velocity, m/s) and phase_u32 (phase in
  * units of 2^-32 cycles); its samples are [floor(k N/F), floor((k+1) N/F)).
- * signal: host [n_samples].
+ * offsets: host [n_frames + 1], offsets[0] = 0, non-decreasing; w, v,
+ * phase_u32: host [offsets[n_frames]], weights >= 0; signal: host
+ * [n_samples].  1 <= n_frames <= 65535, 1 <= n_samples.  The samples are FP32
+ * sums in a fixed order that depends only on the frames, the largest frame's
+ * entry count and n_samples (bitwise reproducible).  Device memory beyond the
+ * entries and the record is bounded (at most 16 MiB of partial records).
+ * Errors: PDV_EINVAL (bad sizes, offsets or weights), PDV_ESTATE (serving),
+ * PDV_ENOMEM, PDV_EDEVICE.
  */
 int pdv_beat_synthesize(struct pdv_ctx* ctx, int32_t n_frames, const uint64_t* offsets,
                         const float* w, const double* v, const uint32_t* phase_u32,

@@ -37,16 +37,16 @@ void launch_copy_desc_fields(hipStream_t s, SetDesc* descs, const int* src, int 
 int launch_kind_of(const pdv_params* sets, int n);
 hipError_t plan_transport(TransportShape& sh, int precision, bool list, int want_bits, int lds_per_block,
                           int lds_per_cu);
-hipError_t launch_synth(hipStream_t s, int n_frames, const void* frames, const ListEntry* entries, double r_scale,
-                        int n_chunks, int max_samples, float* partial, float* signal);
+SynthPlan synth_plan(int n_frames, int n_samples, uint64_t max_entries);
+hipError_t launch_synth(hipStream_t s, const SynthPlan& P, int n_frames, int n_samples, const uint64_t* fbeg,
+                        const uint64_t* fend, const ListEntry* rec, const float* w, const double* v,
+                        const uint32_t* phase, double r_scale, float* partial, float* signal);
 hipError_t launch_stft(hipStream_t s, const float* signal, int n_windows, int nfft, int hop, void* tw, void* tr,
                        float* win, float* map, bool build_tables);
-int synth_chunk();
 int peak_lds_bytes(int n, int keep);
 hipError_t launch_ejecta(hipStream_t s, int n_nodes, const void* info, const EjectaJob& J, double* out);
 hipError_t launch_peak(hipStream_t s, int n_spectra, const double* spectra, int n, int keep, const PeakJob& J,
                        double* smoothed, PeakOut* out);
-size_t synth_frame_bytes();
 hipError_t launch_transport(hipStream_t s, int precision, bool list, const TransportShape& sh,
                             const SetDesc* descs, const uint8_t* tables, uint64_t* tallies, const WorkItem* items,
                             int n_items, const int* n_items_dev, uint32_t* queue, int persistent, ListEntry* lists,
@@ -878,45 +878,30 @@ extern "C" int pdv_last_launch(const pdv_ctx* ctx, float* kernel_ms, int32_t* gr
 // ---------------------------------------------------------------------------
 // Stage 2: beat synthesis and spectrogram
 // ---------------------------------------------------------------------------
-namespace {
-struct SynthFrameH {          // mirrors SynthFrame in stage2.hip
-    uint64_t entry_begin;
-    uint32_t n_entries;
-    int32_t s_begin, s_count, pad;
-};
-}  // namespace
-
 // Entries already on the device (in `lists` when entries == nullptr, else in
-// sg_entries); writes the record into sg_signal.
+// sg_entries); frame k's entries start at entry_begin[k], n_entries[k] of
+// them.  Writes the record into sg_signal.
 int pdv_ctx::synthesize(int n_frames, const uint64_t* entry_begin, const uint64_t* n_entries,
                         const ListEntry_* entries, double wavelength, double fs, int n_samples) {
-    if (synth_frame_bytes() != sizeof(SynthFrameH)) return fail(PDV_EDEVICE, "synth frame layout mismatch");
-    std::vector<SynthFrameH> fr(n_frames);
+    std::vector<uint64_t> fb(2 * (size_t)n_frames);
     uint64_t max_entries = 0;
-    int max_samples = 1;
     for (int k = 0; k < n_frames; ++k) {
-        const int64_t b0 = (int64_t)k * n_samples / n_frames, b1 = (int64_t)(k + 1) * n_samples / n_frames;
-        fr[k].entry_begin = entry_begin[k];
-        fr[k].n_entries = (uint32_t)n_entries[k];
-        fr[k].s_begin = (int32_t)b0;
-        fr[k].s_count = (int32_t)(b1 - b0);
-        fr[k].pad = 0;
+        fb[k] = entry_begin[k];
+        fb[n_frames + k] = entry_begin[k] + n_entries[k];
         max_entries = std::max<uint64_t>(max_entries, n_entries[k]);
-        max_samples = std::max(max_samples, (int)(b1 - b0));
     }
-    const int chunk = synth_chunk();
-    const int n_chunks = (int)((max_entries + chunk - 1) / chunk);
+    const SynthPlan P = synth_plan(n_frames, n_samples, max_entries);
     int r;
-    if ((r = ensure(sg_frames, sizeof(SynthFrameH) * n_frames, "synthesis frames"))) return r;
-    if ((r = ensure(sg_partial, 4ull * std::max(1, n_chunks) * n_frames * max_samples, "synthesis partials")))
-        return r;
+    if ((r = ensure(sg_frames, 16ull * n_frames, "synthesis frames"))) return r;
+    if ((r = ensure(sg_partial, 4ull * std::max<uint64_t>(1, P.partial_floats), "synthesis partials"))) return r;
     if ((r = ensure(sg_signal, 4ull * std::max(1, n_samples), "beat signal"))) return r;
-    if ((r = hip_check(hipMemcpyAsync(sg_frames.ptr, fr.data(), sizeof(SynthFrameH) * n_frames,
-                                      hipMemcpyHostToDevice, stream), "copy frames")))
+    if ((r = hip_check(hipMemcpyAsync(sg_frames.ptr, fb.data(), 16ull * n_frames, hipMemcpyHostToDevice, stream),
+                       "copy frames")))
         return r;
     const ListEntry* src = entries ? entries : (const ListEntry*)lists.ptr;
-    hipError_t e = launch_synth(stream, n_frames, sg_frames.ptr, src, 2.0 / (wavelength * fs), n_chunks,
-                                max_samples, (float*)sg_partial.ptr, (float*)sg_signal.ptr);
+    const uint64_t* d_fb = (const uint64_t*)sg_frames.ptr;
+    hipError_t e = launch_synth(stream, P, n_frames, n_samples, d_fb, d_fb + n_frames, src, nullptr, nullptr, nullptr,
+                                2.0 / (wavelength * fs), (float*)sg_partial.ptr, (float*)sg_signal.ptr);
     return hip_check(e, "beat synthesis kernels");
 }
 
@@ -1059,7 +1044,8 @@ extern "C" int pdv_beat_synthesize(pdv_ctx* ctx, int32_t n_frames, const uint64_
     if (!ctx) return PDV_EINVAL;
     if (ctx->serve) return ctx->fail(PDV_ESTATE, "context is serving: submit requests instead");
     if (ctx->poisoned) return ctx->fail(PDV_EDEVICE, "context poisoned by an earlier device error");
-    if (n_frames < 1 || !offsets || !signal) return ctx->fail(PDV_EINVAL, "need n_frames >= 1, offsets, signal");
+    if (n_frames < 1 || n_frames > SYNTH_MAX_FRAMES || !offsets || !signal)
+        return ctx->fail(PDV_EINVAL, "need n_frames in [1, 65535], offsets, signal");
     if (!(wavelength > 0.0) || !(fs > 0.0) || n_samples < 1) return ctx->fail(PDV_EINVAL, "bad wavelength/fs/n_samples");
     const uint64_t total = offsets[n_frames];
     for (int k = 0; k < n_frames; ++k)

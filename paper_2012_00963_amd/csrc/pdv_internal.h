@@ -118,6 +118,21 @@ struct alignas(16) ListEntry {
 
 enum SetFlags : uint32_t { SF_CLASS = 1u, SF_LIST = 2u };
 
+// Beat synthesis work split: blocks take (sample tile, frame, group of
+// entry chunks); the entries of a frame are split into groups only while
+// the grid stays below SYNTH_TARGET_BLOCKS and the groups' partial records
+// fit SYNTH_PARTIAL_MAX_FLOATS, so the partials never exceed 16 MiB.
+constexpr uint64_t SYNTH_TARGET_BLOCKS = 8192;
+constexpr uint64_t SYNTH_PARTIAL_MAX_FLOATS = 1ull << 22;
+constexpr int SYNTH_MAX_FRAMES = 65535;
+struct SynthPlan {
+    int max_samples;           // samples of the longest frame, ceil(N / F)
+    int tiles;                 // sample tiles of the longest frame
+    int n_groups;              // entry-chunk groups per frame (1: no partial records)
+    int cpg;                   // chunks per group (the last group takes the rest)
+    uint64_t partial_floats;   // partial-record floats the split needs
+};
+
 // Set kinds.  A launch whose sets all share one of the specialised kinds
 // runs a transport kernel with the kind's tests resolved at compile time
 // (fewer branches and scalar registers); any other launch runs the generic

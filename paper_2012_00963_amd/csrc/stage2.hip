@@ -11,125 +11,169 @@
 // (Sec. I, Fig. 1): periodic Hann window of nfft samples every hop samples.
 //
 // Kernels:
-//   synth_partial   one block per (frame, chunk of list entries): entries are
-//                   staged in LDS and every thread accumulates a run of
-//                   consecutive samples; at the run's first sample the phase
+//   synth_tile      one block per (sample tile, frame, group of entry chunks):
+//                   the group's entries are staged in LDS a chunk at a time
+//                   and every thread accumulates a run of consecutive samples
+//                   of the tile; at the run's first sample the phase
 //                   f n / fs + phi0 is formed with an FP64 fused multiply-add
 //                   and reduced to [0,1) in FP64 (records reach tens of
 //                   thousands of cycles), its cosine and sine taken in FP32
 //                   on the revolution-argument hardware unit; each further
 //                   sample of the run rotates that pair by the entry's phase
 //                   step per sample (cos and sin of 2 pi frac(f / fs), formed
-//                   in FP64 when the entry is staged);
-//   synth_reduce    sums the per-chunk partials in fixed order (deterministic);
+//                   in FP64 when the entry is staged).  With one group the
+//                   block writes the record itself; otherwise each group
+//                   writes a partial record;
+//   synth_reduce    sums the groups' partial records in group order
+//                   (deterministic);
 //   stft_kernel     one block per window: real FFT of nfft points through an
 //                   nfft/2-point complex Stockham FFT in LDS (radix 4, one
 //                   radix-2 stage when needed) and the split step, then |X|.
+#include <algorithm>
+
 #include "pdv_device.h"
 #include "pdv_internal.h"
 
 namespace pdv {
 
-struct SynthFrame {
-    uint64_t entry_begin;    // first entry of the frame in the entry array
-    uint32_t n_entries;      // entries kept for the frame
-    int32_t s_begin;         // first sample owned by the frame
-    int32_t s_count;         // samples owned by the frame
-    int32_t pad;
+
+constexpr int SYNTH_CHUNK = 1024;       // entries staged in LDS at a time
+constexpr int SYNTH_THREADS = 128;
+constexpr int SYNTH_RUN = 4;            // consecutive samples per thread
+constexpr int SYNTH_TILE = SYNTH_RUN * SYNTH_THREADS;
+
+// Where the entries come from: an array of ListEntry records (lists written
+// by the transport, or packed from host arrays), or three separate arrays.
+struct EntrySrc {
+    const ListEntry* rec;
+    const float* w;
+    const double* v;
+    const uint32_t* phase;
 };
 
-constexpr int SYNTH_CHUNK = 1024;       // entries staged per block
-constexpr int SYNTH_THREADS = 128;
-constexpr int SYNTH_RUN = 4;            // consecutive samples per thread and pass
-
-// NQ consecutive samples per thread, starting at base + NQ x thread, over
-// the staged entries; a thread whose run starts past the frame's samples
-// has nothing to do.
-template <int NQ>
-__device__ __forceinline__ void synth_samples(const SynthFrame& F, int base, int ne, const double* s_r,
-                                              const double* s_ph, const float* s_a, const float2* s_rot,
-                                              float* out) {
-    const int j0 = base + (int)threadIdx.x * NQ;
-    if (j0 >= F.s_count) return;
-    const double n0 = (double)(F.s_begin + j0);
-    float acc[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) acc[q] = 0.f;
-    for (int i = 0; i < ne; ++i) {
-        // fractional cycles in one v_fract_f64 (x - floor(x), exact; its
-        // clamp below 1 only matters where the FP32 rounding gives 1 anyway)
-        const float cyc = (float)__builtin_amdgcn_fract(fma(s_r[i], n0, s_ph[i]));
-        const float a = s_a[i];
-        float c = __builtin_amdgcn_cosf(cyc);
-        acc[0] = fmaf(a, c, acc[0]);
-        if constexpr (NQ > 1) {
-            float sn = __builtin_amdgcn_sinf(cyc);
-            const float2 rot = s_rot[i];
-#pragma unroll
-            for (int q = 1; q < NQ; ++q) {
-                const float c2 = fmaf(c, rot.x, -sn * rot.y);
-                sn = fmaf(c, rot.y, sn * rot.x);
-                c = c2;
-                acc[q] = fmaf(a, c, acc[q]);
-            }
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        if (j0 + q < F.s_count) out[j0 + q] = acc[q];
+template <bool SOA>
+__device__ __forceinline__ void load_entry(const EntrySrc& src, uint64_t i, float& w, double& v, uint32_t& ph) {
+    if constexpr (SOA) {
+        w = src.w[i];
+        v = src.v[i];
+        ph = src.phase[i];
+    } else {
+        const ListEntry E = src.rec[i];
+        w = E.w;
+        v = E.v;
+        ph = E.phase;
     }
 }
 
-// Accumulate sqrt(w) cos(2 pi frac(r n + phi)) for the frame's samples over
-// one chunk of entries; r = 2 v / (lambda fs) cycles per sample.  A thread
-// takes a run of up to SYNTH_RUN consecutive samples per pass (sharing each
-// entry read and one exact phase); the run length is cut to what the frame's
-// remaining samples need.
+// The chunks [c0, c1) of frame entries starting at e_begin (n_entries in
+// all), accumulated over the NQ consecutive samples j0 .. j0 + NQ - 1 of the
+// frame (absolute sample index n0 for j0).  Every thread of the block takes
+// part in the staging; threads whose run starts past the frame's samples
+// only stage.
+template <int NQ, bool SOA>
+__device__ __forceinline__ void synth_tile(const EntrySrc& src, uint64_t e_begin, uint64_t n_entries, int c0, int c1,
+                                           double r_scale, double n0, bool active, float* acc, double* s_r,
+                                           double* s_ph, float* s_a, float2* s_rot) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.f;
+    for (int ch = c0; ch < c1; ++ch) {
+        const uint64_t e0 = (uint64_t)ch * SYNTH_CHUNK;
+        const int ne = (int)(n_entries - e0 < (uint64_t)SYNTH_CHUNK ? n_entries - e0 : (uint64_t)SYNTH_CHUNK);
+        __syncthreads();            // the previous chunk's entries are no longer read
+        for (int i = threadIdx.x; i < ne; i += blockDim.x) {
+            float w;
+            double v;
+            uint32_t ph;
+            load_entry<SOA>(src, e_begin + e0 + (uint64_t)i, w, v, ph);
+            const double r = v * r_scale;
+            s_r[i] = r;
+            double sn, cs;
+            sincospi(2.0 * (r - floor(r)), &sn, &cs);
+            s_rot[i] = make_float2((float)cs, (float)sn);
+            s_ph[i] = (double)ph * 2.3283064365386963e-10;   // 2^-32
+            s_a[i] = sqrtf(w);
+        }
+        __syncthreads();
+        if (!active) continue;
+        for (int i = 0; i < ne; ++i) {
+            // fractional cycles in one v_fract_f64 (x - floor(x), exact; its
+            // clamp below 1 only matters where the FP32 rounding gives 1 anyway)
+            const float cyc = (float)__builtin_amdgcn_fract(fma(s_r[i], n0, s_ph[i]));
+            const float a = s_a[i];
+            float c = __builtin_amdgcn_cosf(cyc);
+            acc[0] = fmaf(a, c, acc[0]);
+            if constexpr (NQ > 1) {
+                float sn = __builtin_amdgcn_sinf(cyc);
+                const float2 rot = s_rot[i];
+#pragma unroll
+                for (int q = 1; q < NQ; ++q) {
+                    const float c2 = fmaf(c, rot.x, -sn * rot.y);
+                    sn = fmaf(c, rot.y, sn * rot.x);
+                    c = c2;
+                    acc[q] = fmaf(a, c, acc[q]);
+                }
+            }
+        }
+    }
+}
+
+// Frame f owns samples [floor(f N / F), floor((f+1) N / F)) and the entries
+// [fbeg[f], fend[f]).  Block (tile, frame, group) accumulates the tile's
+// SYNTH_TILE samples over the group's entry chunks: group g takes chunks
+// [g cpg, (g+1) cpg), the last group every chunk from (G-1) cpg on.  A thread
+// takes a run of up to SYNTH_RUN consecutive samples, cut to what the tile's
+// remaining samples need.  With one group the block writes the record;
+// otherwise partial[(f G + g) max_samples + j] for the frame's sample j.
+template <bool SOA>
 __global__ void __launch_bounds__(SYNTH_THREADS)
-synth_partial_kernel(const SynthFrame* __restrict__ frames, const ListEntry* __restrict__ entries,
-                     double two_over_lambda_fs, int n_chunks, int max_samples, float* __restrict__ partial) {
+synth_tile_kernel(const uint64_t* __restrict__ fbeg, const uint64_t* __restrict__ fend, EntrySrc src,
+                  double r_scale, int n_frames, int n_samples, int n_groups, int cpg, int max_samples,
+                  float* __restrict__ partial, float* __restrict__ signal) {
     __shared__ double s_r[SYNTH_CHUNK];
     __shared__ double s_ph[SYNTH_CHUNK];
     __shared__ float s_a[SYNTH_CHUNK];
     __shared__ float2 s_rot[SYNTH_CHUNK];
-    const int f = blockIdx.x;
-    const int ch = blockIdx.y;
-    const SynthFrame F = frames[f];
-    const int e0 = ch * SYNTH_CHUNK;
-    int ne = (int)F.n_entries - e0;
-    ne = ne < 0 ? 0 : (ne > SYNTH_CHUNK ? SYNTH_CHUNK : ne);
-    for (int i = threadIdx.x; i < ne; i += blockDim.x) {
-        const ListEntry E = entries[F.entry_begin + (uint64_t)(e0 + i)];
-        const double r = E.v * two_over_lambda_fs;
-        s_r[i] = r;
-        double sn, cs;
-        sincospi(2.0 * (r - floor(r)), &sn, &cs);
-        s_rot[i] = make_float2((float)cs, (float)sn);
-        s_ph[i] = (double)E.phase * 2.3283064365386963e-10;   // 2^-32
-        s_a[i] = sqrtf(E.w);
-    }
-    __syncthreads();
-    float* out = partial + ((uint64_t)f * n_chunks + ch) * (uint64_t)max_samples;
-    for (int base = 0; base < F.s_count; base += SYNTH_RUN * SYNTH_THREADS) {
-        const int left = F.s_count - base;
-        const int nq = left >= SYNTH_RUN * SYNTH_THREADS ? SYNTH_RUN : (left + SYNTH_THREADS - 1) / SYNTH_THREADS;
-        if (nq == 4) synth_samples<4>(F, base, ne, s_r, s_ph, s_a, s_rot, out);
-        else if (nq == 3) synth_samples<3>(F, base, ne, s_r, s_ph, s_a, s_rot, out);
-        else if (nq == 2) synth_samples<2>(F, base, ne, s_r, s_ph, s_a, s_rot, out);
-        else synth_samples<1>(F, base, ne, s_r, s_ph, s_a, s_rot, out);
-    }
+    const int f = blockIdx.y;
+    const int g = blockIdx.z;
+    const int64_t s_begin = (int64_t)f * n_samples / n_frames;
+    const int s_count = (int)((int64_t)(f + 1) * n_samples / n_frames - s_begin);
+    const int tile_base = blockIdx.x * SYNTH_TILE;
+    if (tile_base >= s_count) return;                      // uniform over the block
+    const uint64_t e_begin = fbeg[f];
+    const uint64_t e_end = fend[f];
+    const uint64_t n_entries = e_end > e_begin ? e_end - e_begin : 0;
+    const int used = (int)((n_entries + SYNTH_CHUNK - 1) / SYNTH_CHUNK);
+    int c0 = g * cpg;
+    int c1 = g == n_groups - 1 ? used : c0 + cpg;
+    c0 = c0 < used ? c0 : used;
+    c1 = c1 < used ? c1 : used;
+    const int left = s_count - tile_base;
+    const int nq = left >= SYNTH_TILE ? SYNTH_RUN : (left + SYNTH_THREADS - 1) / SYNTH_THREADS;
+    const int j0 = tile_base + (int)threadIdx.x * nq;
+    const bool active = j0 < s_count;
+    const double n0 = (double)(s_begin + j0);
+    float acc[SYNTH_RUN];
+    if (nq == 4) synth_tile<4, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, acc, s_r, s_ph, s_a, s_rot);
+    else if (nq == 3) synth_tile<3, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, acc, s_r, s_ph, s_a, s_rot);
+    else if (nq == 2) synth_tile<2, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, acc, s_r, s_ph, s_a, s_rot);
+    else synth_tile<1, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, acc, s_r, s_ph, s_a, s_rot);
+    if (!active) return;
+    float* out = n_groups == 1 ? signal + s_begin : partial + ((uint64_t)f * n_groups + g) * (uint64_t)max_samples;
+    for (int q = 0; q < nq; ++q)
+        if (j0 + q < s_count) out[j0 + q] = acc[q];
 }
 
-__global__ void synth_reduce_kernel(const SynthFrame* __restrict__ frames, int n_chunks, int max_samples,
+__global__ void synth_reduce_kernel(int n_frames, int n_samples, int n_groups, int max_samples,
                                     const float* __restrict__ partial, float* __restrict__ signal) {
-    const int f = blockIdx.x;
-    const SynthFrame F = frames[f];
-    const int used = F.n_entries == 0 ? 0 : (int)((F.n_entries + SYNTH_CHUNK - 1) / SYNTH_CHUNK);
-    for (int j = threadIdx.x; j < F.s_count; j += blockDim.x) {
-        float s = 0.f;
-        for (int c = 0; c < used; ++c) s += partial[((uint64_t)f * n_chunks + c) * (uint64_t)max_samples + j];
-        signal[F.s_begin + j] = s;
-    }
+    const int f = blockIdx.y;
+    const int64_t s_begin = (int64_t)f * n_samples / n_frames;
+    const int s_count = (int)((int64_t)(f + 1) * n_samples / n_frames - s_begin);
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= s_count) return;
+    const float* p = partial + (uint64_t)f * n_groups * (uint64_t)max_samples + j;
+    float s = 0.f;
+    for (int g = 0; g < n_groups; ++g) s += p[(uint64_t)g * max_samples];
+    signal[s_begin + j] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -239,15 +283,49 @@ stft_kernel(const float* __restrict__ signal, int nfft, int hop, const F2* __res
 }
 
 // ---- host launchers ----
-hipError_t launch_synth(hipStream_t s, int n_frames, const void* frames, const ListEntry* entries, double r_scale,
-                        int n_chunks, int max_samples, float* partial, float* signal) {
-    if (n_frames <= 0) return hipSuccess;
-    if (n_chunks > 0) {
-        hipLaunchKernelGGL(synth_partial_kernel, dim3(n_frames, n_chunks), dim3(SYNTH_THREADS), 0, s,
-                           (const SynthFrame*)frames, entries, r_scale, n_chunks, max_samples, partial);
+
+// Work split of a beat synthesis; the same for every entry point, so the
+// summation order (and the FP32 record) depends only on the frames, their
+// largest entry count and the record length.
+SynthPlan synth_plan(int n_frames, int n_samples, uint64_t max_entries) {
+    SynthPlan P;
+    P.max_samples = n_frames > 0 ? (int)(((int64_t)n_samples + n_frames - 1) / n_frames) : 0;
+    if (P.max_samples < 1) P.max_samples = 1;
+    P.tiles = (P.max_samples + SYNTH_TILE - 1) / SYNTH_TILE;
+    const uint64_t used = (max_entries + SYNTH_CHUNK - 1) / SYNTH_CHUNK;
+    P.n_groups = 1;
+    P.cpg = used > 0 ? (int)std::min<uint64_t>(used, 0x7fffffff) : 1;
+    if (used > 1 && n_frames > 0) {
+        const uint64_t base = (uint64_t)n_frames * (uint64_t)P.tiles;
+        uint64_t G = (SYNTH_TARGET_BLOCKS + base - 1) / base;
+        G = std::min<uint64_t>(G, used);
+        const uint64_t cap = SYNTH_PARTIAL_MAX_FLOATS / ((uint64_t)n_frames * (uint64_t)P.max_samples);
+        G = std::min<uint64_t>(G, cap);
+        if (G >= 2) {
+            const uint64_t cpg = (used + G - 1) / G;
+            P.cpg = (int)cpg;
+            P.n_groups = (int)((used + cpg - 1) / cpg);
+        }
     }
-    hipLaunchKernelGGL(synth_reduce_kernel, dim3(n_frames), dim3(256), 0, s, (const SynthFrame*)frames, n_chunks,
-                       max_samples, partial, signal);
+    P.partial_floats = P.n_groups > 1 ? (uint64_t)n_frames * (uint64_t)P.n_groups * (uint64_t)P.max_samples : 0;
+    return P;
+}
+
+hipError_t launch_synth(hipStream_t s, const SynthPlan& P, int n_frames, int n_samples, const uint64_t* fbeg,
+                        const uint64_t* fend, const ListEntry* rec, const float* w, const double* v,
+                        const uint32_t* phase, double r_scale, float* partial, float* signal) {
+    if (n_frames <= 0 || n_samples <= 0) return hipSuccess;
+    const EntrySrc src{rec, w, v, phase};
+    const dim3 grid((unsigned)P.tiles, (unsigned)n_frames, (unsigned)P.n_groups);
+    if (rec)
+        hipLaunchKernelGGL(synth_tile_kernel<false>, grid, dim3(SYNTH_THREADS), 0, s, fbeg, fend, src, r_scale,
+                           n_frames, n_samples, P.n_groups, P.cpg, P.max_samples, partial, signal);
+    else
+        hipLaunchKernelGGL(synth_tile_kernel<true>, grid, dim3(SYNTH_THREADS), 0, s, fbeg, fend, src, r_scale,
+                           n_frames, n_samples, P.n_groups, P.cpg, P.max_samples, partial, signal);
+    if (P.n_groups > 1)
+        hipLaunchKernelGGL(synth_reduce_kernel, dim3((unsigned)((P.max_samples + 255) / 256), (unsigned)n_frames),
+                           dim3(256), 0, s, n_frames, n_samples, P.n_groups, P.max_samples, partial, signal);
     return hipGetLastError();
 }
 
@@ -265,7 +343,5 @@ hipError_t launch_stft(hipStream_t s, const float* signal, int n_windows, int nf
     return hipGetLastError();
 }
 
-int synth_chunk() { return SYNTH_CHUNK; }
-size_t synth_frame_bytes() { return sizeof(SynthFrame); }
 
 }  // namespace pdv

@@ -105,14 +105,39 @@ class SgOut(ctypes.Structure):
 _lib = None
 
 
+def _hip_runtimes() -> list:
+    """Paths of the HIP runtime libraries mapped into this process."""
+    seen = []
+    with open("/proc/self/maps") as f:
+        for line in f:
+            path = line.split()[-1] if line.strip() else ""
+            if "libamdhip64" in path and path not in seen:
+                seen.append(path)
+    return seen
+
+
 def load():
-    """Load libpdv.so from the package directory (raises if absent)."""
+    """Load libpdv.so from the package directory (raises if absent).
+
+    PyTorch is imported first: its HIP runtime is then the one the library
+    binds to (the dynamic loader resolves the library's HIP dependency to the
+    runtime already loaded under that name), so torch tensors' device
+    pointers and torch streams are valid arguments, and the process holds a
+    single HIP runtime."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libpdv.so not built at {LIB_PATH}; run __graft_entry__.build()")
+    try:
+        import torch  # noqa: F401  (device memory and streams)
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
+    runtimes = _hip_runtimes()
+    if len(runtimes) > 1:
+        raise ImportError("more than one HIP runtime in this process (%s): load paper_2012_00963_amd.pdv "
+                          "before anything that brings its own" % ", ".join(runtimes))
     P, V = ctypes.POINTER, ctypes.c_void_p
     lib.pdv_create.argtypes = [P(V), ctypes.c_int, ctypes.c_uint64, V]
     lib.pdv_destroy.argtypes = [V]

@@ -1,15 +1,11 @@
-"""Device-pointer outputs (PDV_FLAG_DEVICE_OUTPUT): the bins of a spectrum
-go device to device into caller-owned device arrays, identical to the
-host-array path on the same streams; host arrays flagged as device arrays
-are rejected before any work and leave the context usable.
-
-The device arrays are allocated with the HIP runtime the library itself
-links (found in the process's mappings once the library is loaded); a
-framework that bundles its own HIP runtime keeps its allocations in that
-runtime, where this library does not see them.
+"""Device-pointer outputs (PDV_FLAG_DEVICE_OUTPUT) into torch tensors, on a
+torch stream: the bins of a spectrum go device to device into the tensors'
+memory, identical to the host-array path on the same random streams; host
+arrays flagged as device arrays are rejected before any work and leave the
+context usable.  The binding loads the library into PyTorch's HIP runtime,
+so the process holds one runtime and torch's pointers and streams are valid
+library arguments.
 """
-import ctypes
-
 import numpy as np
 import pytest
 
@@ -17,62 +13,45 @@ from paper_2012_00963_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-H2D, D2H = 1, 2
+
+@pytest.fixture(scope="module")
+def stream():
+    import torch
+    return torch.cuda.Stream()
 
 
 @pytest.fixture(scope="module")
-def ctx():
+def ctx(stream):
     from paper_2012_00963_amd import pdv
-    c = pdv.Context(0)
+    c = pdv.Context(0, stream=stream.cuda_stream)
     yield c
     c.close()
 
 
-@pytest.fixture(scope="module")
-def hip(ctx):
-    path = None
-    with open("/proc/self/maps") as f:
-        for line in f:
-            if "libamdhip64" in line and "torch" not in line:
-                path = line.split()[-1]
-                break
-    assert path, "the library's HIP runtime is not mapped"
-    lib = ctypes.CDLL(path)
-    lib.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
-    lib.hipFree.argtypes = [ctypes.c_void_p]
-    lib.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
-    return lib
+def test_one_hip_runtime(ctx):
+    from paper_2012_00963_amd import pdv
+    rt = pdv._hip_runtimes()
+    assert len(rt) == 1 and "torch" in rt[0], rt
 
 
-def _malloc(hip, nbytes):
-    p = ctypes.c_void_p()
-    assert hip.hipMalloc(ctypes.byref(p), nbytes) == 0
-    return p.value
-
-
-def _read_u64(hip, ptr, n):
-    a = np.empty(n, dtype=np.uint64)
-    assert hip.hipMemcpy(a.ctypes.data, ptr, 8 * n, D2H) == 0
-    return a
-
-
-def test_device_outputs_equal_host_outputs(ctx, hip):
+def test_device_outputs_equal_host_outputs(ctx, stream):
+    import torch
     sets = [wl.small_hg(), dict(wl.large_mie(200_000), seed=11), dict(wl.small_hg(), n_bins=97, n_packets=33_333, seed=5)]
     print("case device outputs", [s["n_bins"] for s in sets], flush=True)
-    bufs = [(_malloc(hip, 8 * s["n_bins"]), _malloc(hip, 8 * s["n_bins"])) for s in sets]
-    try:
-        dev = ctx.spectrum_batch_device(sets, bufs)
-        host = ctx.spectrum_batch(sets)
-        for s, (w, w2), d, h in zip(sets, bufs, dev, host):
-            np.testing.assert_array_equal(_read_u64(hip, w, s["n_bins"]), h["w_fx"])
-            np.testing.assert_array_equal(_read_u64(hip, w2, s["n_bins"]), h["w2_fx"])
-            assert d["sinks_fx"] == h["sinks_fx"]
-            assert d["counts"] == h["counts"]
-            assert d["albedo"] == h["albedo"] and d["g"] == h["g"]
-    finally:
-        for w, w2 in bufs:
-            hip.hipFree(w)
-            hip.hipFree(w2)
+    # tensors allocated on the stream the context runs on
+    with torch.cuda.stream(stream):
+        bufs = [(torch.full((s["n_bins"],), -1, dtype=torch.int64, device="cuda"),
+                 torch.full((s["n_bins"],), -1, dtype=torch.int64, device="cuda")) for s in sets]
+    dev = ctx.spectrum_batch_device(sets, [(w.data_ptr(), w2.data_ptr()) for w, w2 in bufs])
+    host = ctx.spectrum_batch(sets)
+    with torch.cuda.stream(stream):
+        got = [(w.cpu().numpy().view(np.uint64), w2.cpu().numpy().view(np.uint64)) for w, w2 in bufs]
+    for s, (w, w2), d, h in zip(sets, got, dev, host):
+        np.testing.assert_array_equal(w, h["w_fx"])
+        np.testing.assert_array_equal(w2, h["w2_fx"])
+        assert d["sinks_fx"] == h["sinks_fx"]
+        assert d["counts"] == h["counts"]
+        assert d["albedo"] == h["albedo"] and d["g"] == h["g"]
 
 
 def test_host_arrays_flagged_as_device_are_rejected(ctx):

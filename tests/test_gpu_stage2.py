@@ -162,3 +162,40 @@ def test_spectrogram_overflow_flag(ctx):
     g = ctx.spectrogram(p, sg)
     assert g["overflow"] and g["status"] == -4
     assert np.all(g["frame_counts"] > 10)
+
+
+# Work split of the synthesis: a frame's entries are divided into groups of
+# chunks with partial records summed in group order (several chunks per
+# group, groups that are empty for the shorter frames, the last group taking
+# the remainder), or, when the record alone fills the grid, one block per
+# sample tile runs through all of its frame's chunks
+@pytest.mark.parametrize("case", ["groups", "one_group_many_chunks"])
+def test_beat_synthesis_work_split(ctx, case):
+    print("case beat work split", case, flush=True)
+    rng = np.random.Generator(np.random.PCG64(17 if case == "groups" else 18))
+    fs, lam = 20e9, 1550e-9
+    if case == "groups":
+        # 64 frames of 100 samples; one frame with 300 chunks of entries
+        n_frames, ns, counts = 64, 6400, [int(rng.integers(0, 5000)) for _ in range(63)] + [300 * 1024 - 5]
+        n_check = ns
+    else:
+        # one frame of 5e6 samples (9766 tiles) and 2600 entries (3 chunks);
+        # the oracle evaluates the first 30,000 samples (a one-frame record
+        # cut short has the same samples)
+        n_frames, ns, counts = 1, 5_000_000, [2600]
+        n_check = 30_000
+    lists_o, lists_g = [], []
+    for m in counts:
+        w = rng.uniform(0.01, 1.0, m).astype(np.float32)
+        v = rng.uniform(0.0, 4000.0, m)
+        ph = rng.integers(0, 2**32, m, dtype=np.uint64).astype(np.uint32)
+        lists_g.append({"w": w, "v": v, "phase_u32": ph})
+        lists_o.append({"w": w.astype(np.float64), "v": v, "phase": ph.astype(np.float64) / 2**32})
+    g = ctx.beat_synthesize(lists_g, lam, fs, ns)
+    assert np.isfinite(g).all()
+    o = ostage2.beat_signal(lists_o, n_check, fs, lam)
+    assert rel_l2(g[:n_check], o) <= 1e-4, rel_l2(g[:n_check], o)
+    if case == "groups":
+        b = ostage2.frame_bounds(ns, n_frames)
+        k = n_frames - 1
+        assert rel_l2(g[b[k]:b[k + 1]], o[b[k]:b[k + 1]]) <= 1e-4
