@@ -329,6 +329,34 @@ int pdv_beat_synthesize(struct pdv_ctx* ctx, int32_t n_frames, const uint64_t* o
                         double wavelength, double fs, int32_t n_samples, float* signal);
 
 /*
+ * Beat synthesis that allocates nothing, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses
+ * that forbid hipMalloc).  Same operation as pdv_beat_synthesize (eq. 3),
+ * with every array in device memory of the context's device: offsets
+ * [n_frames + 1] (uint64, non-decreasing), w [offsets[n_frames]] (float,
+ * >= 0; a negative weight gives NaN samples), v (double, m/s), phase_u32,
+ * and the output signal [n_samples] (float).  The arrays are read as given
+ * (not validated).  max_frame_entries: the largest entry count of any frame;
+ * with the exact value the record equals pdv_beat_synthesize's bit for bit,
+ * another value changes only how the entries are split among blocks (FP32
+ * summation order), never which entries are summed.
+ * Partial records live in a static per-device array of 16 MiB
+ * (2^22 floats) set up when the context is created;
+ * the work split never needs more (a longer record is summed without
+ * partials).  The work is enqueued on the context's stream and the call
+ * returns without waiting: the record is complete once that stream reaches
+ * this point.  Every call on one device shares its scratch, so calls that
+ * overlap on one device (two streams, two contexts) race; calls in one
+ * stream's order do not.
+ * Errors: PDV_EINVAL (sizes out of range, host or foreign pointers),
+ * PDV_ESTATE (serving, or a context without a device), PDV_EDEVICE.
+ */
+int pdv_beat_synthesize_static(struct pdv_ctx* ctx, int32_t n_frames, const uint64_t* offsets,
+                               const float* w, const double* v, const uint32_t* phase_u32,
+                               uint64_t max_frame_entries, double wavelength, double fs, int32_t n_samples,
+                               float* signal);
+
+/*
  * STFT magnitude alone: periodic Hann window of nfft (power of two) samples
  * every hop samples over signal[n_samples]; map: host [n_windows x (nfft/2+1)].
  * Returns the window count in *n_windows.

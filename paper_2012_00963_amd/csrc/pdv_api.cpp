@@ -41,6 +41,8 @@ SynthPlan synth_plan(int n_frames, int n_samples, uint64_t max_entries);
 hipError_t launch_synth(hipStream_t s, const SynthPlan& P, int n_frames, int n_samples, const uint64_t* fbeg,
                         const uint64_t* fend, const ListEntry* rec, const float* w, const double* v,
                         const uint32_t* phase, double r_scale, float* partial, float* signal);
+hipError_t synth_scratch_init(int device);
+float* synth_scratch(int device);
 hipError_t launch_stft(hipStream_t s, const float* signal, int n_windows, int nfft, int hop, void* tw, void* tr,
                        float* win, float* map, bool build_tables);
 int peak_lds_bytes(int n, int keep);
@@ -247,6 +249,8 @@ extern "C" int pdv_create(pdv_ctx** out, int device, uint64_t mem_budget, void* 
     }
     if (int r = c->hip_check(hipEventCreate(&c->ev_a), "hipEventCreate")) return r;
     if (int r = c->hip_check(hipEventCreate(&c->ev_b), "hipEventCreate")) return r;
+    // the allocation-free synthesis entry point's static scratch on this device
+    if (int r = c->hip_check(synth_scratch_init(device), "static synthesis scratch")) return r;
     c->ready = true;
     return PDV_OK;
 }
@@ -1079,6 +1083,37 @@ extern "C" int pdv_beat_synthesize(pdv_ctx* ctx, int32_t n_frames, const uint64_
                                            ctx->stream), "copy signal")))
         return r;
     return ctx->hip_check(hipStreamSynchronize(ctx->stream), "beat synthesis");
+}
+
+// Allocation-free variant of pdv_beat_synthesize: device inputs and output,
+// the groups' partial records in the library's static per-device scratch,
+// work enqueued on the context stream without waiting.
+extern "C" int pdv_beat_synthesize_static(pdv_ctx* ctx, int32_t n_frames, const uint64_t* offsets, const float* w,
+                                          const double* v, const uint32_t* phase_u32, uint64_t max_frame_entries,
+                                          double wavelength, double fs, int32_t n_samples, float* signal) {
+    if (!ctx) return PDV_EINVAL;
+    if (!ctx->ready) return ctx->fail(PDV_ESTATE, "context has no device");
+    if (ctx->serve) return ctx->fail(PDV_ESTATE, "context is serving: submit requests instead");
+    if (ctx->poisoned) return ctx->fail(PDV_EDEVICE, "context poisoned by an earlier device error");
+    if (n_frames < 1 || n_frames > SYNTH_MAX_FRAMES)
+        return ctx->fail(PDV_EINVAL, "n_frames must be in [1, 65535]");
+    if (n_samples < 1 || n_samples > (1 << 28)) return ctx->fail(PDV_EINVAL, "n_samples must be in [1, 2^28]");
+    if (!(wavelength > 0.0) || !(fs > 0.0) || !std::isfinite(wavelength) || !std::isfinite(fs))
+        return ctx->fail(PDV_EINVAL, "wavelength and fs must be finite and > 0");
+    if (int r = ctx->hip_check(hipSetDevice(ctx->device), "hipSetDevice")) return r;
+    if (!offsets || !ctx->on_device(offsets) || !signal || !ctx->on_device(signal))
+        return ctx->fail(PDV_EINVAL, "offsets and signal must be device memory of the context's device");
+    if (!w || !v || !phase_u32 || !ctx->on_device(w) || !ctx->on_device(v) || !ctx->on_device(phase_u32))
+        return ctx->fail(PDV_EINVAL, "w, v and phase_u32 must be device memory of the context's device");
+    float* scratch = synth_scratch(ctx->device);
+    if (!scratch) return ctx->fail(PDV_ESTATE, "static synthesis scratch not set up on device %d", ctx->device);
+    const SynthPlan P = synth_plan(n_frames, n_samples, max_frame_entries);
+    if (P.partial_floats > SYNTH_PARTIAL_MAX_FLOATS)
+        return ctx->fail(PDV_EINVAL, "partial records of %llu floats exceed the static scratch (%llu)",
+                         (unsigned long long)P.partial_floats, (unsigned long long)SYNTH_PARTIAL_MAX_FLOATS);
+    hipError_t e = launch_synth(ctx->stream, P, n_frames, n_samples, offsets, offsets + 1, nullptr, w, v, phase_u32,
+                                2.0 / (wavelength * fs), scratch, signal);
+    return ctx->hip_check(e, "beat synthesis kernels (static scratch)");
 }
 
 extern "C" int pdv_stft(pdv_ctx* ctx, const float* signal, int32_t n_samples, int32_t nfft, int32_t hop, float* map,

@@ -30,12 +30,44 @@
 //                   nfft/2-point complex Stockham FFT in LDS (radix 4, one
 //                   radix-2 stage when needed) and the split step, then |X|.
 #include <algorithm>
+#include <mutex>
 
 #include "pdv_device.h"
 #include "pdv_internal.h"
 
 namespace pdv {
 
+// Partial records of the allocation-free synthesis entry point: a static
+// array in every device's copy of the code object, held until the process
+// ends.  Host code never uses the array's name as an address: each device's
+// address comes from hipGetSymbolAddress at context creation.
+static __device__ __align__(256) float scratch[SYNTH_PARTIAL_MAX_FLOATS];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float* g_scratch[SCRATCH_MAX_DEVICES] = {};
+}  // namespace
+
+// With `device` current: look up this device's address of the static
+// scratch (once per device).
+hipError_t synth_scratch_init(int device) {
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[device]) return hipSuccess;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[device] = (float*)p;
+    return hipSuccess;
+}
+
+// The device's scratch address, or nullptr before synth_scratch_init.
+float* synth_scratch(int device) {
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch[device];
+}
 
 constexpr int SYNTH_CHUNK = 1024;       // entries staged in LDS at a time
 constexpr int SYNTH_THREADS = 128;

@@ -157,6 +157,8 @@ def load():
                                         ctypes.c_int32, P(ctypes.c_float)]
     lib.pdv_stft.argtypes = [V, P(ctypes.c_float), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                              P(ctypes.c_float), P(ctypes.c_int32)]
+    lib.pdv_beat_synthesize_static.argtypes = [V, ctypes.c_int32, V, V, V, V, ctypes.c_uint64, ctypes.c_double,
+                                               ctypes.c_double, ctypes.c_int32, V]
     lib.pdv_last_launch.argtypes = [V, P(ctypes.c_float), P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32),
                                     P(ctypes.c_int32), P(ctypes.c_int32)]
     _lib = lib
@@ -438,6 +440,22 @@ def _beat_synthesize(self, lists, wavelength: float, fs: float, n_samples: int) 
     return out
 
 
+def _dptr(x) -> int:
+    """Device address of a torch tensor (or an integer address)."""
+    return int(x.data_ptr()) if hasattr(x, "data_ptr") else int(x)
+
+
+def _beat_synthesize_static(self, n_frames: int, offsets, w, v, phase_u32, max_frame_entries: int,
+                            wavelength: float, fs: float, n_samples: int, signal) -> None:
+    """pdv_beat_synthesize_static: device arrays in and out (torch tensors or
+    addresses; offsets uint64 [n_frames+1], w float32, v float64, phase
+    uint32, signal float32 [n_samples]); enqueued on the context's stream,
+    not waited for."""
+    self._check(self.lib.pdv_beat_synthesize_static(
+        self.h, int(n_frames), _dptr(offsets), _dptr(w), _dptr(v), _dptr(phase_u32), int(max_frame_entries),
+        float(wavelength), float(fs), int(n_samples), _dptr(signal)))
+
+
 def _stft(self, signal, nfft: int, hop: int) -> np.ndarray:
     s = np.ascontiguousarray(signal, dtype=np.float32)
     n_win = (len(s) - nfft) // hop + 1 if len(s) >= nfft else 0
@@ -449,6 +467,7 @@ def _stft(self, signal, nfft: int, hop: int) -> np.ndarray:
 
 Context.spectrogram = _spectrogram
 Context.beat_synthesize = _beat_synthesize
+Context.beat_synthesize_static = _beat_synthesize_static
 Context.stft = _stft
 
 
