@@ -27,7 +27,7 @@ Also reported on the same JSON line:
                 FP64, p50/p99 latency).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                       [--legs batched,peaks,sensitivity,spectrogram,serve|none] [--serve-duration S]
+                       [--legs batched,peaks,sensitivity,peel,spectrogram,serve|none] [--serve-duration S]
                        [--serve-only] [--calib-copy BYTES]
 """
 from __future__ import annotations
@@ -87,6 +87,21 @@ def committed_traffic():
     if not m_hash or not m_b or m_hash.group(1) != kernel_hash():
         return None
     return float(m_b.group(1))
+
+
+def err_vs_oracle(g, o, n):
+    """Parity figures of a GPU tally against the FP64 oracle's on the same
+    packets and streams: relative error of the total detected weight, the
+    largest per-bin z (combined variance of both), L1 error of the spectrum."""
+    import numpy as np
+    Wg, Wo = np.asarray(g["W"], dtype=np.float64), np.asarray(o["W"], dtype=np.float64)
+    var = (np.asarray(g["W2"]) - Wg ** 2 / n) + (np.asarray(o["W2"]) - Wo ** 2 / n)
+    use = (np.asarray(g["W2"]) > 0) | (np.asarray(o["W2"]) > 0)
+    z = np.abs(Wg[use] - Wo[use]) / np.sqrt(np.maximum(var[use], 1e-300))
+    tot = Wo.sum()
+    return {"total_rel": float(abs(Wg.sum() - tot) / tot) if tot > 0 else float(abs(Wg.sum())),
+            "z_max": float(z.max()) if z.size else 0.0,
+            "l1": float(np.abs(Wg - Wo).sum() / tot) if tot > 0 else float(np.abs(Wg).sum())}
 
 
 def l1_err(a, b):
@@ -231,6 +246,50 @@ def sensitivity_leg(ctx):
             "transport_s": t2 - t1, "peak_analysis_s": t3 - t2, "rows": rows}
 
 
+def peel_leg(ctx, check_oracle=True):
+    """Next-event (peel-off) estimate against the ordinary cone tally on the
+    small slab at its 5 degree cone, 1e7 packets: GPU time of each, relative
+    standard error of the particle-scattered part of the spectrum (bins above
+    the free-surface peak), the figure of merit 1 / (variance x time) of each,
+    and the estimate's error against the FP64 oracle on the same streams."""
+    import math
+    import numpy as np
+    import torch
+    from paper_2012_00963_amd import workloads
+    p = dict(workloads.small_hg(), n_packets=10_000_000)
+    n = p["n_packets"]
+    ctx.spectrum(dict(p, n_packets=100_000), peel=True)
+    ctx.spectrum(dict(p, n_packets=100_000))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rt = ctx.spectrum(p)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rp = ctx.spectrum(p, peel=True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    dv = (p["v_hi"] - p["v_lo"]) / p["n_bins"]
+    part = np.arange(p["n_bins"]) * dv + p["v_lo"] > p["v_surface"] + 2 * dv
+
+    def rel_var(W, W2):
+        tot = W[part].sum()
+        return float((W2[part] - W[part] ** 2 / n).sum() / tot ** 2) if tot > 0 else float("inf")
+
+    v_t, v_p = rel_var(rt["W"], rt["W2"]), rel_var(rp["P"], rp["P2"])
+    out = {"workload": "small slab, HG g=0.7, tau 0.1, 5 deg cone, 1e7 packets, FP32",
+           "tally_s": t1 - t0, "peel_s": t2 - t1,
+           "tally_particle_rel_se": math.sqrt(v_t), "peel_particle_rel_se": math.sqrt(v_p),
+           "variance_ratio": v_t / v_p if v_p > 0 else None,
+           "figure_of_merit_gain": (v_t * (t1 - t0)) / (v_p * (t2 - t1)) if v_p > 0 else None,
+           "tally_particle_detected": float(rt["W"][part].sum()), "peel_particle_estimate": float(rp["P"][part].sum())}
+    if check_oracle:
+        from oracle import mc
+        o = mc.run(p, peel=True, n_threads=os.cpu_count() or 1)
+        out["vs_oracle"] = err_vs_oracle({"W": rp["P"], "W2": rp["P2"]}, {"W": o["P"], "W2": o["P2"]}, n)
+        out["vs_oracle"]["sample"] = "all 1e7 packets, same streams"
+    return out
+
+
 def spectrogram_leg(ctx):
     """Time-resolved case: 256 frames x 1e6 packets, 20 GS/s beat record of
     1e5 samples with FP64 phase, 4096-point Hann STFT at 80% overlap."""
@@ -318,8 +377,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
-    ap.add_argument("--legs", default="batched,peaks,sensitivity,spectrogram,serve",
-                    help="comma list of extra legs: batched,peaks,sensitivity,spectrogram,serve (or none)")
+    ap.add_argument("--legs", default="batched,peaks,sensitivity,peel,spectrogram,serve",
+                    help="comma list of extra legs: batched,peaks,sensitivity,peel,spectrogram,serve (or none)")
     ap.add_argument("--cpu-sample", type=int, default=20_000_000, help="packets in the oracle sample")
     ap.add_argument("--calib-copy", type=int, default=0, help="only run a copy of this many bytes")
     ap.add_argument("--serve-duration", type=float, default=60.0, help="seconds of the serving trace")
@@ -436,6 +495,8 @@ def main(argv=None):
         out["extra"]["peaks"] = peaks_leg(ctx, spectra_512)
     if "sensitivity" in legs:
         out["extra"]["sensitivity"] = sensitivity_leg(ctx)
+    if "peel" in legs:
+        out["extra"]["peel"] = peel_leg(ctx, check_oracle=not args.no_cpu)
     if "spectrogram" in legs:
         out["extra"]["spectrogram"] = spectrogram_leg(ctx)
     if "serve" in legs:

@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define PDV_ABI_VERSION 1
+#define PDV_ABI_VERSION 2
 
 typedef enum {
     PDV_OK = 0,
@@ -78,6 +78,18 @@ enum { PDV_FP32 = 0, PDV_FP64 = 1 };
  * (pdv_spectrogram and pdv_submit reject it); a pointer that is not device
  * memory of the context's device gives PDV_EINVAL before any work. */
 #define PDV_FLAG_DEVICE_OUTPUT 2u
+/* Also score the next-event (peel-off) estimate of the detector tally into
+ * pdv_spectrum_out.peel_fx: at every particle scattering and surface
+ * reflection, the expected weight that leaves the top inside the detector
+ * cone on the next flight (Beer-Lambert escape of eq. 7 times the share of
+ * the scattering law, eq. 13-16, or of the surface law that points into the
+ * cone, detector of eq. 19), scored at the apparent velocity after the event
+ * (eq. 4), from one draw restricted to the directions that reach the cone
+ * (its own Philox block, counter word 0 = event index | 2^31, so the
+ * ordinary tally is unchanged).  Its expectation equals the detector tally;
+ * for narrow cones its variance is far lower.  Accepted by pdv_spectrum and
+ * pdv_spectrum_batch only. */
+#define PDV_FLAG_PEEL 4u
 
 /*
  * One parameter set: the problem statement of Sec. II.
@@ -178,7 +190,11 @@ typedef struct pdv_counters {
  * nullable; if given and PDV_FLAG_CLASS_TALLIES is set, 2*n_bins entries:
  * [0, n_bins) single-scattering paths (one particle scattering, no surface
  * hit), [n_bins, 2 n_bins) surface-only paths.  Conservation holds exactly:
- * sum(w_fx) + sum(sinks_fx) = n_packets * 2^32.
+ * sum(w_fx) + sum(sinks_fx) = n_packets * 2^32.  peel_fx: nullable; if
+ * given and PDV_FLAG_PEEL is set, 2*n_bins entries (x 2^32, each score
+ * rounded to the nearest 2^-32): [0, n_bins) the next-event estimate sum(c)
+ * per bin, [n_bins, 2 n_bins) sum(c^2); peel_sinks_fx: its scores below and
+ * above the bin range.
  */
 typedef struct pdv_spectrum_out {
     uint64_t* w_fx;
@@ -188,6 +204,8 @@ typedef struct pdv_spectrum_out {
     pdv_counters counters;
     double albedo;        /* single-scattering albedo used (Mie: size average) */
     double g;             /* mean cosine of the phase function used */
+    uint64_t* peel_fx;
+    uint64_t peel_sinks_fx[2];
 } pdv_spectrum_out;
 
 /* Launch options for batches; pass NULL for the tuned defaults. */
@@ -454,7 +472,8 @@ int pdv_serve_start(struct pdv_ctx* ctx, const pdv_serve_opts* opts);
 /* Queue a request; *ticket identifies it.  Thread-safe.  PDV_EINVAL (bad
  * parameters, beyond the serving limits, or PDV_FLAG_DEVICE_OUTPUT: served
  * results are host arrays), PDV_ENOMEM (larger than the
- * whole memory budget), PDV_ESTATE (not serving or stopping). */
+ * whole memory budget), PDV_ESTATE (not serving or stopping).  PDV_FLAG_PEEL
+ * requests are rejected (PDV_EINVAL). */
 int pdv_submit(struct pdv_ctx* ctx, const pdv_request* req, uint64_t* ticket);
 /* Status of a request: PDV_PENDING, or its final status (PDV_OK, PDV_EOVERFLOW,
  * PDV_ECANCELLED, PDV_EDEVICE, ...).  wait_ms > 0 waits up to that long,

@@ -420,7 +420,12 @@ void pdv::fill_desc(SetDesc& d, const pdv_params& p) {
     d.surface_one = p.surface_albedo >= 1.0;
     d.albedo_f = (float)d.albedo;
     d.surface_albedo_f = (float)p.surface_albedo;
-    d.flags = (p.flags & PDV_FLAG_CLASS_TALLIES) ? SF_CLASS : 0u;
+    d.flags = ((p.flags & PDV_FLAG_CLASS_TALLIES) ? SF_CLASS : 0u) | ((p.flags & PDV_FLAG_PEEL) ? SF_PEEL : 0u);
+    d.alpha = std::acos(d.cos_cone);
+    d.sin2_cone = (1.0 - d.cos_cone) * (1.0 + d.cos_cone);
+    d.sin_cone = std::sqrt(d.sin2_cone);
+    d.peel_surface_m = p.surface_law == PDV_SURFACE_LAMBERT ? d.sin2_cone : d.alpha / (0.5 * 3.14159265358979323846);
+    d.cells_per_rad = p.phase_kind == PDV_PHASE_HG ? 0.0 : (double)(p.n_angles - 1) / 3.14159265358979323846;
     d.n_layers = p.n_layers;
     d.phase_kind = p.phase_kind == PDV_PHASE_HG ? PH_HG : PH_TABLE;
     d.n_cells = p.phase_kind == PDV_PHASE_HG ? 0 : p.n_angles - 1;
@@ -447,13 +452,14 @@ int pdv::launch_kind_of(const pdv_params* sets, int n) {
 }
 
 void pdv_ctx::default_opts(pdv_launch_opts& o, uint64_t total_packets, int n_sets, bool fp64, int kind,
-                           bool list) const {
+                           bool list, bool peel) const {
     (void)n_sets;
     // measured on the large case: the specialised FP32 kernels run best as
     // two 1024-thread blocks per CU (eight waves per SIMD), the generic FP32
     // kernel as two 768-thread blocks (six waves), FP64 as one 1024-thread
     // block per CU
-    const int def_block = fp64 ? 1024 : (kind != KIND_GENERIC ? 1024 : 768);
+    // (next-event launches hold six waves per SIMD in every kind)
+    const int def_block = fp64 ? 1024 : (kind != KIND_GENERIC && !peel ? 1024 : 768);
     const int def_bpc = fp64 ? 1 : 2;
     if (o.block_size <= 0) o.block_size = tuned.block_size > 0 ? tuned.block_size : def_block;
     if (o.blocks_per_cu <= 0) o.blocks_per_cu = tuned.blocks_per_cu > 0 ? tuned.blocks_per_cu : def_bpc;
@@ -494,7 +500,9 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
         if (sets[i].flags & PDV_FLAG_DEVICE_OUTPUT) {
             if (!outs || list_capacity) return fail(PDV_EINVAL, "set %d: device outputs need a spectrum call", i);
             const bool cls = outs[i].class_fx && (sets[i].flags & PDV_FLAG_CLASS_TALLIES);
-            if (!on_device(outs[i].w_fx) || !on_device(outs[i].w2_fx) || (cls && !on_device(outs[i].class_fx)))
+            const bool pl = outs[i].peel_fx && (sets[i].flags & PDV_FLAG_PEEL);
+            if (!on_device(outs[i].w_fx) || !on_device(outs[i].w2_fx) || (cls && !on_device(outs[i].class_fx)) ||
+                (pl && !on_device(outs[i].peel_fx)))
                 return fail(PDV_EINVAL, "set %d: PDV_FLAG_DEVICE_OUTPUT needs device arrays on device %d", i, device);
         }
     }
@@ -505,7 +513,10 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
     uint64_t total = 0;
     for (int i = 0; i < n; ++i) total += sets[i].n_packets;
     const int kind = launch_kind_of(sets, n);
-    default_opts(o, total, n, precision == PDV_FP64, kind, list_capacity > 0);
+    bool peel = false;
+    for (int i = 0; i < n; ++i) peel = peel || (sets[i].flags & PDV_FLAG_PEEL) != 0;
+    if (peel && list_capacity) return fail(PDV_EINVAL, "PDV_FLAG_PEEL is for pdv_spectrum and pdv_spectrum_batch only");
+    default_opts(o, total, n, precision == PDV_FP64, kind, list_capacity > 0, peel);
     if (o.block_size != 256 && o.block_size != 512 && o.block_size != 768 && o.block_size != 1024)
         return fail(PDV_EINVAL, "block_size must be 256, 512, 768 or 1024");
     if (o.guide_bits != 0 && (o.guide_bits < MIN_GUIDE_BITS || o.guide_bits > GUIDE_BITS))
@@ -665,6 +676,7 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
     sh.retire_min = o.retire_batch;
     // FP32 sets that all share a specialised kind run that kind's kernel
     sh.kind = kind;
+    sh.peel = peel;
     last_kind = sh.kind;
     {
         hipError_t e = plan_transport(sh, precision, list_capacity > 0, o.guide_bits, lds_per_block, lds_per_cu);
@@ -710,6 +722,8 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
             h_copy.push_back(CopyJob{t0 + tw_w2(nb), (uint64_t)nb, outs[i].w2_fx});
             if (outs[i].class_fx && (sets[i].flags & PDV_FLAG_CLASS_TALLIES))
                 h_copy.push_back(CopyJob{t0 + tw_class(nb), 2ull * nb, outs[i].class_fx});
+            if (outs[i].peel_fx && (sets[i].flags & PDV_FLAG_PEEL))
+                h_copy.push_back(CopyJob{t0 + tw_peel(nb), 2ull * nb, outs[i].peel_fx});
         }
     }
     if (!h_copy.empty()) {
@@ -753,6 +767,7 @@ int pdv_ctx::launch_batch_graph(const TransportShape& sh, int precision, bool li
     k.guide_bits = sh.guide_bits;
     k.retire_min = sh.retire_min;
     k.kind = sh.kind;
+    k.peel = sh.peel ? 1 : 0;
     k.max_layers = sh.max_layers;
     k.max_cells = sh.max_cells;
     k.max_bins = sh.max_bins;
@@ -804,8 +819,11 @@ void pdv_ctx::unpack(const pdv_params& p, const SetDesc& d, const uint64_t* t, p
         std::memcpy(o.w_fx, t + tw_w(nb), 8ull * nb);
         std::memcpy(o.w2_fx, t + tw_w2(nb), 8ull * nb);
         if (o.class_fx && (p.flags & PDV_FLAG_CLASS_TALLIES)) std::memcpy(o.class_fx, t + tw_class(nb), 16ull * nb);
+        if (o.peel_fx && (p.flags & PDV_FLAG_PEEL)) std::memcpy(o.peel_fx, t + tw_peel(nb), 16ull * nb);
     }
     for (int k = 0; k < PDV_N_SINKS; ++k) o.sinks_fx[k] = t[tw_sinks(nb) + k];
+    o.peel_sinks_fx[0] = t[tw_sinks(nb) + SK_PEEL_UNDER];
+    o.peel_sinks_fx[1] = t[tw_sinks(nb) + SK_PEEL_OVER];
     const uint64_t* c = t + tw_counts(nb);
     o.counters.packets = c[C_PACKETS];
     o.counters.collisions = c[C_COLLISIONS];
@@ -952,8 +970,9 @@ extern "C" int pdv_spectrogram(pdv_ctx* ctx, const pdv_params* p, const pdv_sg_p
 
 int pdv_spectrogram_internal(pdv_ctx* ctx, const pdv_params* p, const pdv_sg_params* sg, pdv_sg_out* out) {
     if (!out || !out->map) return ctx->fail(PDV_EINVAL, "NULL spectrogram output map");
-    if (p && (p->flags & PDV_FLAG_DEVICE_OUTPUT))
-        return ctx->fail(PDV_EINVAL, "PDV_FLAG_DEVICE_OUTPUT is for pdv_spectrum and pdv_spectrum_batch only");
+    if (p && (p->flags & (PDV_FLAG_DEVICE_OUTPUT | PDV_FLAG_PEEL)))
+        return ctx->fail(PDV_EINVAL, "PDV_FLAG_DEVICE_OUTPUT and PDV_FLAG_PEEL are for pdv_spectrum and "
+                                     "pdv_spectrum_batch only");
     if (int r = check_sg(ctx, sg)) return r;
     if (int r = validate_params(ctx, p)) return r;
     if (!(p->wavelength > 0.0)) return ctx->fail(PDV_EINVAL, "wavelength must be > 0");

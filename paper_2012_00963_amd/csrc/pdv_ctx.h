@@ -48,13 +48,13 @@ struct TunedLaunch {
 // What a captured batch graph was recorded with.
 struct BatchGraphKey {
     int precision = -1, list = 0, persistent = 0, grid = 0, block = 0, lds = 0, guide_bits = 0, retire_min = 0;
-    int kind = -1;
+    int kind = -1, peel = 0;
     int max_layers = 0, max_cells = 0, max_bins = 0;
     void* ptr[8] = {};
     bool operator==(const BatchGraphKey& o) const {
         if (precision != o.precision || list != o.list || persistent != o.persistent || grid != o.grid ||
             block != o.block || lds != o.lds || guide_bits != o.guide_bits || retire_min != o.retire_min ||
-            kind != o.kind ||
+            kind != o.kind || peel != o.peel ||
             max_layers != o.max_layers || max_cells != o.max_cells || max_bins != o.max_bins)
             return false;
         for (int i = 0; i < 8; ++i)
@@ -131,7 +131,7 @@ struct pdv_ctx {
     int ensure_pinned(HostPinned& b, size_t bytes, const char* what);
     int ensure_mie_basis(const pdv_params& p);
     void default_opts(pdv_launch_opts& o, uint64_t total_packets, int n_sets, bool fp64, int kind,
-                      bool list) const;
+                      bool list, bool peel = false) const;
     int run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, const pdv_launch_opts* opts,
                   uint64_t list_capacity, bool keep_device);
     int synthesize(int n_frames, const uint64_t* entry_begin, const uint64_t* n_entries, const ListEntry_* entries,

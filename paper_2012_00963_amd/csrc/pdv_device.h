@@ -97,6 +97,11 @@ template <> struct M<float> {
     static __device__ __forceinline__ float sin_rev(float r) { return __builtin_amdgcn_sinf(r); }
     // x clamped to [-1, 1] (one v_med3_f32)
     static __device__ __forceinline__ float clamp1(float x) { return __builtin_amdgcn_fmed3f(x, -1.0f, 1.0f); }
+    // exp(-x) through the base-2 exponential unit
+    static __device__ __forceinline__ float exp_neg(float x) {
+        return __builtin_amdgcn_exp2f(-x * 1.44269504088896341f);
+    }
+    static __device__ __forceinline__ float acos(float x) { return ::acosf(x); }
 };
 
 template <> struct M<double> {
@@ -111,6 +116,8 @@ template <> struct M<double> {
     static __device__ __forceinline__ double cos_rev(double r) { return ::cos(2.0 * PI * r); }
     static __device__ __forceinline__ double sin_rev(double r) { return ::sin(2.0 * PI * r); }
     static __device__ __forceinline__ double clamp1(double x) { return x > 1.0 ? 1.0 : (x < -1.0 ? -1.0 : x); }
+    static __device__ __forceinline__ double exp_neg(double x) { return ::exp(-x); }
+    static __device__ __forceinline__ double acos(double x) { return ::acos(x); }
 };
 
 template <typename Real>

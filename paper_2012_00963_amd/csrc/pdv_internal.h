@@ -37,21 +37,27 @@ struct TableLayout {
     static constexpr uint64_t BYTES = (PHASE + 8ull * MAX_ANGLES + 255) & ~255ull;
 };
 
-// Tally block of one set, in uint64 words.
+// Tally block of one set, in uint64 words: sum(w) and sum(w^2) per bin, the
+// two class tallies, the next-event estimate sum(c) and sum(c^2) per bin,
+// eight sink words (the six terminal sinks, then the next-event scores
+// below and above the bin range), eight counters.
 enum TallyWords : int { TW_SINKS = 8, TW_COUNTS = 8 };
 inline __host__ __device__ uint64_t tally_words(int n_bins) {
-    return 4ull * (uint64_t)n_bins + TW_SINKS + TW_COUNTS;
+    return 6ull * (uint64_t)n_bins + TW_SINKS + TW_COUNTS;
 }
 // word offsets inside a tally block
 inline __host__ __device__ uint64_t tw_w(int) { return 0; }
 inline __host__ __device__ uint64_t tw_w2(int n_bins) { return (uint64_t)n_bins; }
 inline __host__ __device__ uint64_t tw_class(int n_bins) { return 2ull * n_bins; }
-inline __host__ __device__ uint64_t tw_sinks(int n_bins) { return 4ull * n_bins; }
-inline __host__ __device__ uint64_t tw_counts(int n_bins) { return 4ull * n_bins + TW_SINKS; }
+inline __host__ __device__ uint64_t tw_peel(int n_bins) { return 4ull * n_bins; }
+inline __host__ __device__ uint64_t tw_peel2(int n_bins) { return 5ull * n_bins; }
+inline __host__ __device__ uint64_t tw_sinks(int n_bins) { return 6ull * n_bins; }
+inline __host__ __device__ uint64_t tw_counts(int n_bins) { return 6ull * n_bins + TW_SINKS; }
 
-// sink word indices inside the sinks block (match pdv.h)
+// sink word indices inside the sinks block (match pdv.h; the last two hold
+// next-event scores outside the bin range)
 enum SinkIdx : int { SK_UNDER = 0, SK_OVER = 1, SK_UNDETECTED = 2, SK_ABS_PARTICLE = 3,
-                     SK_ABS_SURFACE = 4, SK_TRUNCATED = 5 };
+                     SK_ABS_SURFACE = 4, SK_TRUNCATED = 5, SK_PEEL_UNDER = 6, SK_PEEL_OVER = 7 };
 enum CountIdx : int { C_PACKETS = 0, C_COLLISIONS = 1, C_SURFACE = 2, C_EXITS = 3, C_DETECTED = 4 };
 
 // Per-set constants.  Host fills everything except the fields marked
@@ -65,6 +71,11 @@ struct alignas(16) SetDesc {
     double cos_cone;
     double v_lo, dv, inv_dv;
     double zeta_per_tau;        // uniform density: (v_top - v_bottom) / tau_total
+    // detector cone for the next-event estimate: half angle alpha (as
+    // acos(cos alpha)), sin alpha, sin^2 alpha, the share of reflected
+    // directions inside the cone under the set's surface law, and angle
+    // cells per radian of the tabulated law
+    double alpha, sin_cone, sin2_cone, peel_surface_m, cells_per_rad;
     // precomputed Henyey-Greenstein constants: 1+g^2, 1-g^2, 1-g, 2g, 1/(2g)
     double hg_a, hg_b, hg_c0, hg_c1, hg_inv2g;
     double lg_scale;            // LAYER_GUIDE / tau_total (finest guide cells per unit depth)
@@ -116,7 +127,7 @@ struct alignas(16) ListEntry {
     double v;
 };
 
-enum SetFlags : uint32_t { SF_CLASS = 1u, SF_LIST = 2u };
+enum SetFlags : uint32_t { SF_CLASS = 1u, SF_LIST = 2u, SF_PEEL = 4u };
 
 // Beat synthesis work split: blocks take (sample tile, frame, group of
 // entry chunks); the entries of a frame are split into groups only while
@@ -150,6 +161,7 @@ struct TransportShape {
     int lds_bytes = 0;
     int retire_min = 12;                                // finished lanes per retire round
     int kind = KIND_GENERIC;                            // kernel specialisation (FP32 only)
+    bool peel = false;                                  // next-event estimate for sets that ask for it
 };
 
 // Peak analysis (host-packed constants of one call) and its per-spectrum result.

@@ -693,6 +693,7 @@ extern "C" int pdv_submit(pdv_ctx* ctx, const pdv_request* req, uint64_t* ticket
     if (validate_params(nullptr, &p) != PDV_OK) return PDV_EINVAL;
     if (!req->out->w_fx || !req->out->w2_fx) return PDV_EINVAL;
     if (p.flags & PDV_FLAG_DEVICE_OUTPUT) return PDV_EINVAL;   // served results are host arrays
+    if (p.flags & PDV_FLAG_PEEL) return PDV_EINVAL;            // served launches carry the ordinary tally only
     if (p.precision != E->opts.precision) return PDV_EINVAL;
     if (p.n_layers > E->opts.max_layers || p.n_bins > E->opts.max_bins ||
         (p.phase_kind != PDV_PHASE_HG && p.n_angles > E->opts.max_angles))

@@ -47,7 +47,7 @@
 namespace pdv {
 
 struct LdsLayout {
-    uint32_t t_off, lg_off, cdf_off, cg_off, hist_off, hist2_off, list_off, bytes;
+    uint32_t t_off, lg_off, cdf_off, cg_off, hist_off, hist2_off, peel_off, peel2_off, list_off, bytes;
 };
 
 // A guide cell's margin (in finest cells) around the scaled depth: covers
@@ -78,7 +78,7 @@ constexpr int REFILL_CHUNK_MIN = 32;
 constexpr int LIST_STAGE = 64;
 
 __host__ __device__ inline LdsLayout lds_layout(int real_bytes, int max_layers, int max_cells, int max_bins,
-                                                int guide_bits, int list_waves) {
+                                                int guide_bits, int list_waves, bool peel) {
     const uint32_t guide_entries = (1u << guide_bits) + 1u;
     LdsLayout L;
     // FP32 launches stage each layer depth and CDF entry beside the inverse
@@ -91,7 +91,11 @@ __host__ __device__ inline LdsLayout lds_layout(int real_bytes, int max_layers, 
     L.cg_off = align16(L.cdf_off + c_entry * (uint32_t)(max_cells + 1));
     L.hist_off = align16(L.cg_off + 2u * guide_entries);
     L.hist2_off = align16(L.hist_off + 8u * (uint32_t)(max_bins + N_SINK_SLOTS));
-    L.list_off = align16(L.hist2_off + 8u * (uint32_t)max_bins);
+    // next-event launches: sum(c) and sum(c^2) per bin (their scores outside
+    // the bin range go to two of the sink slots)
+    L.peel_off = align16(L.hist2_off + 8u * (uint32_t)max_bins);
+    L.peel2_off = align16(L.peel_off + (peel ? 8u * (uint32_t)max_bins : 0u));
+    L.list_off = align16(L.peel2_off + (peel ? 8u * (uint32_t)max_bins : 0u));
     L.bytes = align16(L.list_off + (uint32_t)sizeof(ListEntry) * LIST_STAGE * (uint32_t)list_waves);
     return L;
 }
@@ -101,6 +105,7 @@ struct SetConst {            // wave-uniform per-set constants (kept in SGPRs)
     Real tau, v_top, dzeta, zeta_per_tau, v_surface, surface_albedo, albedo, cos_cone;
     Real hg_a, hg_b, hg_c0, hg_c1, hg_inv2g, hg_g;
     Real lg_scale, rev_per_cell, dtheta;
+    Real alpha, sin_cone, sin2_cone, peel_surface_m, cells_per_rad;
     double v_lo, dv, inv_dv;
     uint32_t k0, k1, stream, thr_albedo, thr_surface, flags;
     int n_layers, n_cells, n_bins, max_orders, phase_kind, surface_law, weighting;
@@ -134,6 +139,11 @@ __device__ __forceinline__ SetConst<Real> load_const(const SetDesc& d) {
     c.lg_scale = (Real)d.lg_scale;
     c.rev_per_cell = (Real)d.rev_per_cell;
     c.dtheta = (Real)d.dtheta;
+    c.alpha = (Real)d.alpha;
+    c.sin_cone = (Real)d.sin_cone;
+    c.sin2_cone = (Real)d.sin2_cone;
+    c.peel_surface_m = (Real)d.peel_surface_m;
+    c.cells_per_rad = (Real)d.cells_per_rad;
     c.v_lo = d.v_lo;
     c.dv = d.dv;
     c.inv_dv = d.inv_dv;
@@ -233,9 +243,10 @@ __device__ __forceinline__ Real zeta_at(const SetConst<Real>& c, const typename 
 // C[j] <= x; it lies between the guide entries of the top guide_bits bits of
 // x; the angle is uniform inside the cell.  Returned in units of the cell
 // grid (cell index plus the fraction inside it).
-template <typename Real>
-__device__ __forceinline__ Real table_cells(const typename Staged<Real>::CE* C, const uint16_t* cg, int guide_bits,
-                                            uint32_t x) {
+// The cell of a 32-bit CDF value x: the last j with C[j] <= x, between the
+// guide entries of the top guide_bits bits of x.
+template <typename CE>
+__device__ __forceinline__ int table_cell_of(const CE* C, const uint16_t* cg, int guide_bits, uint32_t x) {
     const uint32_t gi = x >> (32 - guide_bits);
     int lo = cg[gi];
     int hi = cg[gi + 1];
@@ -245,6 +256,13 @@ __device__ __forceinline__ Real table_cells(const typename Staged<Real>::CE* C, 
         lo = le ? mid : lo;
         hi = le ? hi : mid - 1;
     }
+    return lo;
+}
+
+template <typename Real>
+__device__ __forceinline__ Real table_cells(const typename Staged<Real>::CE* C, const uint16_t* cg, int guide_bits,
+                                            uint32_t x) {
+    const int lo = table_cell_of(C, cg, guide_bits, x);
     if constexpr (sizeof(Real) == 4) {
         const uint2 e = C[lo];
         return (Real)lo + ((Real)(x - e.x) + (Real)0.5) * __uint_as_float(e.y);
@@ -295,6 +313,181 @@ __device__ __forceinline__ void hg_angle(const SetConst<Real>& c, Real u, Real& 
     st = M<Real>::sqrt(s2 > (Real)0.0 ? s2 : (Real)0.0);
 }
 
+// ---------------------------------------------------------------------------
+// Next-event (peel-off) estimate of the detector tally.
+//
+// A photon leaving a scattering or a reflection at depth T with direction
+// cosine mu' > 0 leaves the top without another interaction with
+// probability exp(-T/mu') (Beer-Lambert, eq. 7), and the detector (eq. 19)
+// takes it if mu' >= cos alpha.  The expected detected weight of the event's
+// next flight, w a E[1(mu' >= cos alpha) exp(-T/mu')] (a the event's albedo,
+// the expectation over the scattering law of eq. 13-16 or the surface law),
+// is scored at the apparent velocity the photon carries after the event
+// (eq. 4).  Summed over all events its expectation is the detector tally,
+// because every detected photon left its last event that way.  One draw
+// restricted to the directions that can reach the cone estimates the
+// expectation, with the probability of that set of directions as weight:
+//   surface, uniform polar angle: psi uniform on [0, alpha], weight
+//     alpha / (pi/2); Lambert: mu'^2 uniform on [cos^2 alpha, 1], weight
+//     sin^2 alpha;
+//   particle: the cone lies within alpha of the vertical, so the scattering
+//     angle lies within alpha of the incoming polar angle theta0 = acos(mu):
+//     it is drawn from the law restricted to [max(0, theta0 - alpha),
+//     min(pi, theta0 + alpha)] (weight: the law's mass there), then the
+//     azimuth uniformly from the arc |phi| <= phi_c on which the new
+//     direction is inside the cone, cos phi_c = (cos alpha - mu cos Theta) /
+//     (sqrt(1 - mu^2) sin Theta) (weight phi_c / pi).
+// Every weight lies in [0, 1].  The draw takes its own Philox block (counter
+// word 0 = event index with the top bit set), so the transport's own draws
+// are untouched and the ordinary tally is the same with or without it.
+// ---------------------------------------------------------------------------
+
+// HG probability of cos Theta <= x, written without cancellation:
+// (1 - g)(1 + x) / (r (1 + g + r)), r = sqrt(1 + g^2 - 2 g x); the inverse
+// of hg_angle's map from u to cos Theta
+template <typename Real>
+__device__ __forceinline__ Real hg_cdf(const SetConst<Real>& c, Real x) {
+    const Real D = M<Real>::fma(-c.hg_c1, x, c.hg_a);
+    const Real r = M<Real>::sqrt(D > (Real)0 ? D : (Real)0);
+    const Real den = r * ((Real)1.0 + c.hg_g + r);
+    return den > (Real)0 ? M<Real>::div(c.hg_c0 * ((Real)1.0 + x), den) : (Real)1.0;
+}
+
+// Width of CDF cell j in units of 2^-32 (the last cell ends at 2^32; a
+// zero width is a cell of zero mass)
+template <typename CE>
+__device__ __forceinline__ uint64_t cell_width(const CE* C, int n_cells, int j) {
+    const uint64_t next = j + 1 < n_cells ? (uint64_t)key_of(C[j + 1]) : 4294967296ull;
+    return next - (uint64_t)key_of(C[j]);
+}
+
+// Tabulated law: probability (units of 2^-32) that the angle lies below the
+// angle x cells from 0 (uniform angle inside a cell)
+template <typename CE>
+__device__ __forceinline__ double table_cdf_at(const CE* C, int n_cells, double x) {
+    if (x <= 0.0) return 0.0;
+    if (x >= (double)n_cells) return 4294967296.0;
+    int j = (int)floor(x);
+    j = j > n_cells - 1 ? n_cells - 1 : j;
+    return (double)key_of(C[j]) + (x - (double)j) * (double)cell_width(C, n_cells, j);
+}
+
+// Weight of one restricted draw after a particle scattering (incoming
+// direction cosine mu, sm = sqrt(1 - mu^2), depth T) or a reflection; also
+// returns 1 - mu' of the drawn direction.
+template <typename Real, int KIND>
+__device__ __forceinline__ Real peel_weight(const SetConst<Real>& c, const typename Staged<Real>::CE* C,
+                                            const uint16_t* cg, int guide_bits, bool surf, Real mu, Real sm, Real T,
+                                            Real ur, Real uphi, Real& omc) {
+    constexpr Real PI = (Real)3.14159265358979323846;
+    if (surf) {
+        Real mu_n, M_;
+        if (Kind<KIND>::lambert(c)) {
+            const Real t = c.sin2_cone * ((Real)1.0 - ur);
+            mu_n = M<Real>::sqrt((Real)1.0 - t);
+            omc = M<Real>::div(t, (Real)1.0 + mu_n);
+        } else {
+            Real sh;
+            if constexpr (sizeof(Real) == 4) {
+                // half the angle, in revolutions: alpha ur / (4 pi)
+                sh = M<Real>::sin_rev(c.alpha * ur * (Real)0.0795774715459476679);
+                omc = (Real)2.0 * sh * sh;
+                mu_n = (Real)1.0 - omc;
+            } else {
+                const Real psi = c.alpha * ur;
+                sh = ::sin((Real)0.5 * psi);
+                mu_n = ::cos(psi);
+                omc = (Real)2.0 * sh * sh;
+            }
+        }
+        M_ = c.peel_surface_m;
+        return mu_n > (Real)0 ? M_ * M<Real>::exp_neg(M<Real>::div(c.tau, mu_n)) : (Real)0;
+    }
+    const Real ca = c.cos_cone;
+    Real cth, sth, M_;
+    if (Kind<KIND>::table(c)) {
+        const int nc = c.n_cells;
+        const Real theta0 = M<Real>::acos(mu);
+        const Real th_lo = theta0 - c.alpha > (Real)0 ? theta0 - c.alpha : (Real)0;
+        const Real th_hi = theta0 + c.alpha < PI ? theta0 + c.alpha : PI;
+        if constexpr (sizeof(Real) == 8) {
+            const double y_lo = table_cdf_at(C, nc, th_lo / c.dtheta);
+            const double y_hi = table_cdf_at(C, nc, th_hi / c.dtheta);
+            M_ = (y_hi - y_lo) * 2.3283064365386963e-10;
+            const double y = y_lo + (y_hi - y_lo) * ur;
+            const double yf = floor(y);
+            const uint32_t xi = yf >= 4294967295.0 ? 0xffffffffu : (uint32_t)yf;
+            const int lo = table_cell_of(C, cg, guide_bits, xi);
+            const double width = (double)cell_width(C, nc, lo);
+            const double f = width > 0.0 ? (y - (double)C[lo]) / width : 0.0;
+            const double th = ((double)lo + f) * c.dtheta;
+            cth = ::cos(th);
+            sth = ::sin(th);
+        } else {
+            // the bounds in cell units; the law's mass between them and the
+            // drawn offset from the lower cell's start stay in 32-bit
+            // integers plus small FP32 parts
+            float x_lo = th_lo * c.cells_per_rad, x_hi = th_hi * c.cells_per_rad;
+            x_hi = x_hi < (float)nc ? x_hi : (float)nc;
+            int jl = (int)x_lo, jh = (int)x_hi;
+            jl = jl > nc - 1 ? nc - 1 : jl;
+            jh = jh > nc - 1 ? nc - 1 : jh;
+            const float fl = x_lo - (float)jl, fh = x_hi - (float)jh;
+            const uint32_t cl = C[jl].x, chh = C[jh].x;
+            const float m_units = M<float>::fma(fh, (float)cell_width(C, nc, jh),
+                                                M<float>::fma(-fl, (float)cell_width(C, nc, jl), (float)(chh - cl)));
+            M_ = m_units * 2.3283064365386963e-10f;
+            const float o = M<float>::fma(m_units, ur, fl * (float)cell_width(C, nc, jl));
+            const float of = floorf(o);
+            uint64_t xi = (uint64_t)cl + (uint64_t)(o > 0.f ? of : 0.f);
+            xi = xi > 0xffffffffull ? 0xffffffffull : xi;
+            const int lo = table_cell_of(C, cg, guide_bits, (uint32_t)xi);
+            const uint2 e = C[lo];
+            const float cells = (float)lo + ((float)((uint32_t)xi - e.x) + (o - of)) * __uint_as_float(e.y);
+            const float rev = cells * c.rev_per_cell;
+            cth = M<float>::cos_rev(rev);
+            sth = M<float>::sin_rev(rev);
+        }
+    } else {
+        Real u_lo, u_hi;
+        if constexpr (sizeof(Real) == 8) {
+            const Real theta0 = ::acos(mu);
+            const Real th_lo = theta0 - c.alpha > 0.0 ? theta0 - c.alpha : 0.0;
+            const Real th_hi = theta0 + c.alpha < PI ? theta0 + c.alpha : PI;
+            u_lo = hg_cdf(c, ::cos(th_hi));
+            u_hi = hg_cdf(c, ::cos(th_lo));
+        } else {
+            // cos(theta0 -+ alpha) = mu cos alpha +- sqrt(1 - mu^2) sin alpha,
+            // cut at 0 and pi
+            const float c_lo = mu >= ca ? 1.0f : M<float>::fma(mu, ca, sm * c.sin_cone);
+            const float c_hi = mu <= -ca ? -1.0f : M<float>::fma(mu, ca, -sm * c.sin_cone);
+            u_lo = hg_cdf(c, c_hi);
+            u_hi = hg_cdf(c, c_lo);
+        }
+        M_ = u_hi - u_lo;
+        hg_angle<Real>(c, M<Real>::fma(M_, ur, u_lo), cth, sth);
+    }
+    const Real den = sm * sth;
+    Real phi_c;
+    if (den <= (sizeof(Real) == 4 ? (Real)1e-30 : (Real)1e-300)) {
+        phi_c = PI;                      // every azimuth gives mu' = mu cos Theta
+    } else {
+        const Real kappa = M<Real>::div(ca - mu * cth, den);
+        phi_c = kappa <= (Real)-1 ? PI : (kappa >= (Real)1 ? (Real)0 : M<Real>::acos(kappa));
+    }
+    Real cphi;
+    if constexpr (sizeof(Real) == 4) cphi = M<float>::cos_rev(phi_c * uphi * 0.159154943091895336f);
+    else cphi = ::cos(phi_c * uphi);
+    Real mu_n = M<Real>::fma(mu, cth, den * cphi);
+    mu_n = mu_n > (Real)1 ? (Real)1 : mu_n;
+    omc = (Real)1.0 - mu_n;
+    if (!(M_ > (Real)0) || phi_c <= (Real)0 || mu_n <= (Real)0) return (Real)0;
+    Real share;
+    if constexpr (sizeof(Real) == 4) share = phi_c * 0.318309886183790672f;
+    else share = phi_c / PI;
+    return M_ * share * M<Real>::exp_neg(M<Real>::div(T, mu_n));
+}
+
 // Event counters: packets, exits and detections are wave-uniform (counted
 // from ballots when the wave retires packets); collisions, surface hits and
 // the absorbed weight (fixed point) are per-lane sums, reduced across the
@@ -330,9 +523,9 @@ __device__ __forceinline__ void flush_acc(LaneAcc& a, WaveAcc& w, uint64_t* tall
 // Occupancy targets: the specialised FP32 kernels fit eight waves per SIMD
 // (64 VGPRs, run as two 1024-thread blocks per CU), the generic FP32 kernel
 // six, the FP64 kernel four.
-template <typename Real, bool LIST, int KIND>
+template <typename Real, bool LIST, int KIND, bool PEEL>
 __global__ void __launch_bounds__(1024)
-__attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? (KIND >= 0 ? 8 : 6) : 4, 8)))
+__attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? (KIND >= 0 && !PEEL ? 8 : 6) : 4, 8)))
 transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ tables,
                  uint64_t* __restrict__ tallies, const WorkItem* __restrict__ items, int n_items,
                  uint32_t* __restrict__ queue, int persistent, int max_layers, int max_cells, int max_bins,
@@ -345,7 +538,7 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
     __shared__ uint32_t s_next;
 
     const LdsLayout L = lds_layout((int)sizeof(Real), max_layers, max_cells, max_bins, guide_bits,
-                                   LIST ? (int)(blockDim.x >> 6) : 0);
+                                   LIST ? (int)(blockDim.x >> 6) : 0, PEEL);
     const int gshift = GUIDE_BITS - guide_bits;
     const int n_guide = 1 << guide_bits;
     using TE = typename Staged<Real>::TE;
@@ -356,6 +549,8 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
     uint16_t* sCG = (uint16_t*)(lds + L.cg_off);
     unsigned long long* sW = (unsigned long long*)(lds + L.hist_off);     // bins, then sink slots
     unsigned long long* sW2 = (unsigned long long*)(lds + L.hist2_off);
+    unsigned long long* sP = (unsigned long long*)(lds + L.peel_off);     // next-event sum(c), sum(c^2)
+    unsigned long long* sP2 = (unsigned long long*)(lds + L.peel2_off);
 
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
@@ -398,6 +593,17 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
             const unsigned long long w = sW[b], w2 = sW2[b];
             if (w) atomicAdd(gW + b, w);
             if (w2) atomicAdd(gW2 + b, w2);
+        }
+        if constexpr (PEEL) {
+            if (d.flags & SF_PEEL) {
+                unsigned long long* gP = (unsigned long long*)(tally + tw_peel(d.n_bins));
+                unsigned long long* gP2 = (unsigned long long*)(tally + tw_peel2(d.n_bins));
+                for (int b = tid; b < d.n_bins; b += nthr) {
+                    const unsigned long long v = sP[b], v2 = sP2[b];
+                    if (v) atomicAdd(gP + b, v);
+                    if (v2) atomicAdd(gP2 + b, v2);
+                }
+            }
         }
         if (tid < N_SINK_SLOTS) {
             const unsigned long long v = sW[d.n_bins + tid];
@@ -462,6 +668,12 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
             }
             for (int i = tid; i < d.n_bins + N_SINK_SLOTS; i += nthr) sW[i] = 0ull;
             for (int i = tid; i < d.n_bins; i += nthr) sW2[i] = 0ull;
+            if constexpr (PEEL) {
+                for (int i = tid; i < d.n_bins; i += nthr) {
+                    sP[i] = 0ull;
+                    sP2[i] = 0ull;
+                }
+            }
             cur_set = set;
             __syncthreads();
         }
@@ -679,6 +891,39 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                 const bool one = surf ? (bool)c.surface_one : (bool)c.albedo_one;
                 absorbed = !leave && !trunc && !one && X.w >= thr;
             }
+            // next-event estimate of this scattering or reflection, from the
+            // state before the event's updates
+            if constexpr (PEEL) {
+                if ((c.flags & SF_PEEL) && (surf || (coll && !trunc))) {
+                    uint32_t key0 = c.k0, key1 = c.k1;
+                    asm volatile("" : "+s"(key0), "+s"(key1));
+                    const Block4 Q = philox10_event((k - 1u) | 0x80000000u, q0, q1, c.stream ^ key1, key0, key1);
+                    const Real sm = M<Real>::sqrt(sm2 > (Real)0 ? sm2 : (Real)0);
+                    Real omc_p;
+                    const Real wt = peel_weight<Real, KIND>(c, sC, sCG, guide_bits, surf, mu, sm, Tn,
+                                                            unit_open<Real>(Q.x), unit_open<Real>(Q.y), omc_p);
+                    const Real sc = w * a * wt;
+                    const uint64_t fc = to_fixed32<Real>(sc);
+                    if (fc != 0ull) {
+                        const Real big_p = M<Real>::fma((Real)0.5 * V, (Real)1.0 - mu, big);
+                        const Real small_p = M<Real>::fma((Real)0.5 * V, omc_p, small);
+                        const double vp = (double)big_p - (double)small_p;
+                        double bf;
+                        if constexpr (sizeof(Real) == 8) bf = floor((vp - c.v_lo) / c.dv);
+                        else bf = floor((vp - c.v_lo) * c.inv_dv);
+                        if (bf < 0.0) {
+                            atomicAdd(&sW[nb + SK_PEEL_UNDER], (unsigned long long)fc);
+                        } else if (bf >= (double)nb) {
+                            atomicAdd(&sW[nb + SK_PEEL_OVER], (unsigned long long)fc);
+                        } else {
+                            const int b = (int)bf;
+                            atomicAdd(&sP[b], (unsigned long long)fc);
+                            const uint64_t fc2 = to_fixed32<Real>(sc * sc);
+                            if (fc2 != 0ull) atomicAdd(&sP2[b], (unsigned long long)fc2);
+                        }
+                    }
+                }
+            }
             // the event counts as a collision or surface hit whether or not
             // the packet continues
             n_surf += surf ? 1 : 0;
@@ -717,41 +962,61 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
 // kind, with the compiler's usual contraction.
 namespace pdv {
 
-template <typename Real, bool LIST, int KIND>
+template <typename Real, bool LIST, int KIND, bool PEEL>
 static const void* kernel_ptr() {
-    return reinterpret_cast<const void*>(&transport_kernel<Real, LIST, KIND>);
+    return reinterpret_cast<const void*>(&transport_kernel<Real, LIST, KIND, PEEL>);
 }
 
-template <typename Real, bool LIST, int KIND>
+template <typename Real, bool LIST, int KIND, bool PEEL>
 static hipError_t launch_kind(hipStream_t s, const TransportShape& sh, const SetDesc* descs, const uint8_t* tables,
                               uint64_t* tallies, const WorkItem* items, int n_items, const int* n_items_dev,
                               uint32_t* queue, int persistent, ListEntry* lists, uint64_t* list_counts) {
-    hipLaunchKernelGGL((transport_kernel<Real, LIST, KIND>), dim3(sh.grid), dim3(sh.block), sh.lds_bytes, s, descs,
-                       tables, tallies, items, n_items, queue, persistent, sh.max_layers, sh.max_cells, sh.max_bins,
-                       lists, list_counts, n_items_dev, sh.guide_bits, sh.retire_min);
+    hipLaunchKernelGGL((transport_kernel<Real, LIST, KIND, PEEL>), dim3(sh.grid), dim3(sh.block), sh.lds_bytes, s,
+                       descs, tables, tallies, items, n_items, queue, persistent, sh.max_layers, sh.max_cells,
+                       sh.max_bins, lists, list_counts, n_items_dev, sh.guide_bits, sh.retire_min);
     return hipGetLastError();
+}
+
+// Kernels of one precision and kind: with or without detected lists, with
+// or without the next-event estimate (lists and the estimate are not
+// combined).
+template <typename Real, int KIND>
+static const void* kind_ptr(bool list, bool peel) {
+    if (list) return kernel_ptr<Real, true, KIND, false>();
+    return peel ? kernel_ptr<Real, false, KIND, true>() : kernel_ptr<Real, false, KIND, false>();
+}
+
+template <typename Real, int KIND>
+static hipError_t launch_of_kind(hipStream_t s, bool list, const TransportShape& sh, const SetDesc* descs,
+                                 const uint8_t* tables, uint64_t* tallies, const WorkItem* items, int n_items,
+                                 const int* n_items_dev, uint32_t* queue, int persistent, ListEntry* lists,
+                                 uint64_t* list_counts) {
+    if (list)
+        return launch_kind<Real, true, KIND, false>(s, sh, descs, tables, tallies, items, n_items, n_items_dev, queue,
+                                                    persistent, lists, list_counts);
+    if (sh.peel)
+        return launch_kind<Real, false, KIND, true>(s, sh, descs, tables, tallies, items, n_items, n_items_dev,
+                                                    queue, persistent, lists, list_counts);
+    return launch_kind<Real, false, KIND, false>(s, sh, descs, tables, tallies, items, n_items, n_items_dev, queue,
+                                                 persistent, lists, list_counts);
 }
 
 #if defined(PDV_TRANSPORT_FP64)
 
-const void* select_kernel_fp64(bool list) {
-    return list ? kernel_ptr<double, true, KIND_GENERIC>() : kernel_ptr<double, false, KIND_GENERIC>();
-}
+const void* select_kernel_fp64(bool list, bool peel) { return kind_ptr<double, KIND_GENERIC>(list, peel); }
 
 hipError_t launch_transport_fp64(hipStream_t s, bool list, const TransportShape& sh, const SetDesc* descs,
                                  const uint8_t* tables, uint64_t* tallies, const WorkItem* items, int n_items,
                                  const int* n_items_dev, uint32_t* queue, int persistent, ListEntry* lists,
                                  uint64_t* list_counts) {
-    return list ? launch_kind<double, true, KIND_GENERIC>(s, sh, descs, tables, tallies, items, n_items, n_items_dev,
-                                                          queue, persistent, lists, list_counts)
-                : launch_kind<double, false, KIND_GENERIC>(s, sh, descs, tables, tallies, items, n_items,
-                                                           n_items_dev, queue, persistent, lists, list_counts);
+    return launch_of_kind<double, KIND_GENERIC>(s, list, sh, descs, tables, tallies, items, n_items, n_items_dev,
+                                                queue, persistent, lists, list_counts);
 }
 
 #else
 
 // FP64 kernels (the other compilation pass)
-const void* select_kernel_fp64(bool list);
+const void* select_kernel_fp64(bool list, bool peel);
 hipError_t launch_transport_fp64(hipStream_t s, bool list, const TransportShape& sh, const SetDesc* descs,
                                  const uint8_t* tables, uint64_t* tallies, const WorkItem* items, int n_items,
                                  const int* n_items_dev, uint32_t* queue, int persistent, ListEntry* lists,
@@ -759,13 +1024,11 @@ hipError_t launch_transport_fp64(hipStream_t s, bool list, const TransportShape&
 
 // FP32 launches of one specialised kind get their own kernel; FP64 (the
 // plain baseline) always runs the generic one.
-static const void* select_kernel(int precision, bool list, int kind) {
-    if (precision == 1) return select_kernel_fp64(list);
-    if (kind == KIND_TABLE_LAYERED)
-        return list ? kernel_ptr<float, true, KIND_TABLE_LAYERED>() : kernel_ptr<float, false, KIND_TABLE_LAYERED>();
-    if (kind == KIND_HG_UNIFORM)
-        return list ? kernel_ptr<float, true, KIND_HG_UNIFORM>() : kernel_ptr<float, false, KIND_HG_UNIFORM>();
-    return list ? kernel_ptr<float, true, KIND_GENERIC>() : kernel_ptr<float, false, KIND_GENERIC>();
+static const void* select_kernel(int precision, bool list, int kind, bool peel) {
+    if (precision == 1) return select_kernel_fp64(list, peel);
+    if (kind == KIND_TABLE_LAYERED) return kind_ptr<float, KIND_TABLE_LAYERED>(list, peel);
+    if (kind == KIND_HG_UNIFORM) return kind_ptr<float, KIND_HG_UNIFORM>(list, peel);
+    return kind_ptr<float, KIND_GENERIC>(list, peel);
 }
 
 static hipError_t allow_lds(const void* k, int bytes) {
@@ -779,20 +1042,23 @@ static hipError_t allow_lds(const void* k, int bytes) {
 // [MIN_GUIDE_BITS, GUIDE_BITS] forces the resolution; 0 takes the finest
 // whose staging lets as many blocks share a CU's LDS as the kernel's
 // registers allow.  Fails with hipErrorInvalidValue when even the coarsest
-// guide exceeds the per-block LDS limit.
+// guide exceeds the per-block LDS limit, or when a next-event launch asks
+// for detected lists.
 hipError_t plan_transport(TransportShape& sh, int precision, bool list, int want_bits, int lds_per_block,
                           int lds_per_cu) {
+    if (list && sh.peel) return hipErrorInvalidValue;
     const int rb = precision == 1 ? 8 : 4;
+    const void* kp = select_kernel(precision, list, sh.kind, sh.peel);
     auto bytes = [&](int bits) {
-        return (int)lds_layout(rb, sh.max_layers, sh.max_cells, sh.max_bins, bits, list ? sh.block / 64 : 0).bytes;
+        return (int)lds_layout(rb, sh.max_layers, sh.max_cells, sh.max_bins, bits, list ? sh.block / 64 : 0, sh.peel)
+            .bytes;
     };
     if (want_bits != 0) {
         if (want_bits < MIN_GUIDE_BITS || want_bits > GUIDE_BITS) return hipErrorInvalidValue;
         sh.guide_bits = want_bits;
     } else {
         int resident = 1;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, select_kernel(precision, list, sh.kind),
-                                                                    sh.block, 0);
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kp, sh.block, 0);
         if (e != hipSuccess) return e;
         if (resident < 1) resident = 1;
         const int budget = std::min(lds_per_block, lds_per_cu / resident);
@@ -802,21 +1068,21 @@ hipError_t plan_transport(TransportShape& sh, int precision, bool list, int want
     }
     sh.lds_bytes = bytes(sh.guide_bits);
     if (sh.lds_bytes > lds_per_block) return hipErrorInvalidValue;
-    return allow_lds(select_kernel(precision, list, sh.kind), sh.lds_bytes);
+    return allow_lds(kp, sh.lds_bytes);
 }
 
-template <bool LIST>
-static hipError_t launch_fp32(hipStream_t s, const TransportShape& sh, const SetDesc* descs, const uint8_t* tables,
-                              uint64_t* tallies, const WorkItem* items, int n_items, const int* n_items_dev,
-                              uint32_t* queue, int persistent, ListEntry* lists, uint64_t* list_counts) {
+static hipError_t launch_fp32(hipStream_t s, bool list, const TransportShape& sh, const SetDesc* descs,
+                              const uint8_t* tables, uint64_t* tallies, const WorkItem* items, int n_items,
+                              const int* n_items_dev, uint32_t* queue, int persistent, ListEntry* lists,
+                              uint64_t* list_counts) {
     if (sh.kind == KIND_TABLE_LAYERED)
-        return launch_kind<float, LIST, KIND_TABLE_LAYERED>(s, sh, descs, tables, tallies, items, n_items,
-                                                            n_items_dev, queue, persistent, lists, list_counts);
+        return launch_of_kind<float, KIND_TABLE_LAYERED>(s, list, sh, descs, tables, tallies, items, n_items,
+                                                         n_items_dev, queue, persistent, lists, list_counts);
     if (sh.kind == KIND_HG_UNIFORM)
-        return launch_kind<float, LIST, KIND_HG_UNIFORM>(s, sh, descs, tables, tallies, items, n_items, n_items_dev,
-                                                         queue, persistent, lists, list_counts);
-    return launch_kind<float, LIST, KIND_GENERIC>(s, sh, descs, tables, tallies, items, n_items, n_items_dev, queue,
-                                                  persistent, lists, list_counts);
+        return launch_of_kind<float, KIND_HG_UNIFORM>(s, list, sh, descs, tables, tallies, items, n_items,
+                                                      n_items_dev, queue, persistent, lists, list_counts);
+    return launch_of_kind<float, KIND_GENERIC>(s, list, sh, descs, tables, tallies, items, n_items, n_items_dev,
+                                               queue, persistent, lists, list_counts);
 }
 
 // Persistent launch whose item count is read from device memory, so a
@@ -827,7 +1093,7 @@ hipError_t launch_transport_dev(hipStream_t s, int precision, const TransportSha
     if (precision == 1)
         return launch_transport_fp64(s, false, sh, descs, tables, tallies, items, 0, n_items_dev, queue, 1, nullptr,
                                      nullptr);
-    return launch_fp32<false>(s, sh, descs, tables, tallies, items, 0, n_items_dev, queue, 1, nullptr, nullptr);
+    return launch_fp32(s, false, sh, descs, tables, tallies, items, 0, n_items_dev, queue, 1, nullptr, nullptr);
 }
 
 // n_items_dev (nullable): read the item count from device memory instead of
@@ -839,10 +1105,8 @@ hipError_t launch_transport(hipStream_t s, int precision, bool list, const Trans
     if (precision == 1)
         return launch_transport_fp64(s, list, sh, descs, tables, tallies, items, n_items, n_items_dev, queue,
                                      persistent, lists, list_counts);
-    return list ? launch_fp32<true>(s, sh, descs, tables, tallies, items, n_items, n_items_dev, queue, persistent,
-                                    lists, list_counts)
-                : launch_fp32<false>(s, sh, descs, tables, tallies, items, n_items, n_items_dev, queue, persistent,
-                                     lists, list_counts);
+    return launch_fp32(s, list, sh, descs, tables, tallies, items, n_items, n_items_dev, queue, persistent, lists,
+                       list_counts);
 }
 
 #endif  // PDV_TRANSPORT_FP64

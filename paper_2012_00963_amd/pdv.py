@@ -26,6 +26,7 @@ SINK_NAMES = ("under", "over", "undetected", "absorbed_particle", "absorbed_surf
 FP32, FP64 = 0, 1
 FLAG_CLASS_TALLIES = 1
 FLAG_DEVICE_OUTPUT = 2
+FLAG_PEEL = 4
 SCALE = 4294967296.0
 
 
@@ -72,6 +73,7 @@ class SpectrumOut(ctypes.Structure):
         ("sinks_fx", ctypes.c_uint64 * 6),
         ("counters", Counters),
         ("albedo", ctypes.c_double), ("g", ctypes.c_double),
+        ("peel_fx", ctypes.c_void_p), ("peel_sinks_fx", ctypes.c_uint64 * 2),
     ]
 
 
@@ -214,6 +216,10 @@ class Result(dict):
         elif key in ("W_single", "W_surface") and self.get("_class") is not None:
             C, nb = self["_class"]
             v = (C[:nb] if key == "W_single" else C[nb:]).astype(np.float64) / SCALE
+        elif key in ("P", "P2") and self.get("peel_fx") is not None:
+            nb = len(self["w_fx"])
+            Pf = self["peel_fx"]
+            v = (Pf[:nb] if key == "P" else Pf[nb:]).astype(np.float64) / SCALE
         else:
             raise KeyError(key)
         self[key] = v
@@ -223,7 +229,7 @@ class Result(dict):
 COUNTER_NAMES = tuple(n for n, _ in Counters._fields_)
 
 
-def _result(out: SpectrumOut, W, W2, C, n_bins):
+def _result(out: SpectrumOut, W, W2, C, n_bins, Pf=None):
     sinks_fx = dict(zip(SINK_NAMES, out.sinks_fx))
     cnt = out.counters
     res = Result(
@@ -235,6 +241,9 @@ def _result(out: SpectrumOut, W, W2, C, n_bins):
     res["sinks"]["detected"] = int(W.sum()) / SCALE     # exact: the bins sum below 2^64
     if C is not None:
         res["_class"] = (C, n_bins)
+    if Pf is not None:
+        res["peel_fx"] = Pf
+        res["peel_sinks"] = {"under": out.peel_sinks_fx[0] / SCALE, "over": out.peel_sinks_fx[1] / SCALE}
     return res
 
 
@@ -317,17 +326,21 @@ class Context:
                         "albedo": outs[i].albedo, "g": outs[i].g})
         return res
 
-    def spectrum(self, p: dict, class_tallies: bool = False) -> dict:
-        return self.spectrum_batch([p], class_tallies=class_tallies)[0]
+    def spectrum(self, p: dict, class_tallies: bool = False, peel: bool = False) -> dict:
+        return self.spectrum_batch([p], class_tallies=class_tallies, peel=peel)[0]
 
-    def spectrum_batch(self, sets: list, opts: dict | None = None, class_tallies: bool = False) -> list:
+    def spectrum_batch(self, sets: list, opts: dict | None = None, class_tallies: bool = False,
+                       peel: bool = False) -> list:
+        """Spectra of a batch (one persistent launch).  peel: also the
+        next-event estimate of the detector tally (result keys peel_fx,
+        P, P2, peel_sinks) for every set."""
         keep = []
         n = len(sets)
         arr = (Params * n)()
         outs = (SpectrumOut * n)()
         # every set's tallies are disjoint views of one buffer, which the
         # library fills completely on success
-        per = 4 if class_tallies else 2
+        per = (4 if class_tallies else 2) + (2 if peel else 0)
         nbs = [int(p.get("n_bins", DEFAULTS["n_bins"])) for p in sets]
         buf = np.empty(per * sum(nbs), dtype=np.uint64)
         base = buf.ctypes.data
@@ -336,6 +349,8 @@ class Context:
         for i, p in enumerate(sets):
             if class_tallies:
                 p = dict(p, flags=int(p.get("flags", 0)) | FLAG_CLASS_TALLIES)
+            if peel:
+                p = dict(p, flags=int(p.get("flags", 0)) | FLAG_PEEL)
             arr[i] = make_params(p, keep)
             nb = nbs[i]
             o = outs[i]
@@ -345,7 +360,12 @@ class Context:
             if class_tallies:
                 o.class_fx = base + 8 * (off + 2 * nb)
                 C = buf[off + 2 * nb:off + 4 * nb]
-            bufs.append((buf[off:off + nb], buf[off + nb:off + 2 * nb], C, nb))
+            Pf = None
+            if peel:
+                q = off + (4 if class_tallies else 2) * nb
+                o.peel_fx = base + 8 * q
+                Pf = buf[q:q + 2 * nb]
+            bufs.append((buf[off:off + nb], buf[off + nb:off + 2 * nb], C, nb, Pf))
             off += per * nb
         o = None
         if opts:

@@ -38,7 +38,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version_and_no_device(lib):
-    assert lib.pdv_abi_version() == 1
+    assert lib.pdv_abi_version() == 2
     n = ctypes.c_int(-1)
     rc = lib.pdv_device_count(ctypes.byref(n))
     if rc == 0 and n.value > 0:
