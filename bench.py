@@ -126,9 +126,16 @@ def run_calib_copy(nbytes: int):
     print(json.dumps({"calib_copy_bytes_each_way": n * 4, "launches": 3}))
 
 
-def batched_leg(ctx):
+def oracle_threads():
+    return os.cpu_count() or 1
+
+
+def batched_leg(ctx, check_oracle=True):
     """512 uneven Mie sets: one FP32 persistent launch against serial
-    per-set FP64 ("plain") launches, with the per-set FP32 error."""
+    per-set FP64 ("plain") launches, with the per-set FP32 error against the
+    FP64 launches and, for a stated sample of 16 sets (the largest optical
+    depth, median diameter and packet count, the smallest packet count and
+    12 drawn with PCG64(40)), against the FP64 oracle on the same streams."""
     import numpy as np
     import torch
     from paper_2012_00963_amd import workloads
@@ -159,6 +166,30 @@ def batched_leg(ctx):
     errs = [l1_err(a["W"], b["W"]) for a, b in zip(r32, r64) if b["W"].sum() > 0]
     tot = [abs(a["W"].sum() - b["W"].sum()) / b["W"].sum() for a, b in zip(r32, r64) if b["W"].sum() > 0]
     ev32 = sum(r["counts"]["collisions"] + r["counts"]["surface"] for r in r32)
+    conserved = all(int(np.sum(r["w_fx"], dtype=np.uint64)) + sum(r["sinks_fx"].values()) == s["n_packets"] * 2**32
+                    for r, s in zip(r32, sets))
+    vs_oracle = None
+    if check_oracle:
+        from oracle import mc
+        pick = {int(np.argmax([s["tau_total"] for s in sets])), int(np.argmax([s["d_median"] for s in sets])),
+                int(np.argmax([s["n_packets"] for s in sets])), int(np.argmin([s["n_packets"] for s in sets]))}
+        rng = np.random.Generator(np.random.PCG64(40))
+        for i in rng.permutation(len(sets)):
+            if len(pick) >= 16:
+                break
+            pick.add(int(i))
+        rows = []
+        tc0 = time.perf_counter()
+        for i in sorted(pick):
+            o = mc.run(s32[i], n_threads=oracle_threads())
+            e = err_vs_oracle(r32[i], o, sets[i]["n_packets"])
+            rows.append(dict(set=i, tau=round(sets[i]["tau_total"], 3), d_median_um=round(sets[i]["d_median"] * 1e6, 2),
+                             packets=int(sets[i]["n_packets"]), **{k: float("%.3g" % v) for k, v in e.items()}))
+        vs_oracle = {"sample": "16 sets: largest tau, d_median and packet count, smallest packet count, 12 more "
+                               "drawn with PCG64(40); each at its full packet count, same streams",
+                     "oracle_s": time.perf_counter() - tc0,
+                     "max_total_rel": max(r["total_rel"] for r in rows), "max_z": max(r["z_max"] for r in rows),
+                     "max_l1": max(r["l1"] for r in rows), "per_set": rows}
     return {
         "_spectra": [r["W"] / max(s["n_packets"], 1) for r, s in zip(r32, sets)],
         "sets": len(sets),
@@ -179,6 +210,8 @@ def batched_leg(ctx):
         "max_l1_fp32_vs_fp64": float(max(errs)),
         "median_l1_fp32_vs_fp64": float(np.median(errs)),
         "max_total_rel_fp32_vs_fp64": float(max(tot)),
+        "conservation_exact_all_sets": bool(conserved),
+        "fp32_vs_oracle": vs_oracle,
     }
 
 
@@ -290,9 +323,14 @@ def peel_leg(ctx, check_oracle=True):
     return out
 
 
-def spectrogram_leg(ctx):
+def spectrogram_leg(ctx, check_oracle=True):
     """Time-resolved case: 256 frames x 1e6 packets, 20 GS/s beat record of
-    1e5 samples with FP64 phase, 4096-point Hann STFT at 80% overlap."""
+    1e5 samples with FP64 phase, 4096-point Hann STFT at 80% overlap.  Two
+    full-size frames (0 and 128) against the FP64 oracle on the same streams:
+    their detected lists (count, total weight, entries matched by phase word
+    and their largest velocity difference) and their samples of the record
+    against the oracle's FP64 synthesis from the oracle's lists."""
+    import numpy as np
     import torch
     from paper_2012_00963_amd import workloads
     p, sg = workloads.spectrogram_case()
@@ -302,24 +340,51 @@ def spectrogram_leg(ctx):
     g = ctx.spectrogram(p, sg)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    return {
+    out = {
         "frames": sg["n_frames"], "packets_per_frame": sg["packets_per_frame"],
         "seconds": t1 - t0, "spectrograms_per_s": 1.0 / (t1 - t0),
         "packets_per_s": sg["n_frames"] * sg["packets_per_frame"] / (t1 - t0),
         "detected_entries": int(g["frame_counts"].sum()), "windows": g["n_windows"],
         "overflow": g["overflow"],
     }
+    if check_oracle:
+        from oracle import mc, stage2
+        gl = ctx.spectrogram(p, sg, want_signal=True, want_lists=True)   # the same record, with its lists
+        tabs = mc.set_tables(p)
+        frames = (0, 128)
+        lists_o = [{"w": np.zeros(0), "v": np.zeros(0), "phase": np.zeros(0)} for _ in range(sg["n_frames"])]
+        rows = []
+        b = stage2.frame_bounds(sg["n_samples"], sg["n_frames"])
+        for k in frames:
+            pk = dict(p, stream=p["stream"] + k, n_packets=sg["packets_per_frame"])
+            o = mc.run(pk, tabs=tabs, list_capacity=sg["list_capacity"], n_threads=oracle_threads())
+            Lo, Lg = o["list"], gl["lists"][k]
+            lists_o[k] = Lo
+            po = {int(x): i for i, x in enumerate(np.round(Lo["phase"] * 2**32).astype(np.uint64))}
+            matched, dv_max = 0, 0.0
+            for j, ph in enumerate(Lg["phase_u32"]):
+                i = po.get(int(ph))
+                if i is not None:
+                    matched += 1
+                    dv_max = max(dv_max, abs(float(Lg["v"][j]) - float(Lo["v"][i])))
+            rows.append({"frame": k, "entries_gpu": int(len(Lg["w"])), "entries_oracle": int(len(Lo["w"])),
+                         "matched": matched, "weight_rel": float(abs(Lg["w"].astype(np.float64).sum() - Lo["w"].sum())
+                                                                 / Lo["w"].sum()),
+                         "max_dv_m_per_s": dv_max})
+        so = stage2.beat_signal(lists_o, sg["n_samples"], sg["fs"], p["wavelength"])
+        for r, k in zip(rows, frames):
+            a, c = gl["signal"][b[k]:b[k + 1]].astype(np.float64), so[b[k]:b[k + 1]]
+            r["signal_rel_l2"] = float(np.linalg.norm(a - c) / np.linalg.norm(c))
+        out["vs_oracle"] = {"sample": "frames 0 and 128 (1e6 packets each, same streams): lists and their "
+                                      "samples of the record", "frames": rows}
+    return out
 
 
-def serve_leg(ctx, duration=60.0):
-    """Poisson arrivals (200/s) of uneven Mie requests, a quarter with a
-    64-frame spectrogram, served with continuous batching (FP32, graph
-    replays), against the same trace replayed with serial per-request plain
-    FP64 launches.  Latency = arrival -> result on the host."""
-    import numpy as np
-    from paper_2012_00963_amd import pdv, workloads
-    trace = workloads.serving_trace(duration=duration)
-    ctx.spectrum(dict(trace[0]["params"], n_packets=1000))     # resident Mie basis
+def _serve_open_loop(ctx, trace, keep_results=False):
+    """Submit the trace's requests at their arrival times to a serving
+    session (FP32, continuous batching, graph replays); returns the codes,
+    the session statistics, the wall time and (optionally) the results."""
+    from paper_2012_00963_amd import pdv
     srv = pdv.Server(ctx, max_active=256, use_graph=1)
     t0 = time.perf_counter()
     tks = []
@@ -331,8 +396,42 @@ def serve_leg(ctx, duration=60.0):
     codes = [srv.poll(tk, wait_ms=-1) for tk in tks]
     t1 = time.perf_counter()
     st = srv.stats()
+    res = [tk.result() for tk in tks] if keep_results else None
     srv.stop()
-    ok = sum(1 for c in codes if c in (0, -4))
+    return codes, st, t1 - t0, res
+
+
+def _fp64_request(ctx, r):
+    p64 = dict(r["params"], precision=1)
+    ctx.spectrum(p64)
+    if r["spectrogram"] is not None:
+        sg = dict(r["spectrogram"])
+        sg.setdefault("list_capacity", max(4096, sg["packets_per_frame"] // 10))
+        ctx.spectrogram(p64, sg)
+
+
+def serve_leg(ctx, duration=60.0, check_oracle=True):
+    """Serving (spec pattern): Poisson arrivals of uneven Mie requests,
+    a quarter with a 64-frame spectrogram.
+      trace rate (200/s, `duration` s): served FP32 with continuous batching
+        against the same trace replayed as serial per-request plain FP64
+        launches; latency = arrival -> result on the host;
+      capacity (closed loop): the first 2000 requests of the trace submitted
+        at once to the server, and run back to back as serial FP64 launches:
+        sustained spectra/s of each;
+      rate sweep: served FP32 at 1000, 2500 and 5000 requests/s (open loop,
+        2000 requests each): sustained rate and p50/p99;
+      error: 50 sampled requests of the trace-rate run against the FP64
+        oracle on the same streams.
+    Requests ending in PDV_EOVERFLOW (a spectrogram list truncated at its
+    capacity; the spectrum itself is complete) are counted apart."""
+    import numpy as np
+    from paper_2012_00963_amd import workloads
+    trace = workloads.serving_trace(duration=duration)
+    ctx.spectrum(dict(trace[0]["params"], n_packets=1000))     # resident Mie basis
+    codes, st, wall, results = _serve_open_loop(ctx, trace, keep_results=check_oracle)
+    ok = sum(1 for c in codes if c == 0)
+    overflow = sum(1 for c in codes if c == -4)
     # serial plain FP64 replay of the same trace
     lat = []
     t2 = time.perf_counter()
@@ -342,25 +441,22 @@ def serve_leg(ctx, duration=60.0):
         dt = arr - time.perf_counter()
         if dt > 0:
             time.sleep(dt)
-        p64 = dict(r["params"], precision=1)
-        ctx.spectrum(p64)
-        if r["spectrogram"] is not None:
-            sg = dict(r["spectrogram"])
-            sg.setdefault("list_capacity", max(4096, sg["packets_per_frame"] // 10))
-            ctx.spectrogram(p64, sg)
+        _fp64_request(ctx, r)
         lat.append((time.perf_counter() - arr) * 1e3)
         n_done += 1
         if time.perf_counter() - t2 > 3 * duration:
             break
     t3 = time.perf_counter()
     lat = np.array(lat)
-    return {
-        "requests": len(trace), "served_ok": ok, "spectrogram_requests": sum(r["spectrogram"] is not None for r in trace),
+    out = {
+        "requests": len(trace), "served_ok": ok, "served_list_overflow": overflow,
+        "served_failed": len(codes) - ok - overflow,
+        "spectrogram_requests": sum(r["spectrogram"] is not None for r in trace),
         "duration_s": duration,
-        "served_wall_s": t1 - t0, "served_spectra_per_s": ok / (t1 - t0),
+        "served_wall_s": wall, "served_spectra_per_s": (ok + overflow) / wall,
         "served_p50_ms": st["p50_ms"], "served_p99_ms": st["p99_ms"], "served_max_ms": st["max_ms"],
-        "served_iterations": st["iterations"], "served_events_per_s": st["events"] / (t1 - t0),
-        "served_busy_fraction": st["busy_s"] / (t1 - t0),
+        "served_iterations": st["iterations"], "served_events_per_s": st["events"] / wall,
+        "served_busy_fraction": st["busy_s"] / wall,
         "served_queue_p50_ms": st["queue_p50_ms"],
         "scheduler_s": {"tables": st["prepare_s"], "launch_and_wait": st["launch_s"],
                         "result_copies": st["collect_s"], "spectrogram_worker": st["spectrogram_s"]},
@@ -368,6 +464,44 @@ def serve_leg(ctx, duration=60.0):
         "fp64_serial_spectra_per_s": n_done / (t3 - t2),
         "fp64_serial_p50_ms": float(np.percentile(lat, 50)), "fp64_serial_p99_ms": float(np.percentile(lat, 99)),
     }
+    # closed-loop capacity on the first 2000 requests
+    head = [dict(r, arrival=0.0) for r in trace[:2000]]
+    c_codes, c_st, c_wall, _ = _serve_open_loop(ctx, head)
+    t4 = time.perf_counter()
+    for r in head:
+        _fp64_request(ctx, r)
+    t5 = time.perf_counter()
+    out["capacity"] = {"requests": len(head), "served_fp32_spectra_per_s": len(head) / c_wall,
+                       "served_ok_or_overflow": sum(1 for c in c_codes if c in (0, -4)),
+                       "fp64_serial_spectra_per_s": len(head) / (t5 - t4),
+                       "speedup": (t5 - t4) / c_wall,
+                       "served_events_per_s": c_st["events"] / c_wall}
+    # open-loop rate sweep of the served path
+    sweep = []
+    for rate in (1000.0, 2500.0, 5000.0):
+        tr = workloads.serving_trace(rate=rate, duration=2000.0 / rate, seed=7)
+        s_codes, s_st, s_wall, _ = _serve_open_loop(ctx, tr)
+        sweep.append({"rate": rate, "requests": len(tr), "spectra_per_s": len(tr) / s_wall,
+                      "ok": sum(1 for c in s_codes if c == 0), "overflow": sum(1 for c in s_codes if c == -4),
+                      "p50_ms": s_st["p50_ms"], "p99_ms": s_st["p99_ms"], "busy_fraction": s_st["busy_s"] / s_wall})
+    out["served_rate_sweep"] = sweep
+    out["fp64_serial_falls_behind_above_per_s"] = out["capacity"]["fp64_serial_spectra_per_s"]
+    if check_oracle:
+        from oracle import mc
+        rng = np.random.Generator(np.random.PCG64(50))
+        pick = sorted(int(i) for i in rng.choice(len(trace), size=50, replace=False))
+        rows = []
+        tc0 = time.perf_counter()
+        for i in pick:
+            pr = trace[i]["params"]
+            o = mc.run(pr, n_threads=oracle_threads())
+            rows.append(err_vs_oracle(results[i], o, pr["n_packets"]))
+        out["vs_oracle"] = {"sample": "50 requests drawn with PCG64(50) from the trace-rate run (their spectra), "
+                                      "same streams", "oracle_s": time.perf_counter() - tc0,
+                            "max_total_rel": max(r["total_rel"] for r in rows),
+                            "max_z": max(r["z_max"] for r in rows), "max_l1": max(r["l1"] for r in rows),
+                            "median_l1": float(np.median([r["l1"] for r in rows]))}
+    return out
 
 
 def main(argv=None):
@@ -379,7 +513,8 @@ def main(argv=None):
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--legs", default="batched,peaks,sensitivity,peel,spectrogram,serve",
                     help="comma list of extra legs: batched,peaks,sensitivity,peel,spectrogram,serve (or none)")
-    ap.add_argument("--cpu-sample", type=int, default=20_000_000, help="packets in the oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="packets of the oracle run (0 = the whole workload)")
     ap.add_argument("--calib-copy", type=int, default=0, help="only run a copy of this many bytes")
     ap.add_argument("--serve-duration", type=float, default=60.0, help="seconds of the serving trace")
     ap.add_argument("--serve-only", action="store_true",
@@ -488,37 +623,52 @@ def main(argv=None):
 
     legs = [x for x in args.legs.split(",") if x and x != "none"]
     spectra_512 = None
+    check = not args.no_cpu
     if "batched" in legs:
-        out["extra"]["batched"] = batched_leg(ctx)
+        out["extra"]["batched"] = batched_leg(ctx, check_oracle=check)
         spectra_512 = out["extra"]["batched"].pop("_spectra")
     if "peaks" in legs:
         out["extra"]["peaks"] = peaks_leg(ctx, spectra_512)
     if "sensitivity" in legs:
         out["extra"]["sensitivity"] = sensitivity_leg(ctx)
     if "peel" in legs:
-        out["extra"]["peel"] = peel_leg(ctx, check_oracle=not args.no_cpu)
+        out["extra"]["peel"] = peel_leg(ctx, check_oracle=check)
     if "spectrogram" in legs:
-        out["extra"]["spectrogram"] = spectrogram_leg(ctx)
+        out["extra"]["spectrogram"] = spectrogram_leg(ctx, check_oracle=check)
     if "serve" in legs:
-        out["extra"]["serve"] = serve_leg(ctx, args.serve_duration)
+        out["extra"]["serve"] = serve_leg(ctx, args.serve_duration, check_oracle=check)
 
     if not args.no_cpu:
         from oracle import mc
-        sample = dict(p, n_packets=args.cpu_sample)
+        n_cpu = args.cpu_sample if 0 < args.cpu_sample < n_packets else n_packets
+        sample = dict(p, n_packets=n_cpu)
         tabs = mc.set_tables(sample)
-        threads = os.cpu_count() or 1
+        threads = oracle_threads()
         tc0 = time.perf_counter()
         ro = mc.run(sample, tabs=tabs, n_threads=threads)
         tc1 = time.perf_counter()
         ev = ro["counts"]["collisions"] + ro["counts"]["surface"]
+        what = "all %d packets of the workload" % n_packets if n_cpu == n_packets else \
+            "the first %d packets of the workload" % n_cpu
         out["cpu_baseline"] = {
             "value": ev / (tc1 - tc0),
             "unit": "scatter events/s",
             "cores": threads,
             "kind": "oracle",
-            "sample": f"first {args.cpu_sample} packets of the same workload (FP64 scalar C++ oracle, "
-                      f"{threads} threads, tables built beforehand), {tc1 - tc0:.2f} s",
+            "sample": f"{what} (FP64 scalar C++ oracle, {threads} threads, tables built beforehand), "
+                      f"{tc1 - tc0:.2f} s",
         }
+        # the GPU results of the same packets and streams against the oracle
+        g32 = res if n_cpu == n_packets else ctx.spectrum(sample)
+        ev_g = g32["counts"]["collisions"] + g32["counts"]["surface"]
+        vs = {"sample": what + ", same streams", "fp32": err_vs_oracle(g32, ro, n_cpu),
+              "fp32_conservation_exact": bool(
+                  int(np.sum(g32["w_fx"], dtype=np.uint64)) + sum(g32["sinks_fx"].values()) == n_cpu * 2**32),
+              "fp32_events_rel": abs(ev_g - ev) / ev}
+        if not args.no_fp64:
+            g64 = r64 if n_cpu == n_packets else ctx.spectrum(dict(sample, precision=1))
+            vs["fp64"] = err_vs_oracle(g64, ro, n_cpu)
+        out["extra"]["vs_oracle"] = vs
     ctx.close()
     print(json.dumps(out))
     return 0
