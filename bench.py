@@ -504,6 +504,38 @@ def serve_leg(ctx, duration=60.0, check_oracle=True):
     return out
 
 
+def profile_case(ctx, case, steps, warmup):
+    """One workload launched warmup + steps times, with the transport kernel
+    time of each step (HIP events on the library stream) on one JSON line."""
+    import numpy as np
+    import torch
+    from paper_2012_00963_amd import workloads
+    if case == "spectrogram":
+        p, sg = workloads.spectrogram_case()
+        run = lambda: ctx.spectrogram(p, sg, want_spectrum=True)
+        packets = sg["n_frames"] * sg["packets_per_frame"]
+    else:
+        p = workloads.large_mie() if case == "mie" else workloads.small_hg(100_000_000)
+        run = (lambda: ctx.spectrum(p, peel=True)) if case == "peel" else (lambda: ctx.spectrum(p))
+        packets = p["n_packets"]
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    ms = []
+    events = 0
+    for _ in range(steps):
+        r = run()
+        ms.append(ctx.last_launch()["kernel_ms"])
+        c = r["spectrum"]["counts"] if case == "spectrogram" and "spectrum" in r else r.get("counts")
+        if c:
+            events = c["collisions"] + c["surface"]
+    torch.cuda.synchronize()
+    print(json.dumps({"case": case, "packets": packets, "events": events, "steps": steps,
+                      "kernel_ms": ms, "kernel_ms_mean": float(np.mean(ms)) if ms else None,
+                      "launch": ctx.last_launch(), "kind": ctx.lib.pdv_last_launch_kind(ctx.h)}), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -519,6 +551,10 @@ def main(argv=None):
     ap.add_argument("--serve-duration", type=float, default=60.0, help="seconds of the serving trace")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving leg (for traces of the serving loop) and print its JSON")
+    ap.add_argument("--profile-case", choices=("mie", "hg", "spectrogram", "peel"), default=None,
+                    help="only launch one workload --steps times (for profiler runs): the large Mie cloud, the "
+                         "small HG slab at 1e8 packets, the 256-frame spectrogram, or the HG slab with the "
+                         "next-event estimate")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -539,6 +575,8 @@ def main(argv=None):
     if args.serve_only:
         print(json.dumps(serve_leg(ctx, duration=args.serve_duration)), flush=True)
         return 0
+    if args.profile_case:
+        return profile_case(ctx, args.profile_case, args.steps, args.warmup)
     p = workloads.large_mie()
     n_packets = p["n_packets"]
 

@@ -471,8 +471,12 @@ void pdv_ctx::default_opts(pdv_launch_opts& o, uint64_t total_packets, int n_set
     // its detections: 12 / 24 / 48 / 64 gave 3.57 / 3.03 / 3.15 / 4.54 ms
     // for the 256-frame spectrogram's transport); FP64 is fastest tallying
     // every round
+    // 32 for the HG slab kind, whose packets last about 1.5 events (16 / 24 /
+    // 32 / 40 / 48 gave 1.34 / 1.24 / 1.24 / 1.24 / 1.27 ms on the 1e8-packet
+    // slab once undetected exits stopped contending for one LDS slot)
     if (o.retire_batch == 0)
-        o.retire_batch = tuned.retire_batch > 0 ? tuned.retire_batch : (fp64 ? 1 : (list ? 24 : 16));
+        o.retire_batch = tuned.retire_batch > 0 ? tuned.retire_batch
+                                                : (fp64 ? 1 : (list ? 24 : (kind == KIND_HG_UNIFORM ? 32 : 16)));
     if (o.packets_per_item == 0) {
         // three large items per block, rounded up so that the item count
         // does not spill into a further round: every item ends with a block
@@ -562,7 +566,7 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
             d.tab_offset = h_desc[src].tab_offset;
         }
         d.tally_offset = tally_words_total;
-        tally_words_total += tally_words(p.n_bins);
+        tally_words_total += tally_words(p.n_bins, d.flags);
         d.list_offset = (uint64_t)i * list_capacity;
         d.list_capacity = list_capacity;
         if (list_capacity) d.flags |= SF_LIST;
@@ -723,7 +727,7 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
             if (outs[i].class_fx && (sets[i].flags & PDV_FLAG_CLASS_TALLIES))
                 h_copy.push_back(CopyJob{t0 + tw_class(nb), 2ull * nb, outs[i].class_fx});
             if (outs[i].peel_fx && (sets[i].flags & PDV_FLAG_PEEL))
-                h_copy.push_back(CopyJob{t0 + tw_peel(nb), 2ull * nb, outs[i].peel_fx});
+                h_copy.push_back(CopyJob{t0 + tw_peel(nb, h_desc[i].flags), 2ull * nb, outs[i].peel_fx});
         }
     }
     if (!h_copy.empty()) {
@@ -819,7 +823,7 @@ void pdv_ctx::unpack(const pdv_params& p, const SetDesc& d, const uint64_t* t, p
         std::memcpy(o.w_fx, t + tw_w(nb), 8ull * nb);
         std::memcpy(o.w2_fx, t + tw_w2(nb), 8ull * nb);
         if (o.class_fx && (p.flags & PDV_FLAG_CLASS_TALLIES)) std::memcpy(o.class_fx, t + tw_class(nb), 16ull * nb);
-        if (o.peel_fx && (p.flags & PDV_FLAG_PEEL)) std::memcpy(o.peel_fx, t + tw_peel(nb), 16ull * nb);
+        if (o.peel_fx && (p.flags & PDV_FLAG_PEEL)) std::memcpy(o.peel_fx, t + tw_peel(nb, d.flags), 16ull * nb);
     }
     for (int k = 0; k < PDV_N_SINKS; ++k) o.sinks_fx[k] = t[tw_sinks(nb) + k];
     o.peel_sinks_fx[0] = t[tw_sinks(nb) + SK_PEEL_UNDER];

@@ -37,22 +37,26 @@ struct TableLayout {
     static constexpr uint64_t BYTES = (PHASE + 8ull * MAX_ANGLES + 255) & ~255ull;
 };
 
-// Tally block of one set, in uint64 words: sum(w) and sum(w^2) per bin, the
-// two class tallies, the next-event estimate sum(c) and sum(c^2) per bin,
-// eight sink words (the six terminal sinks, then the next-event scores
-// below and above the bin range), eight counters.
+// Tally block of one set, in uint64 words: sum(w) and sum(w^2) per bin,
+// eight sink words (the six terminal sinks, then the next-event scores below
+// and above the bin range), eight counters; then, for sets that ask for
+// them, the two class tallies (SF_CLASS) and the next-event estimate sum(c)
+// and sum(c^2) per bin (SF_PEEL).
 enum TallyWords : int { TW_SINKS = 8, TW_COUNTS = 8 };
-inline __host__ __device__ uint64_t tally_words(int n_bins) {
-    return 6ull * (uint64_t)n_bins + TW_SINKS + TW_COUNTS;
-}
-// word offsets inside a tally block
 inline __host__ __device__ uint64_t tw_w(int) { return 0; }
 inline __host__ __device__ uint64_t tw_w2(int n_bins) { return (uint64_t)n_bins; }
-inline __host__ __device__ uint64_t tw_class(int n_bins) { return 2ull * n_bins; }
-inline __host__ __device__ uint64_t tw_peel(int n_bins) { return 4ull * n_bins; }
-inline __host__ __device__ uint64_t tw_peel2(int n_bins) { return 5ull * n_bins; }
-inline __host__ __device__ uint64_t tw_sinks(int n_bins) { return 6ull * n_bins; }
-inline __host__ __device__ uint64_t tw_counts(int n_bins) { return 6ull * n_bins + TW_SINKS; }
+inline __host__ __device__ uint64_t tw_sinks(int n_bins) { return 2ull * n_bins; }
+inline __host__ __device__ uint64_t tw_counts(int n_bins) { return 2ull * n_bins + TW_SINKS; }
+inline __host__ __device__ uint64_t tw_class(int n_bins) { return 2ull * n_bins + TW_SINKS + TW_COUNTS; }
+inline __host__ __device__ uint64_t tw_peel(int n_bins, uint32_t set_flags) {
+    return tw_class(n_bins) + ((set_flags & 1u) ? 2ull * n_bins : 0ull);
+}
+inline __host__ __device__ uint64_t tw_peel2(int n_bins, uint32_t set_flags) {
+    return tw_peel(n_bins, set_flags) + (uint64_t)n_bins;
+}
+inline __host__ __device__ uint64_t tally_words(int n_bins, uint32_t set_flags) {
+    return tw_peel(n_bins, set_flags) + ((set_flags & 4u) ? 2ull * n_bins : 0ull);
+}
 
 // sink word indices inside the sinks block (match pdv.h; the last two hold
 // next-event scores outside the bin range)
@@ -128,6 +132,7 @@ struct alignas(16) ListEntry {
 };
 
 enum SetFlags : uint32_t { SF_CLASS = 1u, SF_LIST = 2u, SF_PEEL = 4u };
+static_assert(SF_CLASS == 1u && SF_PEEL == 4u, "tally_words() tests these flag bits");
 
 // Beat synthesis work split: blocks take (sample tile, frame, group of
 // entry chunks); the entries of a frame are split into groups only while

@@ -78,7 +78,7 @@ struct Req {
     double t_submit = 0, t_admit = 0, t_done = 0;
 };
 
-uint64_t slot_tally_words(int max_bins) { return tally_words(max_bins); }
+uint64_t slot_tally_words(int max_bins) { return tally_words(max_bins, SF_CLASS); }
 
 }  // namespace
 
@@ -337,7 +337,7 @@ struct HipExecutor : Executor {
         for (Req* q : done) {
             const uint64_t off = (uint64_t)q->slot * words;
             if ((r = hipfail(hipMemcpyAsync(h_tally + off, (const uint64_t*)tallies.ptr + off,
-                                            8 * tally_words(q->p.n_bins), hipMemcpyDeviceToHost, s),
+                                            8 * tally_words(q->p.n_bins, SF_CLASS), hipMemcpyDeviceToHost, s),
                              "copy tallies")))
                 return r;
             if ((r = hipfail(hipMemcpyAsync(h_desc + q->slot, (const SetDesc*)descs.ptr + q->slot, sizeof(SetDesc),
@@ -411,7 +411,7 @@ uint64_t ServeEngine::footprint(const Req& r) const {
     uint64_t b = TableLayout::BYTES + 8ull * slot_tally_words(opts.max_bins);
     if (r.want_sg) {
         b += 16ull * r.sg.list_capacity * (uint64_t)r.sg.n_frames;          // detected lists
-        b += (uint64_t)r.sg.n_frames * (TableLayout::BYTES + 8ull * tally_words(r.p.n_bins));
+        b += (uint64_t)r.sg.n_frames * (TableLayout::BYTES + 8ull * tally_words(r.p.n_bins, 0));
         b += 8ull * (uint64_t)r.sg.n_samples + 4ull * (uint64_t)r.sg.nfft * 64;
     }
     return b;

@@ -47,7 +47,7 @@
 namespace pdv {
 
 struct LdsLayout {
-    uint32_t t_off, lg_off, cdf_off, cg_off, hist_off, hist2_off, peel_off, peel2_off, list_off, bytes;
+    uint32_t t_off, lg_off, cdf_off, cg_off, hist_off, hist2_off, peel_off, peel2_off, und_off, list_off, bytes;
 };
 
 // A guide cell's margin (in finest cells) around the scaled depth: covers
@@ -78,7 +78,7 @@ constexpr int REFILL_CHUNK_MIN = 32;
 constexpr int LIST_STAGE = 64;
 
 __host__ __device__ inline LdsLayout lds_layout(int real_bytes, int max_layers, int max_cells, int max_bins,
-                                                int guide_bits, int list_waves, bool peel) {
+                                                int guide_bits, int list_waves, bool peel, int threads) {
     const uint32_t guide_entries = (1u << guide_bits) + 1u;
     LdsLayout L;
     // FP32 launches stage each layer depth and CDF entry beside the inverse
@@ -95,7 +95,11 @@ __host__ __device__ inline LdsLayout lds_layout(int real_bytes, int max_layers, 
     // the bin range go to two of the sink slots)
     L.peel_off = align16(L.hist2_off + 8u * (uint32_t)max_bins);
     L.peel2_off = align16(L.peel_off + (peel ? 8u * (uint32_t)max_bins : 0u));
-    L.list_off = align16(L.peel2_off + (peel ? 8u * (uint32_t)max_bins : 0u));
+    // undetected exits: one 64-bit slot per thread, which only that thread
+    // adds to (nearly every packet ends there; one shared slot serialised
+    // the wave's atomics on a single address)
+    L.und_off = align16(L.peel2_off + (peel ? 8u * (uint32_t)max_bins : 0u));
+    L.list_off = align16(L.und_off + 8u * (uint32_t)threads);
     L.bytes = align16(L.list_off + (uint32_t)sizeof(ListEntry) * LIST_STAGE * (uint32_t)list_waves);
     return L;
 }
@@ -211,18 +215,31 @@ __device__ __forceinline__ uint32_t key_of(const uint32_t& e) { return e; }
 // GUIDE_MARGIN); the staged guide keeps every 2^gshift-th cell, so the
 // lower cell index rounds down and the upper one up.  zeta is linear inside
 // the layer.
-template <typename Real, int KIND>
-__device__ __forceinline__ Real zeta_at(const SetConst<Real>& c, const typename Staged<Real>::TE* T,
-                                        const uint16_t* lg, int gshift, Real t) {
-    if (Kind<KIND>::uniform(c)) return M<Real>::fma(-t, c.zeta_per_tau, c.v_top);
+template <typename Real>
+struct Window {
+    int lo, hi;
+};
+
+// The guide window of the layer holding depth t (guide reads only).
+template <typename Real>
+__device__ __forceinline__ Window<Real> zeta_window(const SetConst<Real>& c, const uint16_t* lg, int gshift, Real t) {
     const Real x = t * c.lg_scale;
     int a = (int)(x - (Real)GUIDE_MARGIN);
     int b = (int)(x + (Real)GUIDE_MARGIN) + 1;
     a = a < 0 ? 0 : (a > LAYER_GUIDE - 1 ? LAYER_GUIDE - 1 : a);
-    b = b > LAYER_GUIDE ? LAYER_GUIDE : b;
-    int lo = lg[a >> gshift];
-    int hi = lg[(b + (1 << gshift) - 1) >> gshift];
-    hi = hi > c.n_layers - 1 ? c.n_layers - 1 : hi;
+    b = b < 0 ? 0 : (b > LAYER_GUIDE ? LAYER_GUIDE : b);    // depths outside the slab stay in bounds
+    Window<Real> w;
+    w.lo = lg[a >> gshift];
+    w.hi = lg[(b + (1 << gshift) - 1) >> gshift];
+    return w;
+}
+
+// Bisection inside the window until every lane of the wave has converged,
+// then the velocity coordinate, linear inside the layer.
+template <typename Real>
+__device__ __forceinline__ Real zeta_finish(const SetConst<Real>& c, const typename Staged<Real>::TE* T,
+                                            Window<Real> w, Real t) {
+    int lo = w.lo, hi = w.hi > c.n_layers - 1 ? c.n_layers - 1 : w.hi;
     while (__ballot(lo < hi) != 0ull) {
         const int mid = (lo + hi + 1) >> 1;
         const bool le = key_of(T[mid]) <= t;
@@ -239,17 +256,30 @@ __device__ __forceinline__ Real zeta_at(const SetConst<Real>& c, const typename 
     return M<Real>::fma(-((Real)lo + frac), c.dzeta, c.v_top);
 }
 
+template <typename Real, int KIND>
+__device__ __forceinline__ Real zeta_at(const SetConst<Real>& c, const typename Staged<Real>::TE* T,
+                                        const uint16_t* lg, int gshift, Real t) {
+    if (Kind<KIND>::uniform(c)) return M<Real>::fma(-t, c.zeta_per_tau, c.v_top);
+    return zeta_finish<Real>(c, T, zeta_window<Real>(c, lg, gshift, t), t);
+}
+
 // Scattering angle from the integer CDF: the cell is the last j with
 // C[j] <= x; it lies between the guide entries of the top guide_bits bits of
 // x; the angle is uniform inside the cell.  Returned in units of the cell
 // grid (cell index plus the fraction inside it).
 // The cell of a 32-bit CDF value x: the last j with C[j] <= x, between the
 // guide entries of the top guide_bits bits of x.
-template <typename CE>
-__device__ __forceinline__ int table_cell_of(const CE* C, const uint16_t* cg, int guide_bits, uint32_t x) {
+__device__ __forceinline__ Window<float> table_window(const uint16_t* cg, int guide_bits, uint32_t x) {
     const uint32_t gi = x >> (32 - guide_bits);
-    int lo = cg[gi];
-    int hi = cg[gi + 1];
+    Window<float> w;
+    w.lo = cg[gi];
+    w.hi = cg[gi + 1];
+    return w;
+}
+
+template <typename CE>
+__device__ __forceinline__ int table_search(const CE* C, Window<float> w, uint32_t x) {
+    int lo = w.lo, hi = w.hi;
     while (__ballot(lo < hi) != 0ull) {
         const int mid = (lo + hi + 1) >> 1;
         const bool le = key_of(C[mid]) <= x;
@@ -259,10 +289,14 @@ __device__ __forceinline__ int table_cell_of(const CE* C, const uint16_t* cg, in
     return lo;
 }
 
+template <typename CE>
+__device__ __forceinline__ int table_cell_of(const CE* C, const uint16_t* cg, int guide_bits, uint32_t x) {
+    return table_search(C, table_window(cg, guide_bits, x), x);
+}
+
+// Cell index plus the fraction inside the cell (uniform angle in a cell)
 template <typename Real>
-__device__ __forceinline__ Real table_cells(const typename Staged<Real>::CE* C, const uint16_t* cg, int guide_bits,
-                                            uint32_t x) {
-    const int lo = table_cell_of(C, cg, guide_bits, x);
+__device__ __forceinline__ Real table_frac(const typename Staged<Real>::CE* C, int lo, uint32_t x) {
     if constexpr (sizeof(Real) == 4) {
         const uint2 e = C[lo];
         return (Real)lo + ((Real)(x - e.x) + (Real)0.5) * __uint_as_float(e.y);
@@ -275,6 +309,12 @@ __device__ __forceinline__ Real table_cells(const typename Staged<Real>::CE* C, 
         const Real width = dw != 0u ? (Real)dw : (Real)4294967296.0;
         return (Real)lo + M<Real>::div((Real)(x - cj) + (Real)0.5, width);
     }
+}
+
+template <typename Real>
+__device__ __forceinline__ Real table_cells(const typename Staged<Real>::CE* C, const uint16_t* cg, int guide_bits,
+                                            uint32_t x) {
+    return table_frac<Real>(C, table_cell_of(C, cg, guide_bits, x), x);
 }
 
 // Henyey-Greenstein polar cosine by inversion of its cumulative
@@ -538,7 +578,7 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
     __shared__ uint32_t s_next;
 
     const LdsLayout L = lds_layout((int)sizeof(Real), max_layers, max_cells, max_bins, guide_bits,
-                                   LIST ? (int)(blockDim.x >> 6) : 0, PEEL);
+                                   LIST ? (int)(blockDim.x >> 6) : 0, PEEL, (int)blockDim.x);
     const int gshift = GUIDE_BITS - guide_bits;
     const int n_guide = 1 << guide_bits;
     using TE = typename Staged<Real>::TE;
@@ -549,6 +589,7 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
     uint16_t* sCG = (uint16_t*)(lds + L.cg_off);
     unsigned long long* sW = (unsigned long long*)(lds + L.hist_off);     // bins, then sink slots
     unsigned long long* sW2 = (unsigned long long*)(lds + L.hist2_off);
+    unsigned long long* sU = (unsigned long long*)(lds + L.und_off);      // this block's threads' undetected weight
     unsigned long long* sP = (unsigned long long*)(lds + L.peel_off);     // next-event sum(c), sum(c^2)
     unsigned long long* sP2 = (unsigned long long*)(lds + L.peel2_off);
 
@@ -596,8 +637,8 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
         }
         if constexpr (PEEL) {
             if (d.flags & SF_PEEL) {
-                unsigned long long* gP = (unsigned long long*)(tally + tw_peel(d.n_bins));
-                unsigned long long* gP2 = (unsigned long long*)(tally + tw_peel2(d.n_bins));
+                unsigned long long* gP = (unsigned long long*)(tally + tw_peel(d.n_bins, d.flags));
+                unsigned long long* gP2 = (unsigned long long*)(tally + tw_peel2(d.n_bins, d.flags));
                 for (int b = tid; b < d.n_bins; b += nthr) {
                     const unsigned long long v = sP[b], v2 = sP2[b];
                     if (v) atomicAdd(gP + b, v);
@@ -608,6 +649,11 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
         if (tid < N_SINK_SLOTS) {
             const unsigned long long v = sW[d.n_bins + tid];
             if (v) atomicAdd(gS + tid, v);
+        }
+        {
+            // the threads' undetected weight: summed per wave, one atomic each
+            const unsigned long long u = wave_sum_u64(sU[tid]);
+            if (lane == 0 && u) atomicAdd(gS + SK_UNDETECTED, u);
         }
         __syncthreads();
     };
@@ -668,6 +714,7 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
             }
             for (int i = tid; i < d.n_bins + N_SINK_SLOTS; i += nthr) sW[i] = 0ull;
             for (int i = tid; i < d.n_bins; i += nthr) sW2[i] = 0ull;
+            sU[tid] = 0ull;
             if constexpr (PEEL) {
                 for (int i = tid; i < d.n_bins; i += nthr) {
                     sP[i] = 0ull;
@@ -727,7 +774,8 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                                                                                           : SK_ABS_PARTICLE)));
                     }
                     const uint64_t fw = to_fixed32<Real>(w);
-                    atomicAdd(&sW[slot], (unsigned long long)fw);
+                    if (slot == nb + SK_UNDETECTED) sU[tid] += (unsigned long long)fw;
+                    else atomicAdd(&sW[slot], (unsigned long long)fw);
                     if (slot < nb) {
                         atomicAdd(&sW2[slot], (unsigned long long)to_fixed32<Real>(w * w));
                         if (Kind<KIND>::cls(c)) {
@@ -1050,7 +1098,8 @@ hipError_t plan_transport(TransportShape& sh, int precision, bool list, int want
     const int rb = precision == 1 ? 8 : 4;
     const void* kp = select_kernel(precision, list, sh.kind, sh.peel);
     auto bytes = [&](int bits) {
-        return (int)lds_layout(rb, sh.max_layers, sh.max_cells, sh.max_bins, bits, list ? sh.block / 64 : 0, sh.peel)
+        return (int)lds_layout(rb, sh.max_layers, sh.max_cells, sh.max_bins, bits, list ? sh.block / 64 : 0, sh.peel,
+                               sh.block)
             .bytes;
     };
     if (want_bits != 0) {

@@ -311,12 +311,7 @@ class Context:
         for i, p in enumerate(sets):
             arr[i] = make_params(dict(p, flags=int(p.get("flags", 0)) | FLAG_DEVICE_OUTPUT), keep)
             outs[i].w_fx, outs[i].w2_fx = int(outputs[i][0]), int(outputs[i][1])
-        o = None
-        if opts:
-            o = LaunchOpts(int(opts.get("block_size", 0)), int(opts.get("blocks_per_cu", 0)),
-                           int(opts.get("packets_per_item", 0)), int(opts.get("persistent", -1)),
-                           int(opts.get("use_graph", 0)), int(opts.get("guide_bits", 0)),
-                           int(opts.get("retire_batch", 0)))
+        o = _launch_opts(opts)
         self._check(self.lib.pdv_spectrum_batch(self.h, arr, n, outs, ctypes.byref(o) if o else None))
         res = []
         for i in range(n):
@@ -334,26 +329,79 @@ class Context:
         """Spectra of a batch (one persistent launch).  peel: also the
         next-event estimate of the detector tally (result keys peel_fx,
         P, P2, peel_sinks) for every set."""
-        keep = []
+        return PreparedBatch(self, sets, class_tallies=class_tallies, peel=peel).run(opts)
+
+    def prepare_batch(self, sets: list, class_tallies: bool = False, peel: bool = False) -> "PreparedBatch":
+        """Marshal a batch once; PreparedBatch.run() then calls the library
+        on the same structs and output buffers."""
+        return PreparedBatch(self, sets, class_tallies=class_tallies, peel=peel)
+
+    def last_launch(self) -> dict:
+        ms = ctypes.c_float()
+        g, b, it, gb, lds = (ctypes.c_int32() for _ in range(5))
+        self.lib.pdv_last_launch(self.h, ctypes.byref(ms), ctypes.byref(g), ctypes.byref(b), ctypes.byref(it),
+                                 ctypes.byref(gb), ctypes.byref(lds))
+        return {"kernel_ms": float(ms.value), "grid": g.value, "block": b.value, "items": it.value,
+                "guide_bits": gb.value, "lds_bytes": lds.value, "kind": int(self.lib.pdv_last_launch_kind(self.h))}
+
+
+def _launch_opts(opts):
+    if not opts:
+        return None
+    return LaunchOpts(int(opts.get("block_size", 0)), int(opts.get("blocks_per_cu", 0)),
+                      int(opts.get("packets_per_item", 0)), int(opts.get("persistent", -1)),
+                      int(opts.get("use_graph", 0)), int(opts.get("guide_bits", 0)),
+                      int(opts.get("retire_batch", 0)))
+
+
+class _Results(list):
+    """Results of a batch, each built from the output structs on first access."""
+
+    def __init__(self, outs, bufs):
+        super().__init__([None] * len(bufs))
+        self._outs, self._bufs = outs, bufs
+
+    def __getitem__(self, i):
+        if isinstance(i, slice):
+            return [self[j] for j in range(*i.indices(len(self)))]
+        v = list.__getitem__(self, i)
+        if v is None:
+            v = _result(self._outs[i], *self._bufs[i])
+            list.__setitem__(self, i, v)
+        return v
+
+    def __iter__(self):
+        for i in range(len(self)):
+            yield self[i]
+
+
+class PreparedBatch:
+    """A batch of parameter sets marshalled once into pdv_params structs and
+    output buffers (every set's tallies are disjoint views of one buffer,
+    which the library fills completely on success).  run() launches it; the
+    results of a run are valid until the next run of the same batch."""
+
+    def __init__(self, ctx: "Context", sets: list, class_tallies: bool = False, peel: bool = False):
+        self.ctx = ctx
+        self.keep = []
         n = len(sets)
-        arr = (Params * n)()
-        outs = (SpectrumOut * n)()
-        # every set's tallies are disjoint views of one buffer, which the
-        # library fills completely on success
+        self.n = n
+        self.arr = (Params * n)()
+        self.outs = (SpectrumOut * n)()
         per = (4 if class_tallies else 2) + (2 if peel else 0)
         nbs = [int(p.get("n_bins", DEFAULTS["n_bins"])) for p in sets]
-        buf = np.empty(per * sum(nbs), dtype=np.uint64)
-        base = buf.ctypes.data
-        bufs = []
+        self.buf = np.empty(per * sum(nbs), dtype=np.uint64)
+        base = self.buf.ctypes.data
+        self.bufs = []
         off = 0
+        buf = self.buf
         for i, p in enumerate(sets):
-            if class_tallies:
-                p = dict(p, flags=int(p.get("flags", 0)) | FLAG_CLASS_TALLIES)
-            if peel:
-                p = dict(p, flags=int(p.get("flags", 0)) | FLAG_PEEL)
-            arr[i] = make_params(p, keep)
+            if class_tallies or peel:
+                p = dict(p, flags=int(p.get("flags", 0)) | (FLAG_CLASS_TALLIES if class_tallies else 0)
+                         | (FLAG_PEEL if peel else 0))
+            self.arr[i] = make_params(p, self.keep)
             nb = nbs[i]
-            o = outs[i]
+            o = self.outs[i]
             o.w_fx = base + 8 * off
             o.w2_fx = base + 8 * (off + nb)
             C = None
@@ -365,24 +413,14 @@ class Context:
                 q = off + (4 if class_tallies else 2) * nb
                 o.peel_fx = base + 8 * q
                 Pf = buf[q:q + 2 * nb]
-            bufs.append((buf[off:off + nb], buf[off + nb:off + 2 * nb], C, nb, Pf))
+            self.bufs.append((buf[off:off + nb], buf[off + nb:off + 2 * nb], C, nb, Pf))
             off += per * nb
-        o = None
-        if opts:
-            o = LaunchOpts(int(opts.get("block_size", 0)), int(opts.get("blocks_per_cu", 0)),
-                           int(opts.get("packets_per_item", 0)), int(opts.get("persistent", -1)),
-                           int(opts.get("use_graph", 0)), int(opts.get("guide_bits", 0)),
-                           int(opts.get("retire_batch", 0)))
-        self._check(self.lib.pdv_spectrum_batch(self.h, arr, n, outs, ctypes.byref(o) if o else None))
-        return [_result(outs[i], *bufs[i]) for i in range(n)]
 
-    def last_launch(self) -> dict:
-        ms = ctypes.c_float()
-        g, b, it, gb, lds = (ctypes.c_int32() for _ in range(5))
-        self.lib.pdv_last_launch(self.h, ctypes.byref(ms), ctypes.byref(g), ctypes.byref(b), ctypes.byref(it),
-                                 ctypes.byref(gb), ctypes.byref(lds))
-        return {"kernel_ms": float(ms.value), "grid": g.value, "block": b.value, "items": it.value,
-                "guide_bits": gb.value, "lds_bytes": lds.value, "kind": int(self.lib.pdv_last_launch_kind(self.h))}
+    def run(self, opts: dict | None = None) -> list:
+        o = _launch_opts(opts)
+        self.ctx._check(self.ctx.lib.pdv_spectrum_batch(self.ctx.h, self.arr, self.n, self.outs,
+                                                         ctypes.byref(o) if o else None))
+        return _Results(self.outs, self.bufs)
 
 
 def _fptr(a):
