@@ -90,6 +90,14 @@ enum { PDV_FP32 = 0, PDV_FP64 = 1 };
  * for narrow cones its variance is far lower.  Accepted by pdv_spectrum and
  * pdv_spectrum_batch only. */
 #define PDV_FLAG_PEEL 4u
+/* Add this call's tallies and counters to what the (host) outputs already
+ * hold instead of overwriting them: checkpoint and resume.  A run of packets
+ * [0, N) split into calls over [0, k) and [k, N) (pid_begin = k,
+ * n_packets = N - k, outputs carried over, for example saved to disk and
+ * read back) equals one call over [0, N) bit for bit, because every packet
+ * draws from its own random stream and the tallies are integer sums.  Not
+ * with PDV_FLAG_DEVICE_OUTPUT (PDV_EINVAL).  Served requests accept it. */
+#define PDV_FLAG_ACCUMULATE 8u
 
 /*
  * One parameter set: the problem statement of Sec. II.
@@ -437,6 +445,11 @@ typedef struct pdv_serve_opts {
                                       (every packet is tallied as undetected with unit weight) */
     int32_t host_fail_iteration;   /* PDV_EXEC_HOST: report a device failure at this iteration (0 = never) */
     double host_ns_per_packet;     /* PDV_EXEC_HOST: simulated cost per packet */
+    double watchdog_ms;            /* > 0: a launch (with its result copies) still running after this long
+                                      fails every active and waiting request with PDV_EDEVICE, and the
+                                      context is poisoned (the device may still be busy); 0 = no limit */
+    int32_t sg_workers;            /* spectrogram workers, each with its own context and stream (0 = 3, at
+                                      most 8); requests with a spectrogram are finished by the next free one */
 } pdv_serve_opts;
 
 /*

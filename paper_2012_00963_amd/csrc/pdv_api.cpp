@@ -38,6 +38,8 @@ int launch_kind_of(const pdv_params* sets, int n);
 hipError_t plan_transport(TransportShape& sh, int precision, bool list, int want_bits, int lds_per_block,
                           int lds_per_cu);
 SynthPlan synth_plan(int n_frames, int n_samples, uint64_t max_entries);
+void launch_frame_ranges(hipStream_t s, int n_frames, uint64_t capacity, const uint64_t* counts, uint64_t* fbeg,
+                         uint64_t* fend);
 hipError_t launch_synth(hipStream_t s, const SynthPlan& P, int n_frames, int n_samples, const uint64_t* fbeg,
                         const uint64_t* fend, const ListEntry* rec, const float* w, const double* v,
                         const uint32_t* phase, double r_scale, float* partial, float* signal);
@@ -491,7 +493,7 @@ void pdv_ctx::default_opts(pdv_launch_opts& o, uint64_t total_packets, int n_set
 }
 
 int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, const pdv_launch_opts* opts_in,
-                       uint64_t list_capacity, bool keep_device) {
+                       uint64_t list_capacity, bool keep_device, bool defer) {
     if (poisoned) return fail(PDV_EDEVICE, "context poisoned by an earlier device error");
     if (!ready) return fail(PDV_ESTATE, "context not initialised");
     if (!sets || n < 1) return fail(PDV_EINVAL, "need at least one parameter set");
@@ -501,6 +503,8 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
         if (int r = validate_params(this, &sets[i])) return r;
         if (sets[i].precision != precision) return fail(PDV_EINVAL, "all sets of a batch need one precision");
         if (outs && (!outs[i].w_fx || !outs[i].w2_fx)) return fail(PDV_EINVAL, "set %d: NULL w_fx or w2_fx", i);
+        if ((sets[i].flags & PDV_FLAG_ACCUMULATE) && (sets[i].flags & PDV_FLAG_DEVICE_OUTPUT))
+            return fail(PDV_EINVAL, "set %d: PDV_FLAG_ACCUMULATE applies to host outputs only", i);
         if (sets[i].flags & PDV_FLAG_DEVICE_OUTPUT) {
             if (!outs || list_capacity) return fail(PDV_EINVAL, "set %d: device outputs need a spectrum call", i);
             const bool cls = outs[i].class_fx && (sets[i].flags & PDV_FLAG_CLASS_TALLIES);
@@ -737,20 +741,33 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
         launch_copy_jobs(s, (int)h_copy.size(), copy_jobs.ptr, (const uint64_t*)tallies.ptr);
         if ((r = hip_check(hipGetLastError(), "device output copies"))) return r;
     }
-    // tallies come back through pinned staging (a pageable copy of the
-    // 16 MB of a 512-set batch ran at a fraction of the link rate)
-    if ((r = ensure_pinned(tally_pinned, 8 * std::max<uint64_t>(1, tally_words_total), "tally staging"))) return r;
-    uint64_t* ht = (uint64_t*)tally_pinned.ptr;
-    if ((r = hip_check(hipMemcpyAsync(ht, tallies.ptr, 8 * tally_words_total, hipMemcpyDeviceToHost, s),
-                       "copy tallies")))
-        return r;
-    if ((r = hip_check(hipMemcpyAsync(h_desc.data(), descs.ptr, sizeof(SetDesc) * n, hipMemcpyDeviceToHost, s),
-                       "copy descriptors back")))
-        return r;
-    if ((r = hip_check(hipStreamSynchronize(s), "transport kernel"))) return r;
+    // tallies and the descriptors the table kernels finished come back
+    // through pinned staging (a pageable copy of a 512-set batch's tallies
+    // ran at a fraction of the link rate, and a pageable destination would
+    // make the host wait for the copy here)
+    const size_t tb = 8 * tally_words_total;
+    pending_tally_words = tally_words_total;
+    if (outs) {       // (a spectrogram without its spectrum keeps the tallies on the device)
+        if ((r = ensure_pinned(tally_pinned, tb + sizeof(SetDesc) * n + 8, "tally staging"))) return r;
+        uint8_t* ht = (uint8_t*)tally_pinned.ptr;
+        if (tb && (r = hip_check(hipMemcpyAsync(ht, tallies.ptr, tb, hipMemcpyDeviceToHost, s), "copy tallies")))
+            return r;
+        if ((r = hip_check(hipMemcpyAsync(ht + tb, descs.ptr, sizeof(SetDesc) * n, hipMemcpyDeviceToHost, s),
+                           "copy descriptors back")))
+            return r;
+    }
+    if (defer) return PDV_OK;
+    return finish_batch(sets, n, outs);
+}
+
+// Wait for a batch's result copies and unpack them into the outputs.
+int pdv_ctx::finish_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs) {
+    if (int r = hip_check(hipStreamSynchronize(stream), "transport kernel")) return r;
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, ev_a, ev_b) == hipSuccess) last_kernel_ms = ms;
     if (outs) {
+        const uint64_t* ht = (const uint64_t*)tally_pinned.ptr;
+        std::memcpy(h_desc.data(), (const uint8_t*)tally_pinned.ptr + 8 * pending_tally_words, sizeof(SetDesc) * n);
         for (int i = 0; i < n; ++i) unpack(sets[i], h_desc[i], ht + h_desc[i].tally_offset, outs[i]);
     }
     return PDV_OK;
@@ -819,21 +836,32 @@ int pdv_ctx::launch_batch_graph(const TransportShape& sh, int precision, bool li
 
 void pdv_ctx::unpack(const pdv_params& p, const SetDesc& d, const uint64_t* t, pdv_spectrum_out& o) {
     const int nb = p.n_bins;
+    // PDV_FLAG_ACCUMULATE adds to what the outputs hold (a checkpoint of
+    // earlier packets); integer sums, so a run resumed in parts equals one run
+    const bool acc = (p.flags & PDV_FLAG_ACCUMULATE) != 0;
+    auto put = [&](uint64_t* dst, const uint64_t* src, size_t n) {
+        if (acc) {
+            for (size_t i = 0; i < n; ++i) dst[i] += src[i];
+        } else {
+            std::memcpy(dst, src, 8 * n);
+        }
+    };
+    auto put1 = [&](uint64_t& dst, uint64_t v) { dst = acc ? dst + v : v; };
     if (!(p.flags & PDV_FLAG_DEVICE_OUTPUT)) {   // device outputs were filled on the device
-        std::memcpy(o.w_fx, t + tw_w(nb), 8ull * nb);
-        std::memcpy(o.w2_fx, t + tw_w2(nb), 8ull * nb);
-        if (o.class_fx && (p.flags & PDV_FLAG_CLASS_TALLIES)) std::memcpy(o.class_fx, t + tw_class(nb), 16ull * nb);
-        if (o.peel_fx && (p.flags & PDV_FLAG_PEEL)) std::memcpy(o.peel_fx, t + tw_peel(nb, d.flags), 16ull * nb);
+        put(o.w_fx, t + tw_w(nb), nb);
+        put(o.w2_fx, t + tw_w2(nb), nb);
+        if (o.class_fx && (p.flags & PDV_FLAG_CLASS_TALLIES)) put(o.class_fx, t + tw_class(nb), 2ull * nb);
+        if (o.peel_fx && (p.flags & PDV_FLAG_PEEL)) put(o.peel_fx, t + tw_peel(nb, d.flags), 2ull * nb);
     }
-    for (int k = 0; k < PDV_N_SINKS; ++k) o.sinks_fx[k] = t[tw_sinks(nb) + k];
-    o.peel_sinks_fx[0] = t[tw_sinks(nb) + SK_PEEL_UNDER];
-    o.peel_sinks_fx[1] = t[tw_sinks(nb) + SK_PEEL_OVER];
+    for (int k = 0; k < PDV_N_SINKS; ++k) put1(o.sinks_fx[k], t[tw_sinks(nb) + k]);
+    put1(o.peel_sinks_fx[0], t[tw_sinks(nb) + SK_PEEL_UNDER]);
+    put1(o.peel_sinks_fx[1], t[tw_sinks(nb) + SK_PEEL_OVER]);
     const uint64_t* c = t + tw_counts(nb);
-    o.counters.packets = c[C_PACKETS];
-    o.counters.collisions = c[C_COLLISIONS];
-    o.counters.surface = c[C_SURFACE];
-    o.counters.exits = c[C_EXITS];
-    o.counters.detected = c[C_DETECTED];
+    put1(o.counters.packets, c[C_PACKETS]);
+    put1(o.counters.collisions, c[C_COLLISIONS]);
+    put1(o.counters.surface, c[C_SURFACE]);
+    put1(o.counters.exits, c[C_EXITS]);
+    put1(o.counters.detected, c[C_DETECTED]);
     o.albedo = d.albedo;
     o.g = d.g_mean;
 }
@@ -916,17 +944,25 @@ int pdv_ctx::synthesize(int n_frames, const uint64_t* entry_begin, const uint64_
         fb[n_frames + k] = entry_begin[k] + n_entries[k];
         max_entries = std::max<uint64_t>(max_entries, n_entries[k]);
     }
-    const SynthPlan P = synth_plan(n_frames, n_samples, max_entries);
     int r;
     if ((r = ensure(sg_frames, 16ull * n_frames, "synthesis frames"))) return r;
-    if ((r = ensure(sg_partial, 4ull * std::max<uint64_t>(1, P.partial_floats), "synthesis partials"))) return r;
-    if ((r = ensure(sg_signal, 4ull * std::max(1, n_samples), "beat signal"))) return r;
     if ((r = hip_check(hipMemcpyAsync(sg_frames.ptr, fb.data(), 16ull * n_frames, hipMemcpyHostToDevice, stream),
                        "copy frames")))
         return r;
-    const ListEntry* src = entries ? entries : (const ListEntry*)lists.ptr;
     const uint64_t* d_fb = (const uint64_t*)sg_frames.ptr;
-    hipError_t e = launch_synth(stream, P, n_frames, n_samples, d_fb, d_fb + n_frames, src, nullptr, nullptr, nullptr,
+    return synthesize_dev(n_frames, d_fb, d_fb + n_frames, entries, max_entries, wavelength, fs, n_samples);
+}
+
+// Frame entry ranges [d_fbeg[k], d_fend[k]) already on the device;
+// max_entries bounds every frame's count (it sets the work split).
+int pdv_ctx::synthesize_dev(int n_frames, const uint64_t* d_fbeg, const uint64_t* d_fend, const ListEntry_* entries,
+                            uint64_t max_entries, double wavelength, double fs, int n_samples) {
+    const SynthPlan P = synth_plan(n_frames, n_samples, max_entries);
+    int r;
+    if ((r = ensure(sg_partial, 4ull * std::max<uint64_t>(1, P.partial_floats), "synthesis partials"))) return r;
+    if ((r = ensure(sg_signal, 4ull * std::max(1, n_samples), "beat signal"))) return r;
+    const ListEntry* src = entries ? entries : (const ListEntry*)lists.ptr;
+    hipError_t e = launch_synth(stream, P, n_frames, n_samples, d_fbeg, d_fend, src, nullptr, nullptr, nullptr,
                                 2.0 / (wavelength * fs), (float*)sg_partial.ptr, (float*)sg_signal.ptr);
     return hip_check(e, "beat synthesis kernels");
 }
@@ -987,46 +1023,32 @@ int pdv_spectrogram_internal(pdv_ctx* ctx, const pdv_params* p, const pdv_sg_par
         frames[k].n_packets = sg->packets_per_frame;
     }
     const int nb = p->n_bins;
-    std::vector<uint64_t> W((size_t)F * nb), W2((size_t)F * nb);
-    std::vector<pdv_spectrum_out> outs(F);
-    for (int k = 0; k < F; ++k) {
+    // per-frame tallies come back only when the summed spectrum is asked for
+    const bool want_spec = out->spectrum != nullptr;
+    std::vector<uint64_t> W(want_spec ? (size_t)F * nb : 0), W2(want_spec ? (size_t)F * nb : 0);
+    std::vector<pdv_spectrum_out> outs(want_spec ? F : 0);
+    for (int k = 0; k < (want_spec ? F : 0); ++k) {
         std::memset(&outs[k], 0, sizeof(pdv_spectrum_out));
         outs[k].w_fx = W.data() + (size_t)k * nb;
         outs[k].w2_fx = W2.data() + (size_t)k * nb;
     }
-    if (int r = ctx->run_batch(frames.data(), F, outs.data(), nullptr, sg->list_capacity, true)) return r;
-    // detected entries per frame (the transport already synchronised the stream)
-    std::vector<uint64_t> counts(F), begin(F), kept(F);
-    if (int r = ctx->hip_check(hipMemcpy(counts.data(), ctx->list_counts.ptr, 8ull * F, hipMemcpyDeviceToHost),
-                               "copy list counts"))
+    // transport, frame ranges, synthesis, STFT and the result copies are
+    // enqueued back to back; the host waits once, at the end
+    if (int r = ctx->run_batch(frames.data(), F, want_spec ? outs.data() : nullptr, nullptr, sg->list_capacity, true,
+                               true))
         return r;
-    int overflow = 0;
-    for (int k = 0; k < F; ++k) {
-        begin[k] = (uint64_t)k * sg->list_capacity;
-        kept[k] = std::min<uint64_t>(counts[k], sg->list_capacity);
-        if (counts[k] > sg->list_capacity) overflow = 1;
-    }
-    if (out->list_w || out->list_v || out->list_phase) {
-        if (!out->list_w || !out->list_v || !out->list_phase || out->list_stride == 0)
-            return ctx->fail(PDV_EINVAL, "list output needs list_w, list_v, list_phase and list_stride > 0");
-        std::vector<ListEntry> ent((size_t)F * sg->list_capacity);
-        if (int r = ctx->hip_check(hipMemcpy(ent.data(), ctx->lists.ptr, sizeof(ListEntry) * ent.size(),
-                                             hipMemcpyDeviceToHost), "copy lists"))
-            return r;
-        for (int k = 0; k < F; ++k) {
-            const uint64_t m = std::min<uint64_t>(kept[k], out->list_stride);
-            for (uint64_t i = 0; i < m; ++i) {
-                const ListEntry& e = ent[(size_t)k * sg->list_capacity + i];
-                out->list_w[(size_t)k * out->list_stride + i] = e.w;
-                out->list_v[(size_t)k * out->list_stride + i] = e.v;
-                out->list_phase[(size_t)k * out->list_stride + i] = e.phase;
-            }
-        }
-    }
-    if (int r = ctx->synthesize(F, begin.data(), kept.data(), nullptr, p->wavelength, sg->fs, sg->n_samples))
-        return r;
+    const uint64_t cap = sg->list_capacity;
+    if (int r = ctx->ensure(ctx->sg_frames, 16ull * F, "synthesis frames")) return r;
+    uint64_t* d_fb = (uint64_t*)ctx->sg_frames.ptr;
+    launch_frame_ranges(ctx->stream, F, cap, (const uint64_t*)ctx->list_counts.ptr, d_fb, d_fb + F);
+    if (int r = ctx->hip_check(hipGetLastError(), "frame ranges")) return r;
+    if (int r = ctx->synthesize_dev(F, d_fb, d_fb + F, nullptr, cap, p->wavelength, sg->fs, sg->n_samples)) return r;
     int nw = 0;
     if (int r = ctx->stft((const float*)ctx->sg_signal.ptr, sg->n_samples, sg->nfft, sg->hop, &nw)) return r;
+    if (int r = ctx->ensure_pinned(ctx->counts_pinned, 8ull * F, "list counts")) return r;
+    if (int r = ctx->hip_check(hipMemcpyAsync(ctx->counts_pinned.ptr, ctx->list_counts.ptr, 8ull * F,
+                                              hipMemcpyDeviceToHost, ctx->stream), "copy list counts"))
+        return r;
     const size_t map_floats = (size_t)nw * (sg->nfft / 2 + 1);
     if (map_floats)
         if (int r = ctx->hip_check(hipMemcpyAsync(out->map, ctx->sg_map.ptr, 4 * map_floats, hipMemcpyDeviceToHost,
@@ -1036,7 +1058,32 @@ int pdv_spectrogram_internal(pdv_ctx* ctx, const pdv_params* p, const pdv_sg_par
         if (int r = ctx->hip_check(hipMemcpyAsync(out->signal, ctx->sg_signal.ptr, 4ull * sg->n_samples,
                                                   hipMemcpyDeviceToHost, ctx->stream), "copy signal"))
             return r;
-    if (int r = ctx->hip_check(hipStreamSynchronize(ctx->stream), "spectrogram")) return r;
+    if (int r = ctx->finish_batch(frames.data(), F, want_spec ? outs.data() : nullptr)) return r;
+    // detected entries per frame
+    std::vector<uint64_t> counts(F), kept(F);
+    std::memcpy(counts.data(), ctx->counts_pinned.ptr, 8ull * F);
+    int overflow = 0;
+    for (int k = 0; k < F; ++k) {
+        kept[k] = std::min<uint64_t>(counts[k], cap);
+        if (counts[k] > cap) overflow = 1;
+    }
+    if (out->list_w || out->list_v || out->list_phase) {
+        if (!out->list_w || !out->list_v || !out->list_phase || out->list_stride == 0)
+            return ctx->fail(PDV_EINVAL, "list output needs list_w, list_v, list_phase and list_stride > 0");
+        std::vector<ListEntry> ent((size_t)F * cap);
+        if (int r = ctx->hip_check(hipMemcpy(ent.data(), ctx->lists.ptr, sizeof(ListEntry) * ent.size(),
+                                             hipMemcpyDeviceToHost), "copy lists"))
+            return r;
+        for (int k = 0; k < F; ++k) {
+            const uint64_t m = std::min<uint64_t>(kept[k], out->list_stride);
+            for (uint64_t i = 0; i < m; ++i) {
+                const ListEntry& e = ent[(size_t)k * cap + i];
+                out->list_w[(size_t)k * out->list_stride + i] = e.w;
+                out->list_v[(size_t)k * out->list_stride + i] = e.v;
+                out->list_phase[(size_t)k * out->list_stride + i] = e.phase;
+            }
+        }
+    }
     if (out->frame_counts) std::memcpy(out->frame_counts, counts.data(), 8ull * F);
     out->n_windows = nw;
     out->overflow = overflow;

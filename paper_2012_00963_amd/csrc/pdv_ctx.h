@@ -132,10 +132,17 @@ struct pdv_ctx {
     int ensure_mie_basis(const pdv_params& p);
     void default_opts(pdv_launch_opts& o, uint64_t total_packets, int n_sets, bool fp64, int kind,
                       bool list, bool peel = false) const;
+    // defer: enqueue the result copies and return without waiting;
+    // finish_batch then waits and unpacks
     int run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, const pdv_launch_opts* opts,
-                  uint64_t list_capacity, bool keep_device);
+                  uint64_t list_capacity, bool keep_device, bool defer = false);
+    int finish_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs);
+    uint64_t pending_tally_words = 0;    // tally words of a deferred batch in tally_pinned
     int synthesize(int n_frames, const uint64_t* entry_begin, const uint64_t* n_entries, const ListEntry_* entries,
                    double wavelength, double fs, int n_samples);
+    int synthesize_dev(int n_frames, const uint64_t* d_fbeg, const uint64_t* d_fend, const ListEntry_* entries,
+                       uint64_t max_entries, double wavelength, double fs, int n_samples);
+    HostPinned counts_pinned;            // list counts of a spectrogram
     int stft(const float* d_signal, int n_samples, int nfft, int hop, int* n_windows);
     void unpack(const pdv_params& p, const pdv::SetDesc& d, const uint64_t* t, pdv_spectrum_out& o);
     int launch_batch_graph(const pdv::TransportShape& sh, int precision, bool list, int persistent);

@@ -89,7 +89,9 @@ struct Executor {
     virtual ~Executor() = default;
     virtual int init() = 0;
     virtual int prepare(const std::vector<Req*>& admitted) = 0;
-    virtual int run(const std::vector<WorkItem>& items) = 0;
+    // finishing: requests whose last packets are in this launch (their
+    // results may be copied back right after it)
+    virtual int run(const std::vector<WorkItem>& items, const std::vector<Req*>& finishing) = 0;
     // copy the finished requests' results to their callers (st[i] per request)
     virtual int collect(const std::vector<Req*>& done, std::vector<int>& st) = 0;
     virtual const char* error() const = 0;
@@ -119,14 +121,14 @@ struct ServeEngine {
     double t_start = 0, busy_s = 0;
     double prepare_s = 0, launch_s = 0, collect_s = 0, sg_s = 0;
     // spectrogram worker: its own context (device buffers, stream)
-    pdv_ctx* sg_ctx = nullptr;
+    std::vector<pdv_ctx*> sg_ctx;        // one context (buffers, Mie basis, stream) per worker
     std::deque<std::shared_ptr<Req>> sg_queue;
     std::condition_variable cv_sg;
     bool sg_stop = false;
-    std::thread sg_th;
+    std::vector<std::thread> sg_th;
 
     void loop();
-    void sg_loop();
+    void sg_loop(int worker);
     void join_all();
     // final status of a request (caller holds mu)
     void finish(const std::shared_ptr<Req>& q, int st);
@@ -307,9 +309,12 @@ struct HipExecutor : Executor {
                                  (uint32_t*)queue.ptr);
         return hipfail(e, "transport launch");
     }
-    int run(const std::vector<WorkItem>& its) override {
+    std::vector<Req*> copied;    // requests whose results the last launch copied back
+    int run(const std::vector<WorkItem>& its, const std::vector<Req*>& finishing) override {
+        copied.clear();
         if (its.empty()) return PDV_OK;
         hipStream_t s = ctx->stream;
+        copied = finishing;
         std::memcpy(h_items, its.data(), sizeof(WorkItem) * its.size());
         *h_nitems = (int)its.size();
         int r;
@@ -328,13 +333,29 @@ struct HipExecutor : Executor {
         } else {
             if ((r = record(s))) return r;
         }
-        return hipfail(hipStreamSynchronize(s), "transport");
+        // the result copies of the requests this launch finishes follow it
+        // on the stream, so one wait covers both
+        if ((r = copy_results(s, finishing))) return r;
+        if (!(E->opts.watchdog_ms > 0.0)) return hipfail(hipStreamSynchronize(s), "transport");
+        // bounded wait: poll an event behind the launch and its copies
+        if ((r = hipfail(hipEventRecord(ctx->ev_b, s), "watchdog event"))) return r;
+        const double deadline = now_s() + 1e-3 * E->opts.watchdog_ms;
+        for (;;) {
+            const hipError_t q = hipEventQuery(ctx->ev_b);
+            if (q == hipSuccess) return PDV_OK;
+            if (q != hipErrorNotReady) return hipfail(q, "transport");
+            if (now_s() > deadline) {
+                ctx->poisoned = true;
+                err = "watchdog: launch still running after " + std::to_string(E->opts.watchdog_ms) + " ms";
+                return PDV_EDEVICE;
+            }
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+        }
     }
-    int collect(const std::vector<Req*>& done, std::vector<int>& st) override {
-        hipStream_t s = ctx->stream;
+    int copy_results(hipStream_t s, const std::vector<Req*>& reqs) {
         const uint64_t words = slot_tally_words(E->opts.max_bins);
         int r;
-        for (Req* q : done) {
+        for (Req* q : reqs) {
             const uint64_t off = (uint64_t)q->slot * words;
             if ((r = hipfail(hipMemcpyAsync(h_tally + off, (const uint64_t*)tallies.ptr + off,
                                             8 * tally_words(q->p.n_bins, SF_CLASS), hipMemcpyDeviceToHost, s),
@@ -344,7 +365,20 @@ struct HipExecutor : Executor {
                                             hipMemcpyDeviceToHost, s), "copy descriptor")))
                 return r;
         }
-        if ((r = hipfail(hipStreamSynchronize(s), "copy results"))) return r;
+        return PDV_OK;
+    }
+    int collect(const std::vector<Req*>& done, std::vector<int>& st) override {
+        const uint64_t words = slot_tally_words(E->opts.max_bins);
+        int r;
+        // requests the launch did not finish (cancelled ones are not
+        // collected) come back here; the others were copied after the launch
+        std::vector<Req*> late;
+        for (Req* q : done)
+            if (std::find(copied.begin(), copied.end(), q) == copied.end()) late.push_back(q);
+        if (!late.empty()) {
+            if ((r = copy_results(ctx->stream, late))) return r;
+            if ((r = hipfail(hipStreamSynchronize(ctx->stream), "copy results"))) return r;
+        }
         st.assign(done.size(), PDV_OK);
         for (size_t i = 0; i < done.size(); ++i) {
             Req* q = done[i];
@@ -372,7 +406,7 @@ struct HostExecutor : Executor {
         for (Req* q : adm) std::fill(slots[q->slot].begin(), slots[q->slot].end(), 0);
         return PDV_OK;
     }
-    int run(const std::vector<WorkItem>& its) override {
+    int run(const std::vector<WorkItem>& its, const std::vector<Req*>&) override {
         ++iter;
         if (E->opts.host_fail_iteration && iter == (uint64_t)E->opts.host_fail_iteration) {
             err = "injected executor failure";
@@ -387,8 +421,16 @@ struct HostExecutor : Executor {
             t[tw_counts(nb) + C_EXITS] += w.count;
             pk += w.count;
         }
-        if (E->opts.host_ns_per_packet > 0)
-            std::this_thread::sleep_for(std::chrono::nanoseconds((uint64_t)(E->opts.host_ns_per_packet * pk)));
+        if (E->opts.host_ns_per_packet > 0) {
+            const double ns = E->opts.host_ns_per_packet * (double)pk;
+            // a launch that outlives the watchdog is given up at the deadline
+            if (E->opts.watchdog_ms > 0.0 && ns > 1e6 * E->opts.watchdog_ms) {
+                std::this_thread::sleep_for(std::chrono::nanoseconds((uint64_t)(1e6 * E->opts.watchdog_ms)));
+                err = "watchdog: launch still running after " + std::to_string(E->opts.watchdog_ms) + " ms";
+                return PDV_EDEVICE;
+            }
+            std::this_thread::sleep_for(std::chrono::nanoseconds((uint64_t)ns));
+        }
         return PDV_OK;
     }
     int collect(const std::vector<Req*>& done, std::vector<int>& st) override {
@@ -498,16 +540,23 @@ void ServeEngine::loop() {
                 }
             }
         }
-        if (rc == PDV_OK) rc = exec->run(items);
+        std::vector<Req*> finishing;
+        if (rc == PDV_OK) {
+            std::unique_lock<std::mutex> lk(mu);
+            for (auto& q : active)
+                if (!q->cancel && q->issued >= q->p.n_packets) finishing.push_back(q.get());
+        }
+        if (rc == PDV_OK) rc = exec->run(items, finishing);
         const double t_run = now_s();
-        busy_s += t_run - t0;
-        prepare_s += t_prep - t0;
-        launch_s += t_run - t_prep;
-        ++n_iterations;
         // retire finished requests: one batched copy of their results
         std::vector<std::shared_ptr<Req>> done_now;
         {
+            // the statistics are read by pdv_serve_report under the same lock
             std::unique_lock<std::mutex> lk(mu);
+            busy_s += t_run - t0;
+            prepare_s += t_prep - t0;
+            launch_s += t_run - t_prep;
+            ++n_iterations;
             for (auto& q : active)
                 if (rc != PDV_OK || q->cancel || q->issued >= q->p.n_packets) done_now.push_back(q);
         }
@@ -516,10 +565,11 @@ void ServeEngine::loop() {
             if (rc == PDV_OK && !q->cancel) to_copy.push_back(q.get());
         std::vector<int> cst;
         if (rc == PDV_OK && !to_copy.empty()) rc = exec->collect(to_copy, cst);
-        collect_s += now_s() - t_run;
+        const double t_col = now_s();
         bool handed = false;
         {
             std::unique_lock<std::mutex> lk(mu);
+            collect_s += t_col - t_run;
             if (rc != PDV_OK && fail_msg.empty()) fail_msg = exec->error();
             size_t ci = 0;
             for (auto& q : done_now) {
@@ -572,7 +622,8 @@ void ServeEngine::finish(const std::shared_ptr<Req>& q, int st) {
 
 // Spectrogram worker: frames, beat synthesis and STFT of requests whose
 // spectrum is done, on the worker's own context and stream.
-void ServeEngine::sg_loop() {
+void ServeEngine::sg_loop(int worker) {
+    pdv_ctx* wctx = sg_ctx[worker];
     for (;;) {
         std::shared_ptr<Req> q;
         {
@@ -588,10 +639,10 @@ void ServeEngine::sg_loop() {
             }
         }
         const double t0 = now_s();
-        const int st = pdv_spectrogram_internal(sg_ctx, &q->p, &q->sg, q->sg_out);
+        const int st = pdv_spectrogram_internal(wctx, &q->p, &q->sg, q->sg_out);
         std::unique_lock<std::mutex> lk(mu);
         sg_s += now_s() - t0;
-        if (st != PDV_OK && st != PDV_EOVERFLOW && fail_msg.empty()) fail_msg = pdv_last_error(sg_ctx);
+        if (st != PDV_OK && st != PDV_EOVERFLOW && fail_msg.empty()) fail_msg = pdv_last_error(wctx);
         finish(q, st);
         cv_done.notify_all();
     }
@@ -606,11 +657,13 @@ void ServeEngine::join_all() {
         sg_stop = true;
     }
     cv_sg.notify_all();
-    if (sg_th.joinable()) sg_th.join();
-    if (sg_ctx) {
-        pdv_destroy(sg_ctx);
-        sg_ctx = nullptr;
+    for (std::thread& t : sg_th)
+        if (t.joinable()) t.join();
+    for (pdv_ctx*& c : sg_ctx) {
+        pdv_destroy(c);
+        c = nullptr;
     }
+    sg_ctx.clear();
 }
 
 void pdv_ctx::shutdown_serving() {
@@ -654,6 +707,10 @@ extern "C" int pdv_serve_start(pdv_ctx* ctx, const pdv_serve_opts* o) {
         opts.packets_per_item > (1ull << 31))
         return ctx->fail(PDV_EINVAL, "serving limits out of range");
     if (opts.precision != PDV_FP32 && opts.precision != PDV_FP64) return ctx->fail(PDV_EINVAL, "bad precision");
+    if (!(opts.watchdog_ms >= 0.0) || !std::isfinite(opts.watchdog_ms))
+        return ctx->fail(PDV_EINVAL, "watchdog_ms must be finite and >= 0");
+    if (opts.sg_workers <= 0) opts.sg_workers = 3;
+    if (opts.sg_workers > 8) return ctx->fail(PDV_EINVAL, "sg_workers must be in [1, 8]");
     if (opts.mem_budget == 0) opts.mem_budget = ctx->mem_budget ? ctx->mem_budget / 2 : (1ull << 34);
     auto E = std::make_unique<ServeEngine>();
     E->ctx = ctx;
@@ -668,20 +725,26 @@ extern "C" int pdv_serve_start(pdv_ctx* ctx, const pdv_serve_opts* o) {
         return ctx->fail(r, "serving executor: %s", msg.c_str());
     }
     if (opts.executor == PDV_EXEC_HIP) {
-        // the spectrogram worker's own context: buffers, Mie basis and stream
-        const int r = pdv_create(&E->sg_ctx, ctx->device, opts.mem_budget, nullptr);
-        if (r != PDV_OK) {
-            std::string msg = E->sg_ctx ? pdv_last_error(E->sg_ctx) : "pdv_create failed";
-            if (E->sg_ctx) pdv_destroy(E->sg_ctx);
-            E->sg_ctx = nullptr;
-            return ctx->fail(r, "serving spectrogram context: %s", msg.c_str());
+        // each spectrogram worker's own context: buffers, Mie basis and
+        // stream, so the workers' requests overlap on the device
+        for (int w = 0; w < opts.sg_workers; ++w) {
+            pdv_ctx* c = nullptr;
+            const int r = pdv_create(&c, ctx->device, opts.mem_budget, nullptr);
+            if (r != PDV_OK) {
+                std::string msg = c ? pdv_last_error(c) : "pdv_create failed";
+                if (c) pdv_destroy(c);
+                for (pdv_ctx* o2 : E->sg_ctx) pdv_destroy(o2);
+                E->sg_ctx.clear();
+                return ctx->fail(r, "serving spectrogram context: %s", msg.c_str());
+            }
+            E->sg_ctx.push_back(c);
         }
     }
     E->t_start = now_s();
     ServeEngine* raw = E.get();
     ctx->serve = std::move(E);
     raw->th = std::thread([raw] { raw->loop(); });
-    if (raw->sg_ctx) raw->sg_th = std::thread([raw] { raw->sg_loop(); });
+    for (int w = 0; w < (int)raw->sg_ctx.size(); ++w) raw->sg_th.emplace_back([raw, w] { raw->sg_loop(w); });
     return PDV_OK;
 }
 

@@ -343,6 +343,24 @@ SynthPlan synth_plan(int n_frames, int n_samples, uint64_t max_entries) {
     return P;
 }
 
+// Entry ranges of frames whose lists sit at fixed capacity: frame f's list
+// starts at f x capacity and holds min(count, capacity) entries.
+__global__ void frame_ranges_kernel(int n_frames, uint64_t capacity, const uint64_t* __restrict__ counts,
+                                    uint64_t* __restrict__ fbeg, uint64_t* __restrict__ fend) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= n_frames) return;
+    const uint64_t c = counts[f];
+    fbeg[f] = (uint64_t)f * capacity;
+    fend[f] = (uint64_t)f * capacity + (c < capacity ? c : capacity);
+}
+
+void launch_frame_ranges(hipStream_t s, int n_frames, uint64_t capacity, const uint64_t* counts, uint64_t* fbeg,
+                         uint64_t* fend) {
+    if (n_frames <= 0) return;
+    hipLaunchKernelGGL(frame_ranges_kernel, dim3((n_frames + 255) / 256), dim3(256), 0, s, n_frames, capacity, counts,
+                       fbeg, fend);
+}
+
 hipError_t launch_synth(hipStream_t s, const SynthPlan& P, int n_frames, int n_samples, const uint64_t* fbeg,
                         const uint64_t* fend, const ListEntry* rec, const float* w, const double* v,
                         const uint32_t* phase, double r_scale, float* partial, float* signal) {

@@ -40,6 +40,8 @@
 // 64-bit atomics when the block changes set or retires.  Tallies are
 // integers (weight x 2^32), so results do not depend on the launch shape.
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "pdv_device.h"
 #include "pdv_internal.h"
@@ -1079,10 +1081,37 @@ static const void* select_kernel(int precision, bool list, int kind, bool peel) 
     return kind_ptr<float, KIND_GENERIC>(list, peel);
 }
 
+// Per-kernel launch facts, set once: the dynamic LDS a kernel is allowed
+// (the attribute call is repeated only for a larger size: each call made the
+// next launch on the stream take ~0.2 ms of host time) and its resident
+// blocks per CU at a block size.
+namespace {
+std::mutex g_kmu;
+std::map<const void*, int> g_allowed_lds;
+std::map<std::pair<const void*, int>, int> g_resident;
+}  // namespace
+
 static hipError_t allow_lds(const void* k, int bytes) {
     // dynamic LDS beyond 64 KiB must be allowed per kernel
     if (bytes <= 65536) return hipSuccess;
-    return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    std::lock_guard<std::mutex> lk(g_kmu);
+    int& cur = g_allowed_lds[k];
+    if (cur >= bytes) return hipSuccess;
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess) cur = bytes;
+    return e;
+}
+
+static hipError_t resident_blocks(const void* k, int block, int* resident) {
+    std::lock_guard<std::mutex> lk(g_kmu);
+    auto it = g_resident.find({k, block});
+    if (it != g_resident.end()) {
+        *resident = it->second;
+        return hipSuccess;
+    }
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(resident, k, block, 0);
+    if (e == hipSuccess) g_resident[{k, block}] = *resident;
+    return e;
 }
 
 // Pick the guide resolution and LDS size of a launch and allow that LDS
@@ -1107,7 +1136,7 @@ hipError_t plan_transport(TransportShape& sh, int precision, bool list, int want
         sh.guide_bits = want_bits;
     } else {
         int resident = 1;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kp, sh.block, 0);
+        hipError_t e = resident_blocks(kp, sh.block, &resident);
         if (e != hipSuccess) return e;
         if (resident < 1) resident = 1;
         const int budget = std::min(lds_per_block, lds_per_cu / resident);

@@ -27,6 +27,7 @@ FP32, FP64 = 0, 1
 FLAG_CLASS_TALLIES = 1
 FLAG_DEVICE_OUTPUT = 2
 FLAG_PEEL = 4
+FLAG_ACCUMULATE = 8
 SCALE = 4294967296.0
 
 
@@ -321,6 +322,26 @@ class Context:
                         "albedo": outs[i].albedo, "g": outs[i].g})
         return res
 
+    def spectrum_resume(self, p: dict, ckpt: dict) -> dict:
+        """Checkpoint and resume (PDV_FLAG_ACCUMULATE): transport p's
+        packets and add their tallies and counters to the checkpoint ckpt,
+        a result of earlier calls (or load_checkpoint()) over other packets
+        of the same set."""
+        keep = []
+        nb = int(p["n_bins"])
+        W = np.array(ckpt["w_fx"], dtype=np.uint64)
+        W2 = np.array(ckpt["w2_fx"], dtype=np.uint64)
+        assert W.shape == (nb,) and W2.shape == (nb,), "checkpoint of another bin count"
+        out = SpectrumOut()
+        out.w_fx, out.w2_fx = W.ctypes.data, W2.ctypes.data
+        for k, name in enumerate(SINK_NAMES):
+            out.sinks_fx[k] = int(ckpt["sinks_fx"][name])
+        for name in COUNTER_NAMES:
+            setattr(out.counters, name, int(ckpt["counts"][name]))
+        cp = make_params(dict(p, flags=int(p.get("flags", 0)) | FLAG_ACCUMULATE), keep)
+        self._check(self.lib.pdv_spectrum(self.h, ctypes.byref(cp), ctypes.byref(out)))
+        return _result(out, W, W2, None, nb)
+
     def spectrum(self, p: dict, class_tallies: bool = False, peel: bool = False) -> dict:
         return self.spectrum_batch([p], class_tallies=class_tallies, peel=peel)[0]
 
@@ -498,6 +519,24 @@ def _beat_synthesize(self, lists, wavelength: float, fs: float, n_samples: int) 
     return out
 
 
+def save_checkpoint(path: str, res: dict, next_pid: int) -> None:
+    """Write the integer tallies and counters of a (partial) spectrum and the
+    first packet id still to run (NumPy .npz, no pickled objects)."""
+    np.savez(path, w_fx=np.asarray(res["w_fx"], np.uint64), w2_fx=np.asarray(res["w2_fx"], np.uint64),
+             sinks_fx=np.array([res["sinks_fx"][n] for n in SINK_NAMES], np.uint64),
+             counts=np.array([res["counts"][n] for n in COUNTER_NAMES], np.uint64),
+             next_pid=np.array([next_pid], np.uint64))
+
+
+def load_checkpoint(path: str) -> tuple:
+    """(checkpoint dict for Context.spectrum_resume, next packet id)."""
+    z = np.load(path, allow_pickle=False)
+    ck = {"w_fx": z["w_fx"], "w2_fx": z["w2_fx"],
+          "sinks_fx": {n: int(v) for n, v in zip(SINK_NAMES, z["sinks_fx"])},
+          "counts": {n: int(v) for n, v in zip(COUNTER_NAMES, z["counts"])}}
+    return ck, int(z["next_pid"][0])
+
+
 def _dptr(x) -> int:
     """Device address of a torch tensor (or an integer address)."""
     return int(x.data_ptr()) if hasattr(x, "data_ptr") else int(x)
@@ -541,7 +580,8 @@ class ServeOpts(ctypes.Structure):
                 ("packets_per_item", ctypes.c_uint64), ("max_layers", ctypes.c_int32),
                 ("max_angles", ctypes.c_int32), ("max_bins", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("executor", ctypes.c_int32),
-                ("host_fail_iteration", ctypes.c_int32), ("host_ns_per_packet", ctypes.c_double)]
+                ("host_fail_iteration", ctypes.c_int32), ("host_ns_per_packet", ctypes.c_double),
+                ("watchdog_ms", ctypes.c_double), ("sg_workers", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -621,15 +661,26 @@ class Server:
             raise PdvError(-6, "serving session stopped")
         return self.h
 
-    def submit(self, p: dict, sg: dict | None = None) -> Ticket:
+    def submit(self, p: dict, sg: dict | None = None, ckpt: dict | None = None) -> Ticket:
+        """Queue a request; ckpt: a checkpoint its tallies are added to
+        (PDV_FLAG_ACCUMULATE)."""
         self._handle()
         keep = []
         req = Request()
+        if ckpt is not None:
+            p = dict(p, flags=int(p.get("flags", 0)) | FLAG_ACCUMULATE)
         req.params = make_params(p, keep)
         nb = int(p["n_bins"])
         W, W2 = np.zeros(nb, dtype=np.uint64), np.zeros(nb, dtype=np.uint64)
         out = SpectrumOut()
         out.w_fx, out.w2_fx = W.ctypes.data, W2.ctypes.data
+        if ckpt is not None:
+            W[:] = ckpt["w_fx"]
+            W2[:] = ckpt["w2_fx"]
+            for k, name in enumerate(SINK_NAMES):
+                out.sinks_fx[k] = int(ckpt["sinks_fx"][name])
+            for name in COUNTER_NAMES:
+                setattr(out.counters, name, int(ckpt["counts"][name]))
         keep += [out, W, W2]
         req.out = ctypes.pointer(out)
         sg_bufs = None

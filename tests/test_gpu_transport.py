@@ -316,3 +316,23 @@ def test_autotune_is_result_invariant(ctx, tmp_path):
     for a, b in zip(ref, tuned):
         assert np.array_equal(a["w_fx"], b["w_fx"]) and a["sinks_fx"] == b["sinks_fx"]
     ctx.lib.pdv_set_launch_defaults(ctx.h, pdv.LaunchOpts(0, 0, 0, -1, 0))
+
+
+def test_resume_from_checkpoint(ctx, tmp_path):
+    """Checkpoint and resume: the Mie cloud's packets [0, k) saved to disk,
+    read back, and [k, N) added to them (PDV_FLAG_ACCUMULATE) equal one run
+    over [0, N) bit for bit; twice, across a ragged split."""
+    from paper_2012_00963_amd import pdv
+    p = wl.large_mie(400_003)
+    whole = ctx.spectrum(p)
+    ck = None
+    cuts = [0, 123_457, 300_000, p["n_packets"]]
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        part = dict(p, pid_begin=a, n_packets=b - a)
+        r = ctx.spectrum(part) if ck is None else ctx.spectrum_resume(part, ck)
+        path = str(tmp_path / ("ckpt_%d.npz" % b))
+        pdv.save_checkpoint(path, r, next_pid=b)
+        ck, nxt = pdv.load_checkpoint(path)
+        assert nxt == b
+    assert np.array_equal(ck["w_fx"], whole["w_fx"]) and np.array_equal(ck["w2_fx"], whole["w2_fx"])
+    assert ck["sinks_fx"] == whole["sinks_fx"] and ck["counts"] == whole["counts"]

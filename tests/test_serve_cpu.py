@@ -145,3 +145,45 @@ def test_submit_checks():
     s.stop()
     with pytest.raises(pdv.PdvError):
         s.submit(req(10))                       # not serving any more
+
+
+def test_watchdog_fails_a_launch_that_overruns():
+    """A launch still running at the watchdog deadline fails every request
+    with PDV_EDEVICE from the host side (the host executor simulates a
+    100 ms launch against a 20 ms watchdog)."""
+    s = pdv.Server(max_active=4, packets_per_iteration=1 << 17, packets_per_item=1 << 17,
+                   host_ns_per_packet=1000.0, watchdog_ms=20.0)
+    t0 = time.perf_counter()
+    tk = s.submit(req(100_000))
+    assert s.poll(tk, wait_ms=-1) == -3
+    assert time.perf_counter() - t0 < 0.09          # given up at the deadline, not after the launch
+    assert s.stop() == -3
+    assert "watchdog" in s.last_error
+    # a launch inside the limit is unaffected
+    ok = pdv.Server(max_active=4, host_ns_per_packet=10.0, watchdog_ms=200.0)
+    tk = ok.submit(req(50_000))
+    assert ok.poll(tk, wait_ms=-1) == 0 and tk.result()["counts"]["packets"] == 50_000
+    assert ok.stop() == 0
+    with pytest.raises(pdv.PdvError):
+        pdv.Server(watchdog_ms=-1.0)
+
+
+def test_resume_from_checkpoint(tmp_path):
+    """Checkpoint and resume (PDV_FLAG_ACCUMULATE) through the serving path:
+    packets [0, k) saved to disk, read back, [k, N) added to them, equals one
+    request over [0, N) in every tally word and counter."""
+    s = pdv.Server(max_active=4, packets_per_iteration=1 << 14, packets_per_item=1 << 12)
+    n, k = 90_001, 37_123
+    whole = s.submit(req(n))
+    first = s.submit(req(k))
+    assert s.poll(whole, wait_ms=-1) == 0 and s.poll(first, wait_ms=-1) == 0
+    path = str(tmp_path / "ckpt.npz")
+    pdv.save_checkpoint(path, first.result(), next_pid=k)
+    ck, nxt = pdv.load_checkpoint(path)
+    assert nxt == k
+    rest = s.submit(req(n - k, pid_begin=nxt), ckpt=ck)
+    assert s.poll(rest, wait_ms=-1) == 0
+    a, b = rest.result(), whole.result()
+    assert np.array_equal(a["w_fx"], b["w_fx"]) and np.array_equal(a["w2_fx"], b["w2_fx"])
+    assert a["sinks_fx"] == b["sinks_fx"] and a["counts"] == b["counts"]
+    s.stop()
