@@ -584,7 +584,7 @@ def main(argv=None):
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     ctx = pdv.Context(0)
     if args.serve_only:
-        print(json.dumps(serve_leg(ctx, duration=args.serve_duration)), flush=True)
+        print(json.dumps(serve_leg(ctx, duration=args.serve_duration, check_oracle=not args.no_cpu)), flush=True)
         return 0
     if args.profile_case:
         return profile_case(ctx, args.profile_case, args.steps, args.warmup)
