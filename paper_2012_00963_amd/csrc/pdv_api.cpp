@@ -587,13 +587,18 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
     h_items.clear();
     for (int i : order) {
         const pdv_params& p = sets[i];
-        for (uint64_t s = 0; s < p.n_packets; s += o.packets_per_item) {
+        // items never cross a multiple of 2^32 packet ids (a list-writing
+        // launch forms detected entries' phase words with one high id word
+        // per item)
+        for (uint64_t s = 0; s < p.n_packets;) {
             WorkItem w;
             w.set = (uint32_t)i;
             w.pad = 0;
             w.pid_begin = p.pid_begin + s;
-            w.count = std::min<uint64_t>(o.packets_per_item, p.n_packets - s);
+            const uint64_t to_wrap = (1ull << 32) - (w.pid_begin & 0xffffffffull);
+            w.count = std::min<uint64_t>(std::min<uint64_t>(o.packets_per_item, p.n_packets - s), to_wrap);
             h_items.push_back(w);
+            s += w.count;
         }
     }
     const int n_items = (int)h_items.size();
@@ -629,7 +634,12 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
 
     // ---- tables ----
     launch_layer_tables(s, n_layer_jobs, layer_jobs.ptr, (const double*)density.ptr, (uint8_t*)tables.ptr);
-    // caller phase tables and Mie sets
+    // caller phase tables and Mie sets.  Every group's jobs sit in their own
+    // range of h_phase (reserved, so it never moves while a copy from it may
+    // be in flight) and of the device job array; the host does not wait here
+    // (stream order: a group's kernel reads its basis before a later
+    // group's basis kernels rewrite it)
+    h_phase.reserve(n);
     for (int i = 0; i < n; ++i) {
         const pdv_params& p = sets[i];
         if (h_src[i] != i) continue;
@@ -640,19 +650,21 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
             h_phase.push_back(J);
         }
     }
-    if (!h_phase.empty()) {
-        if ((r = hip_check(H2D(phase_jobs.ptr, h_phase.data(), sizeof(PhaseJob) * h_phase.size()), "copy jobs")))
-            return r;
-        launch_phase_cdf(s, (int)h_phase.size(), phase_jobs.ptr, 0, nullptr, nullptr, (uint8_t*)tables.ptr,
-                         (SetDesc*)descs.ptr, 0);
-        if ((r = hip_check(hipStreamSynchronize(s), "table kernels"))) return r;
-    }
+    auto launch_group = [&](size_t g0, int n_nodes, const void* info, const double* basis, int n_angles) {
+        const size_t ng = h_phase.size() - g0;
+        if (ng == 0) return (int)PDV_OK;
+        PhaseJob* dj = (PhaseJob*)phase_jobs.ptr + g0;
+        if (int e = hip_check(H2D(dj, h_phase.data() + g0, sizeof(PhaseJob) * ng), "copy jobs")) return e;
+        launch_phase_cdf(s, (int)ng, dj, n_nodes, info, basis, (uint8_t*)tables.ptr, (SetDesc*)descs.ptr, n_angles);
+        return hip_check(hipGetLastError(), "phase table kernels");
+    };
+    if ((r = launch_group(0, 0, nullptr, nullptr, 0))) return r;
     // Mie sets grouped by optics key (one cached basis at a time)
     std::vector<char> done(n, 0);
     for (int i = 0; i < n; ++i) {
         if (sets[i].phase_kind != PDV_PHASE_MIE || done[i] || h_src[i] != i) continue;
         if ((r = ensure_mie_basis(sets[i]))) return r;
-        h_phase.clear();
+        const size_t g0 = h_phase.size();
         for (int j = i; j < n; ++j) {
             const pdv_params& p = sets[j];
             if (p.phase_kind != PDV_PHASE_MIE || done[j] || h_src[j] != j) continue;
@@ -662,11 +674,7 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
             h_phase.push_back(J);
             done[j] = 1;
         }
-        if ((r = hip_check(H2D(phase_jobs.ptr, h_phase.data(), sizeof(PhaseJob) * h_phase.size()), "copy jobs")))
-            return r;
-        launch_phase_cdf(s, (int)h_phase.size(), phase_jobs.ptr, mie_nodes, mie_info.ptr,
-                         (const double*)mie_basis.ptr, (uint8_t*)tables.ptr, (SetDesc*)descs.ptr, mie_key.n_angles);
-        if ((r = hip_check(hipStreamSynchronize(s), "mie phase kernels"))) return r;
+        if ((r = launch_group(g0, mie_nodes, mie_info.ptr, (const double*)mie_basis.ptr, mie_key.n_angles))) return r;
     }
 
     if (n_unique < n) launch_copy_desc_fields(s, (SetDesc*)descs.ptr, (const int*)dup_src.ptr, n);

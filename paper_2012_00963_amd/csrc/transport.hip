@@ -605,7 +605,14 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
     // append the staged entries to set's list: one atomic reserves the slots,
     // lane i copies entry i (entries past the list's capacity are counted,
     // not stored)
-    auto flush_list = [&](int set) {
+    // Staged entries hold the packet id's low word in place of the phase
+    // word; the flush forms each entry's phase word (the packet's Philox
+    // block with event counter 0xFFFFFFFF), one lane per entry, so the block
+    // is drawn once per staged detection instead of by the whole wave in
+    // every retire round that has one.  pid_hi: the high word of every
+    // packet id of the current work item (items do not cross a multiple of
+    // 2^32).
+    auto flush_list = [&](int set, uint32_t pid_hi) {
         if (l_fill == 0) return;
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -614,8 +621,13 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
         if (lane == 0) base = atomicAdd((unsigned long long*)(list_counts + set), (unsigned long long)l_fill);
         base = __shfl(base, 0, 64);
         if ((uint32_t)lane < l_fill) {
+            ListEntry e = sL[lane];
+            const uint32_t k0 = (uint32_t)(d.seed & 0xffffffffu), k1 = (uint32_t)(d.seed >> 32);
+            uint32_t p0, p1;
+            philox_packet_words(e.phase, pid_hi, k0, p0, p1);
+            e.phase = philox10_event(0xffffffffu, p0, p1, d.stream ^ k1, k0, k1).x;
             const unsigned long long slot = base + (unsigned long long)lane;
-            if (slot < d.list_capacity) lists[d.list_offset + slot] = sL[lane];
+            if (slot < d.list_capacity) lists[d.list_offset + slot] = e;
         }
         __builtin_amdgcn_wave_barrier();
         l_fill = 0;
@@ -789,10 +801,9 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                     }
                     if constexpr (LIST) {
                         if (detected) {
-                            const Block4 P = philox10_event(0xffffffffu, q0, q1, c.stream ^ c.k1, c.k0, c.k1);
                             det_now = true;
                             e_w = (float)w;
-                            e_phase = P.x;
+                            e_phase = (uint32_t)pid;       // the phase word is formed at the flush
                             e_v = vt;
                         }
                     }
@@ -813,7 +824,7 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                     const uint64_t dm = __ballot(det_now);
                     if (dm != 0ull) {
                         const uint32_t n_new = (uint32_t)__popcll(dm);
-                        if (l_fill + n_new > (uint32_t)LIST_STAGE) flush_list(set);
+                        if (l_fill + n_new > (uint32_t)LIST_STAGE) flush_list(set, (uint32_t)(pid0 >> 32));
                         if (det_now) {
                             const uint32_t r = __builtin_amdgcn_mbcnt_hi(
                                 (uint32_t)(dm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)dm, 0u));
@@ -995,7 +1006,7 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
         }
         // the item's staged detections go out before the next item (which
         // may belong to another set)
-        if constexpr (LIST) flush_list(set);
+        if constexpr (LIST) flush_list(set, (uint32_t)(pid0 >> 32));
         __syncthreads();
     }
     if (cur_set >= 0) flush_set(cur_set);

@@ -239,3 +239,35 @@ def test_spectrogram_full_size_sampled_frames(ctx, oracle_mc):
         # one flipped entry moves a frame by about one packet amplitude
         # (1/sqrt(5.4e4 entries) = 4e-3 of it)
         assert e <= 2e-2, (k, e)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_spectrogram_lists_across_pid_word_boundary(ctx, oracle_mc, precision):
+    """Frames whose packet ids run across a multiple of 2^32: the high id word
+    changes inside a frame, and every detected entry's phase word (the
+    packet's Philox block with event counter 0xFFFFFFFF) still equals the
+    oracle's, so the lists match entry by entry."""
+    p, sg = wl.spectrogram_case(n_frames=3, packets_per_frame=60_000)
+    p = dict(p, precision=precision, pid_begin=(1 << 32) - 25_000)
+    sg = dict(sg, n_samples=6_000, list_capacity=20_000)
+    g = ctx.spectrogram(p, sg, want_lists=True)
+    assert not g["overflow"]
+    tabs = oracle_mc.set_tables(p)
+    flipped = 0
+    for k in range(sg["n_frames"]):
+        pk = dict(p, stream=p["stream"] + k, n_packets=sg["packets_per_frame"])
+        Lo = oracle_mc.run(pk, tabs=tabs, list_capacity=sg["list_capacity"], pid_begin=p["pid_begin"])["list"]
+        Lg = g["lists"][k]
+        po = np.round(Lo["phase"] * 2**32).astype(np.uint64)
+        ko = {int(x): i for i, x in enumerate(po)}
+        hits = 0
+        for j, ph in enumerate(Lg["phase_u32"]):
+            i = ko.get(int(ph))
+            if i is None:
+                flipped += 1
+                continue
+            hits += 1
+            assert abs(Lg["w"][j] - Lo["w"][i]) <= 1e-6 * Lo["w"][i] + 1e-9
+        flipped += len(Lo["w"]) - hits
+        assert hits > 100, hits
+    assert flipped <= (3 if precision == 0 else 0), flipped
