@@ -534,15 +534,18 @@ __device__ __forceinline__ Real peel_weight(const SetConst<Real>& c, const typen
 // from ballots when the wave retires packets); collisions, surface hits and
 // the absorbed weight (fixed point) are per-lane sums, reduced across the
 // wave when the block changes set or retires.
-struct WaveAcc {
-    uint64_t packets, exits, detected;
-};
+// A lane's running sums over the packets it finished in the current set.
+// Packet, exit and detection counts are not kept per lane or per wave: a
+// block adds each work item's packet count when it takes the item, the rare
+// outcomes (a detection, a packet that ends inside the cloud) add one to a
+// block counter in their own branch, and the exits are the packets less
+// those that ended inside, formed at the set's flush.
 struct LaneAcc {
     uint64_t abs_particle, abs_surface;
     uint32_t collisions, surface;
 };
 
-__device__ __forceinline__ void flush_acc(LaneAcc& a, WaveAcc& w, uint64_t* tally, int n_bins) {
+__device__ __forceinline__ void flush_acc(LaneAcc& a, uint64_t* tally, int n_bins) {
     const uint64_t s_ap = wave_sum_u64(a.abs_particle);
     const uint64_t s_as = wave_sum_u64(a.abs_surface);
     const uint64_t c_c = wave_sum_u64(a.collisions);
@@ -552,14 +555,10 @@ __device__ __forceinline__ void flush_acc(LaneAcc& a, WaveAcc& w, uint64_t* tall
         if (s_ap) atomicAdd(sk + SK_ABS_PARTICLE, (unsigned long long)s_ap);
         if (s_as) atomicAdd(sk + SK_ABS_SURFACE, (unsigned long long)s_as);
         unsigned long long* ct = (unsigned long long*)(tally + tw_counts(n_bins));
-        if (w.packets) atomicAdd(ct + C_PACKETS, (unsigned long long)w.packets);
         if (c_c) atomicAdd(ct + C_COLLISIONS, (unsigned long long)c_c);
         if (c_s) atomicAdd(ct + C_SURFACE, (unsigned long long)c_s);
-        if (w.exits) atomicAdd(ct + C_EXITS, (unsigned long long)w.exits);
-        if (w.detected) atomicAdd(ct + C_DETECTED, (unsigned long long)w.detected);
     }
     a = LaneAcc{0, 0, 0, 0};
-    w = WaveAcc{0, 0, 0};
 }
 
 // Occupancy targets: the specialised FP32 kernels fit eight waves per SIMD
@@ -578,6 +577,9 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
     __shared__ WorkItem s_item;
     __shared__ int s_item_idx;
     __shared__ uint32_t s_next;
+    // the current set's packets taken by this block (written by thread 0),
+    // how many of them were detected and how many ended inside the cloud
+    __shared__ unsigned long long s_packets, s_detected, s_ended;
 
     const LdsLayout L = lds_layout((int)sizeof(Real), max_layers, max_cells, max_bins, guide_bits,
                                    LIST ? (int)(blockDim.x >> 6) : 0, PEEL, (int)blockDim.x);
@@ -634,13 +636,26 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
     };
     int cur_set = -1;
     LaneAcc acc = LaneAcc{0, 0, 0, 0};
-    WaveAcc wacc = WaveAcc{0, 0, 0};
+    if (tid == 0) {
+        s_packets = 0ull;
+        s_detected = 0ull;
+        s_ended = 0ull;
+    }
 
     auto flush_set = [&](int set) {
         const SetDesc& d = descs[set];
         uint64_t* tally = tallies + d.tally_offset;
-        flush_acc(acc, wacc, tally, d.n_bins);
+        flush_acc(acc, tally, d.n_bins);
         __syncthreads();
+        if (tid == 0) {
+            unsigned long long* ct = (unsigned long long*)(tally + tw_counts(d.n_bins));
+            if (s_packets) atomicAdd(ct + C_PACKETS, s_packets);
+            if (s_packets - s_ended) atomicAdd(ct + C_EXITS, s_packets - s_ended);
+            if (s_detected) atomicAdd(ct + C_DETECTED, s_detected);
+            s_packets = 0ull;
+            s_detected = 0ull;
+            s_ended = 0ull;
+        }
         unsigned long long* gW = (unsigned long long*)(tally + tw_w(d.n_bins));
         unsigned long long* gW2 = (unsigned long long*)(tally + tw_w2(d.n_bins));
         unsigned long long* gS = (unsigned long long*)(tally + tw_sinks(d.n_bins));
@@ -739,6 +754,7 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
             __syncthreads();
         }
 
+        if (tid == 0) s_packets += count;    // read only by thread 0, at the set's flush
         const SetConst<Real> c = load_const<Real>(descs[set]);
         const int nb = c.n_bins;
         uint32_t chunk = count / (2u * (uint32_t)(nthr >> 6));
@@ -763,9 +779,6 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
             // wave's range, claiming a new range from the item when it runs out.
             const uint64_t idle = __ballot(st != ST_ALIVE);
             if (idle == ~0ull || (!exhausted && (int)__popcll(idle) >= retire_min)) {
-                wacc.packets += (uint64_t)__popcll(__ballot(st >= ST_EXIT));
-                wacc.exits += (uint64_t)__popcll(__ballot(st == ST_EXIT));
-                wacc.detected += (uint64_t)__popcll(__ballot(st == ST_EXIT && mu >= c.cos_cone));
                 bool det_now = false;        // this lane's packet goes to the detected list
                 float e_w = 0.f;
                 uint32_t e_phase = 0;
@@ -781,11 +794,13 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                         if constexpr (sizeof(Real) == 8) bf = floor((vt - c.v_lo) / c.dv);
                         else bf = floor((vt - c.v_lo) * c.inv_dv);
                         slot = bf < 0.0 ? nb + SK_UNDER : (bf >= (double)nb ? nb + SK_OVER : (int)bf);
+                        atomicAdd(&s_detected, 1ull);
+                    } else if (st == ST_EXIT) {
+                        slot = nb + SK_UNDETECTED;
                     } else {
-                        slot = nb + (st == ST_EXIT ? SK_UNDETECTED
-                                                   : (st == ST_TRUNC ? SK_TRUNCATED
-                                                                     : (st == ST_ABS_SURF ? SK_ABS_SURFACE
-                                                                                          : SK_ABS_PARTICLE)));
+                        slot = nb + (st == ST_TRUNC ? SK_TRUNCATED
+                                                    : (st == ST_ABS_SURF ? SK_ABS_SURFACE : SK_ABS_PARTICLE));
+                        atomicAdd(&s_ended, 1ull);
                     }
                     const uint64_t fw = to_fixed32<Real>(w);
                     if (slot == nb + SK_UNDETECTED) sU[tid] += (unsigned long long)fw;
