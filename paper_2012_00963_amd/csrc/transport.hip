@@ -573,6 +573,13 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                  ListEntry* __restrict__ lists, uint64_t* __restrict__ list_counts,
                  const int* __restrict__ n_items_dev, int guide_bits, int retire_min) {
     extern __shared__ __align__(16) uint8_t lds[];
+    // Packets on a uniform slab under the HG law scatter about 1.5 times on
+    // average, so a whole round spent on each packet's final flight out of
+    // the cloud is a large share of the work: this kind draws and tests every
+    // next flight at the end of the event before it (the same blocks, the
+    // same arithmetic, the same decisions).  The first flight is drawn when
+    // the packet starts, for all packets of a retire round together.
+    constexpr bool LOOKAHEAD = KIND == KIND_HG_UNIFORM && !PEEL && sizeof(Real) == 4;
     if (n_items_dev) n_items = *n_items_dev;   // item count from device memory (graph replays)
     __shared__ WorkItem s_item;
     __shared__ int s_item_idx;
@@ -772,6 +779,22 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
         uint32_t k = 0;
         int n_sc = 0, n_surf = 0;
         Real T = 0, mu = -1, w = 1, big = 0, small = 0, abs_s = 0;
+        // look-ahead kinds: the next flight's depth and the block words the
+        // next event uses, drawn at the end of the previous event
+        uint32_t cy = 0, cz = 0;
+        Real Tc = 0;
+        // draws the packet's next Philox block into X_ and returns the
+        // optical depth the flight from T_ along mu_ reaches (eq. 10: the
+        // path length in optical depth is -ln u)
+        auto draw_flight = [&](Real mu_, Real T_, Block4& X_) -> Real {
+            // the key enters opaquely each event, so the ten round keys are
+            // recomputed on the scalar unit rather than held in 20 SGPRs
+            uint32_t key0 = c.k0, key1 = c.k1;
+            asm volatile("" : "+s"(key0), "+s"(key1));
+            X_ = philox10_event(k, q0, q1, c.stream ^ key1, key0, key1);
+            k += 1;
+            return M<Real>::fma(-M<Real>::neg_log(unit_open<Real>(X_.x)), mu_, T_);
+        };
 
         while (true) {
             // Retire and refill in rounds: when retire_min lanes wait (or all
@@ -882,20 +905,34 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                     w_next += take;
                     empty = __ballot(st == ST_EMPTY);
                 }
+                if constexpr (LOOKAHEAD) {
+                    // the first flight of each packet started in this round
+                    // (downward from the top: it never leaves)
+                    if (st == ST_ALIVE && k == 0u) {
+                        Block4 Y;
+                        Tc = draw_flight(mu, T, Y);
+                        cy = Y.y;
+                        cz = Y.z;
+                    }
+                }
                 if (__ballot(st == ST_ALIVE) == 0ull) break;
             }
             if (st == ST_ALIVE) {
-            // the key enters opaquely each event, so the ten round keys are
-            // recomputed on the scalar unit rather than held in 20 SGPRs
-            uint32_t key0 = c.k0, key1 = c.k1;
-            asm volatile("" : "+s"(key0), "+s"(key1));
-            const Block4 X = philox10_event(k, q0, q1, c.stream ^ key1, key0, key1);
-            k += 1;
-            const Real u0 = unit_open<Real>(X.x);
+            Block4 X;
+            Real Tn;
+            bool leave;
+            if constexpr (LOOKAHEAD) {
+                // the flight was drawn when the previous event ended (or at the
+                // packet's start) and stays inside the cloud
+                X = Block4{0u, cy, cz, 0u};
+                Tn = Tc;
+                leave = false;
+            } else {
+                Tn = draw_flight(mu, T, X);
+                leave = mu > (Real)0 && Tn <= (Real)0;
+            }
             const Real u1 = unit_open<Real>(X.y);
             const Real u2 = unit_open<Real>(X.z);
-            const Real Tn = M<Real>::fma(-M<Real>::neg_log(u0), mu, T);
-            const bool leave = mu > (Real)0 && Tn <= (Real)0;
             const bool surf = mu < (Real)0 && Tn >= c.tau;
             const bool coll = !leave && !surf;
 
@@ -1014,6 +1051,15 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                 small = M<Real>::fma((Real)0.5 * V, omc, small);
                 mu = mu_new;
                 T = surf ? c.tau : Tn;
+                if constexpr (LOOKAHEAD) {
+                    // the next flight now: a packet that leaves the cloud ends
+                    // in this round instead of spending another on the flight
+                    Block4 Y;
+                    Tc = draw_flight(mu, T, Y);
+                    cy = Y.y;
+                    cz = Y.z;
+                    if (mu > (Real)0 && Tc <= (Real)0) st = ST_EXIT;
+                }
             } else {
                 st = leave ? ST_EXIT : (trunc ? ST_TRUNC : (surf ? ST_ABS_SURF : ST_ABS_PART));
             }
