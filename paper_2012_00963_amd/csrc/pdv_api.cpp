@@ -480,12 +480,18 @@ void pdv_ctx::default_opts(pdv_launch_opts& o, uint64_t total_packets, int n_set
         o.retire_batch = tuned.retire_batch > 0 ? tuned.retire_batch
                                                 : (fp64 ? 1 : (list ? 24 : (kind == KIND_HG_UNIFORM ? 32 : 16)));
     if (o.packets_per_item == 0) {
-        // three large items per block, rounded up so that the item count
+        // a few large items per block, rounded up so that the item count
         // does not spill into a further round: every item ends with a block
         // barrier that waits for the block's longest packet, and the pull of
-        // the last items evens out the blocks' finishing times
+        // the last items evens out the blocks' finishing times.  Three per
+        // block for spectra (1 / 2 / 3 / 4 / 6 on the 1e8-packet HG slab:
+        // 0.94 / 0.97 / 0.91 / 0.99 / 1.01 ms); two for list-writing launches,
+        // whose sets (the frames of a spectrogram) each take a block's
+        // tables and tallies anew (256 frames of 1e6 packets: 2.13 / 1.98 /
+        // 2.05 / 2.01 / 2.06 ms)
         uint64_t grid = (uint64_t)n_cu * (uint64_t)o.blocks_per_cu;
-        uint64_t ppi = (total_packets + 3 * grid - 1) / (3 * grid);
+        const uint64_t per_block = list ? 2 : 3;
+        uint64_t ppi = (total_packets + per_block * grid - 1) / (per_block * grid);
         ppi = std::max<uint64_t>(ppi, 1024);
         ppi = std::min<uint64_t>(ppi, 1ull << 18);
         o.packets_per_item = tuned.packets_per_item > 0 ? tuned.packets_per_item : ppi;
@@ -587,18 +593,26 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
     h_items.clear();
     for (int i : order) {
         const pdv_params& p = sets[i];
-        // items never cross a multiple of 2^32 packet ids (a list-writing
-        // launch forms detected entries' phase words with one high id word
-        // per item)
-        for (uint64_t s = 0; s < p.n_packets;) {
-            WorkItem w;
-            w.set = (uint32_t)i;
-            w.pad = 0;
-            w.pid_begin = p.pid_begin + s;
-            const uint64_t to_wrap = (1ull << 32) - (w.pid_begin & 0xffffffffull);
-            w.count = std::min<uint64_t>(std::min<uint64_t>(o.packets_per_item, p.n_packets - s), to_wrap);
-            h_items.push_back(w);
-            s += w.count;
+        // the set's packets in equal items of at most packets_per_item
+        // (sizes differ by one at most: no short remainder that leaves its
+        // block idle at the end); items never cross a multiple of 2^32
+        // packet ids (a list-writing launch forms detected entries' phase
+        // words with one high id word per item)
+        const uint64_t n_it = (p.n_packets + o.packets_per_item - 1) / o.packets_per_item;
+        const uint64_t even = n_it ? p.n_packets / n_it : 0, extra = n_it ? p.n_packets % n_it : 0;
+        uint64_t off = 0;
+        for (uint64_t j = 0; j < n_it; ++j) {
+            for (uint64_t len = even + (j < extra ? 1 : 0); len > 0;) {
+                WorkItem w;
+                w.set = (uint32_t)i;
+                w.pad = 0;
+                w.pid_begin = p.pid_begin + off;
+                const uint64_t to_wrap = (1ull << 32) - (w.pid_begin & 0xffffffffull);
+                w.count = std::min<uint64_t>(len, to_wrap);
+                h_items.push_back(w);
+                off += w.count;
+                len -= w.count;
+            }
         }
     }
     const int n_items = (int)h_items.size();
