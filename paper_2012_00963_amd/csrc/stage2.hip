@@ -11,19 +11,21 @@
 // (Sec. I, Fig. 1): periodic Hann window of nfft samples every hop samples.
 //
 // Kernels:
-//   synth_tile      one block per (sample tile, frame, group of entry chunks):
+//   synth_tile      one wave per (sample tile, frame, group of entry chunks):
 //                   the group's entries are staged in LDS a chunk at a time
-//                   and every thread accumulates a run of consecutive samples
+//                   and every lane accumulates a run of consecutive samples
 //                   of the tile; at the run's first sample the phase
 //                   f n / fs + phi0 is formed with an FP64 fused multiply-add
 //                   and reduced to [0,1) in FP64 (records reach tens of
 //                   thousands of cycles), its cosine and sine taken in FP32
-//                   on the revolution-argument hardware unit; each further
-//                   sample of the run rotates that pair by the entry's phase
-//                   step per sample (cos and sin of 2 pi frac(f / fs), formed
-//                   in FP64 when the entry is staged).  With one group the
-//                   block writes the record itself; otherwise each group
-//                   writes a partial record;
+//                   on the revolution-argument hardware unit; the further
+//                   samples of the run follow from the three-term recurrence
+//                   of cos(x + q theta) in Reinsch's difference form
+//                   (d += -4 sin^2(theta/2) c, c += d: two operations per
+//                   sample, accurate for small steps theta), whose constants
+//                   are formed in FP64 when the entry is staged.  With one
+//                   group the block writes the record itself; otherwise each
+//                   group writes a partial record;
 //   synth_reduce    sums the groups' partial records in group order
 //                   (deterministic);
 //   stft_kernel     one block per window: real FFT of nfft points through an
@@ -69,10 +71,11 @@ float* synth_scratch(int device) {
     return g_scratch[device];
 }
 
-constexpr int SYNTH_CHUNK = 1024;       // entries staged in LDS at a time
-constexpr int SYNTH_THREADS = 128;
-constexpr int SYNTH_RUN = 4;            // consecutive samples per thread
-constexpr int SYNTH_TILE = SYNTH_RUN * SYNTH_THREADS;
+constexpr int SYNTH_CHUNK = 256;        // entries staged in LDS at a time (8 KB)
+constexpr int SYNTH_THREADS = 64;       // one wave per block
+constexpr int SYNTH_HALF = SYNTH_THREADS / 2;
+constexpr int SYNTH_RUN = 16;           // consecutive samples per lane, at most
+constexpr int SYNTH_TILE = SYNTH_RUN * SYNTH_HALF;
 
 // Where the entries come from: an array of ListEntry records (lists written
 // by the transport, or packed from host arrays), or three separate arrays.
@@ -99,13 +102,24 @@ __device__ __forceinline__ void load_entry(const EntrySrc& src, uint64_t i, floa
 
 // The chunks [c0, c1) of frame entries starting at e_begin (n_entries in
 // all), accumulated over the NQ consecutive samples j0 .. j0 + NQ - 1 of the
-// frame (absolute sample index n0 for j0).  Every thread of the block takes
-// part in the staging; threads whose run starts past the frame's samples
-// only stage.
+// frame (absolute sample index n0 for j0).  The two half-waves cover the
+// same samples and take alternate entries (lane l and lane l + 32 hold the
+// two halves of one run's sums), so each lane's run is twice as long as one
+// wave over the tile would give it.  Every lane takes part in the staging;
+// lanes whose run starts past the frame's samples only stage.
+//
+// Staged per entry: rp = (r, phi0), r = f / fs in cycles per sample, and
+// st = (a, s a, k, sin t) with a = sqrt(w).  The step per sample is
+// theta = 2 pi frac(r); where cos(theta) < 0 the recurrence runs with
+// t = theta - pi and s = -1 (cos(x + q theta) = (-1)^q cos(x + q t)), else
+// with t = theta and s = 1, so that |t| <= pi/2 and k = 4 sin^2(t/2) keeps
+// the step accurate.  The run's samples: c_0 = cos x from the hardware unit,
+// d_0 = c_0 - cos(x - t) = c_0 k/2 - sin x sin t, then d_{q+1} = d_q - k c_q
+// and c_{q+1} = c_q + d_{q+1}; sample q adds a c_q (q even) or s a c_q (q odd).
 template <int NQ, bool SOA>
 __device__ __forceinline__ void synth_tile(const EntrySrc& src, uint64_t e_begin, uint64_t n_entries, int c0, int c1,
-                                           double r_scale, double n0, bool active, float* acc, double* s_r,
-                                           double* s_ph, float* s_a, float2* s_rot) {
+                                           double r_scale, double n0, bool active, float* acc, double2* s_rp,
+                                           float4* s_st) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = 0.f;
     for (int ch = c0; ch < c1; ++ch) {
@@ -118,53 +132,73 @@ __device__ __forceinline__ void synth_tile(const EntrySrc& src, uint64_t e_begin
             uint32_t ph;
             load_entry<SOA>(src, e_begin + e0 + (uint64_t)i, w, v, ph);
             const double r = v * r_scale;
-            s_r[i] = r;
-            double sn, cs;
-            sincospi(2.0 * (r - floor(r)), &sn, &cs);
-            s_rot[i] = make_float2((float)cs, (float)sn);
-            s_ph[i] = (double)ph * 2.3283064365386963e-10;   // 2^-32
-            s_a[i] = sqrtf(w);
+            // the step in half cycles, in (-1, 1]
+            double h = 2.0 * (r - floor(r));
+            h = h > 1.0 ? h - 2.0 : h;
+            // shifted by one half cycle where |h| > 1/2 (cos(theta) < 0)
+            const bool flip = h > 0.5 || h < -0.5;
+            const double t = flip ? (h > 0.0 ? h - 1.0 : h + 1.0) : h;
+            double sh, ch_;
+            sincospi(0.5 * t, &sh, &ch_);
+            const float a = sqrtf(w);
+            s_rp[i] = make_double2(r, (double)ph * 2.3283064365386963e-10);   // 2^-32
+            // sin t = 2 sin(t/2) cos(t/2); k = 4 sin^2(t/2)
+            s_st[i] = make_float4(a, flip ? -a : a, (float)(4.0 * sh * sh), (float)(2.0 * sh * ch_));
         }
         __syncthreads();
         if (!active) continue;
-        for (int i = 0; i < ne; ++i) {
+        for (int i = (int)(threadIdx.x >> 5); i < ne; i += 2) {
+            const double2 rp = s_rp[i];
+            const float4 st = s_st[i];
             // fractional cycles in one v_fract_f64 (x - floor(x), exact; its
             // clamp below 1 only matters where the FP32 rounding gives 1 anyway)
-            const float cyc = (float)__builtin_amdgcn_fract(fma(s_r[i], n0, s_ph[i]));
-            const float a = s_a[i];
+            const float cyc = (float)__builtin_amdgcn_fract(fma(rp.x, n0, rp.y));
             float c = __builtin_amdgcn_cosf(cyc);
-            acc[0] = fmaf(a, c, acc[0]);
+            acc[0] = fmaf(st.x, c, acc[0]);
             if constexpr (NQ > 1) {
-                float sn = __builtin_amdgcn_sinf(cyc);
-                const float2 rot = s_rot[i];
+                float d = fmaf(0.5f * st.z, c, -__builtin_amdgcn_sinf(cyc) * st.w);
 #pragma unroll
                 for (int q = 1; q < NQ; ++q) {
-                    const float c2 = fmaf(c, rot.x, -sn * rot.y);
-                    sn = fmaf(c, rot.y, sn * rot.x);
-                    c = c2;
-                    acc[q] = fmaf(a, c, acc[q]);
+                    d = fmaf(-st.z, c, d);
+                    c += d;
+                    acc[q] = fmaf((q & 1) ? st.y : st.x, c, acc[q]);
                 }
             }
         }
     }
 }
 
+// One lane's run: the sums over the group's entries, the second
+// half-wave's sums added onto the first's (every lane takes part), and the
+// first half-wave's store of the run's samples below s_count.
+template <int NQ, bool SOA>
+__device__ __forceinline__ void synth_run(const EntrySrc& src, uint64_t e_begin, uint64_t n_entries, int c0, int c1,
+                                          double r_scale, double n0, bool active, double2* s_rp, float4* s_st,
+                                          float* out, int j0, int s_count) {
+    float acc[NQ];
+    synth_tile<NQ, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, acc, s_rp, s_st);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] += __shfl_xor(acc[q], SYNTH_HALF, 64);
+    if (!active || threadIdx.x >= SYNTH_HALF) return;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+        if (j0 + q < s_count) out[j0 + q] = acc[q];
+}
+
 // Frame f owns samples [floor(f N / F), floor((f+1) N / F)) and the entries
 // [fbeg[f], fend[f]).  Block (tile, frame, group) accumulates the tile's
 // SYNTH_TILE samples over the group's entry chunks: group g takes chunks
-// [g cpg, (g+1) cpg), the last group every chunk from (G-1) cpg on.  A thread
-// takes a run of up to SYNTH_RUN consecutive samples, cut to what the tile's
-// remaining samples need.  With one group the block writes the record;
+// [g cpg, (g+1) cpg), the last group every chunk from (G-1) cpg on.  Lane l
+// and lane l + 32 take the run of up to SYNTH_RUN consecutive samples from
+// tile sample l x nq, nq cut to what the tile's remaining samples need.  With one group the block writes the record;
 // otherwise partial[(f G + g) max_samples + j] for the frame's sample j.
 template <bool SOA>
 __global__ void __launch_bounds__(SYNTH_THREADS)
 synth_tile_kernel(const uint64_t* __restrict__ fbeg, const uint64_t* __restrict__ fend, EntrySrc src,
                   double r_scale, int n_frames, int n_samples, int n_groups, int cpg, int max_samples,
                   float* __restrict__ partial, float* __restrict__ signal) {
-    __shared__ double s_r[SYNTH_CHUNK];
-    __shared__ double s_ph[SYNTH_CHUNK];
-    __shared__ float s_a[SYNTH_CHUNK];
-    __shared__ float2 s_rot[SYNTH_CHUNK];
+    __shared__ double2 s_rp[SYNTH_CHUNK];
+    __shared__ float4 s_st[SYNTH_CHUNK];
     const int f = blockIdx.y;
     const int g = blockIdx.z;
     const int64_t s_begin = (int64_t)f * n_samples / n_frames;
@@ -180,19 +214,29 @@ synth_tile_kernel(const uint64_t* __restrict__ fbeg, const uint64_t* __restrict_
     c0 = c0 < used ? c0 : used;
     c1 = c1 < used ? c1 : used;
     const int left = s_count - tile_base;
-    const int nq = left >= SYNTH_TILE ? SYNTH_RUN : (left + SYNTH_THREADS - 1) / SYNTH_THREADS;
-    const int j0 = tile_base + (int)threadIdx.x * nq;
+    const int nq = left >= SYNTH_TILE ? SYNTH_RUN : (left + SYNTH_HALF - 1) / SYNTH_HALF;
+    const int j0 = tile_base + (int)(threadIdx.x & (SYNTH_HALF - 1)) * nq;
     const bool active = j0 < s_count;
     const double n0 = (double)(s_begin + j0);
-    float acc[SYNTH_RUN];
-    if (nq == 4) synth_tile<4, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, acc, s_r, s_ph, s_a, s_rot);
-    else if (nq == 3) synth_tile<3, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, acc, s_r, s_ph, s_a, s_rot);
-    else if (nq == 2) synth_tile<2, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, acc, s_r, s_ph, s_a, s_rot);
-    else synth_tile<1, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, acc, s_r, s_ph, s_a, s_rot);
-    if (!active) return;
     float* out = n_groups == 1 ? signal + s_begin : partial + ((uint64_t)f * n_groups + g) * (uint64_t)max_samples;
-    for (int q = 0; q < nq; ++q)
-        if (j0 + q < s_count) out[j0 + q] = acc[q];
+    switch (nq) {
+        case 16: synth_run<16, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
+        case 15: synth_run<15, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
+        case 14: synth_run<14, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
+        case 13: synth_run<13, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
+        case 12: synth_run<12, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
+        case 11: synth_run<11, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
+        case 10: synth_run<10, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
+        case 9: synth_run<9, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
+        case 8: synth_run<8, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
+        case 7: synth_run<7, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
+        case 6: synth_run<6, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
+        case 5: synth_run<5, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
+        case 4: synth_run<4, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
+        case 3: synth_run<3, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
+        case 2: synth_run<2, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
+        default: synth_run<1, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
+    }
 }
 
 __global__ void synth_reduce_kernel(int n_frames, int n_samples, int n_groups, int max_samples,

@@ -175,11 +175,12 @@ def test_beat_synthesis_work_split(ctx, case):
     rng = np.random.Generator(np.random.PCG64(17 if case == "groups" else 18))
     fs, lam = 20e9, 1550e-9
     if case == "groups":
-        # 64 frames of 100 samples; one frame with 300 chunks of entries
+        # 64 frames of 100 samples; one frame with 307,195 entries (1200
+        # chunks of 256, the last one short)
         n_frames, ns, counts = 64, 6400, [int(rng.integers(0, 5000)) for _ in range(63)] + [300 * 1024 - 5]
         n_check = ns
     else:
-        # one frame of 5e6 samples (9766 tiles) and 2600 entries (3 chunks);
+        # one frame of 5e6 samples (9766 tiles) and 2600 entries (11 chunks);
         # the oracle evaluates the first 30,000 samples (a one-frame record
         # cut short has the same samples)
         n_frames, ns, counts = 1, 5_000_000, [2600]
