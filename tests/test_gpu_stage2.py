@@ -272,3 +272,30 @@ def test_spectrogram_lists_across_pid_word_boundary(ctx, oracle_mc, precision):
         flipped += len(Lo["w"]) - hits
         assert hits > 100, hits
     assert flipped <= (3 if precision == 0 else 0), flipped
+
+
+def test_beat_synthesis_step_extremes(ctx):
+    """One entry per frame at the step sizes where a sample-to-sample
+    recurrence is least accurate: zero and tiny velocities (step near 0),
+    the neighbourhood of the Nyquist rate (step near half a cycle, where the
+    recurrence runs on the step shifted by half a cycle), negative velocities
+    and a whole cycle per sample; frames of 512 samples so that runs reach
+    their full length.  Each frame against the FP64 oracle."""
+    fs, lam = 20e9, 1550e-9
+    nyq = 0.25 * lam * fs                       # v at f = fs / 2
+    vs = [0.0, 1e-3, 0.7, 37.0, 1000.0, 0.5 * nyq, nyq - 2.0, nyq - 1e-3, nyq, nyq + 1e-3, nyq + 2.0,
+          1.5 * nyq, -3.0, -0.5 * nyq, -nyq, 2.0 * nyq, 2.0 * nyq + 0.5, 4000.0]
+    rng = np.random.Generator(np.random.PCG64(23))
+    lists_o, lists_g = [], []
+    for v in vs:
+        w = np.array([rng.uniform(0.1, 1.0)], np.float32)
+        ph = rng.integers(0, 2**32, 1, dtype=np.uint64).astype(np.uint32)
+        lists_g.append({"w": w, "v": np.array([v]), "phase_u32": ph})
+        lists_o.append({"w": w.astype(np.float64), "v": np.array([v]), "phase": ph.astype(np.float64) / 2**32})
+    ns = 512 * len(vs)
+    g = ctx.beat_synthesize(lists_g, lam, fs, ns)
+    o = ostage2.beat_signal(lists_o, ns, fs, lam)
+    b = ostage2.frame_bounds(ns, len(vs))
+    for k, v in enumerate(vs):
+        e = rel_l2(g[b[k]:b[k + 1]], o[b[k]:b[k + 1]])
+        assert e <= 2e-5, (k, v, e)
