@@ -534,14 +534,22 @@ def profile_case(ctx, case, steps, warmup):
     torch.cuda.synchronize()
     ms = []
     events = 0
+    pairs = None
     for _ in range(steps):
         r = run()
         ms.append(ctx.last_launch()["kernel_ms"])
         c = r["spectrum"]["counts"] if case == "spectrogram" and "spectrum" in r else r.get("counts")
         if c:
             events = c["collisions"] + c["surface"]
+        if case == "spectrogram":
+            # (entry, sample) pairs the beat synthesis sums: each frame's
+            # stored entries times its samples
+            fc = np.minimum(np.asarray(r["frame_counts"], np.int64), sg["list_capacity"])
+            F, N = sg["n_frames"], sg["n_samples"]
+            per = np.array([(f + 1) * N // F - f * N // F for f in range(F)], np.int64)
+            pairs = int(np.sum(fc * per))
     torch.cuda.synchronize()
-    print(json.dumps({"case": case, "packets": packets, "events": events, "steps": steps,
+    print(json.dumps({"case": case, "packets": packets, "events": events, "pairs": pairs, "steps": steps,
                       "kernel_ms": ms, "kernel_ms_mean": float(np.mean(ms)) if ms else None,
                       "launch": ctx.last_launch(), "kind": ctx.lib.pdv_last_launch_kind(ctx.h)}), flush=True)
     return 0
