@@ -49,6 +49,7 @@ void launch_phase_cdf(hipStream_t s, int n_jobs, const void* jobs, int n_nodes, 
 void launch_zero_u64(hipStream_t s, uint64_t* p, uint64_t n);
 hipError_t plan_transport(TransportShape& sh, int precision, bool list, int want_bits, int lds_per_block,
                           int lds_per_cu);
+int launch_kind_of(const pdv_params* sets, int n);
 hipError_t launch_transport_dev(hipStream_t s, int precision, const TransportShape& sh, const SetDesc* descs,
                                 const uint8_t* tables, uint64_t* tallies, const WorkItem* items,
                                 const int* n_items_dev, uint32_t* queue);
@@ -90,8 +91,9 @@ struct Executor {
     virtual int init() = 0;
     virtual int prepare(const std::vector<Req*>& admitted) = 0;
     // finishing: requests whose last packets are in this launch (their
-    // results may be copied back right after it)
-    virtual int run(const std::vector<WorkItem>& items, const std::vector<Req*>& finishing) = 0;
+    // results may be copied back right after it); kind: the kernel kind
+    // every set of the launch shares (KIND_GENERIC for a mix)
+    virtual int run(const std::vector<WorkItem>& items, const std::vector<Req*>& finishing, int kind) = 0;
     // copy the finished requests' results to their callers (st[i] per request)
     virtual int collect(const std::vector<Req*>& done, std::vector<int>& st) = 0;
     virtual const char* error() const = 0;
@@ -148,15 +150,24 @@ struct HipExecutor : Executor {
     PhaseJob* h_pj = nullptr;        // pinned staging: phase jobs of one iteration
     uint64_t* h_tally = nullptr;     // pinned staging: tally blocks per slot
     int max_items = 0;
-    TransportShape shape;
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
+    // One launch shape and one captured graph per kernel kind: the generic
+    // kernel (any mix of requests) and the two specialised FP32 kinds, which
+    // give bit-identical tallies.  512-thread blocks, as many per CU as the
+    // kernel's occupancy keeps resident (four at eight waves per SIMD, three
+    // at six, two at four).
+    static constexpr int N_KIND = 3;
+    TransportShape shape_k[N_KIND];
+    hipGraphExec_t gexec_k[N_KIND] = {};
+    hipGraph_t graph_k[N_KIND] = {};
+    static int kind_index(int kind) { return kind == KIND_TABLE_LAYERED ? 1 : (kind == KIND_HG_UNIFORM ? 2 : 0); }
     std::string err;
 
     explicit HipExecutor(ServeEngine* e) : E(e), ctx(e->ctx) {}
     ~HipExecutor() override {
-        if (gexec) (void)hipGraphExecDestroy(gexec);
-        if (graph) (void)hipGraphDestroy(graph);
+        for (int k = 0; k < N_KIND; ++k) {
+            if (gexec_k[k]) (void)hipGraphExecDestroy(gexec_k[k]);
+            if (graph_k[k]) (void)hipGraphDestroy(graph_k[k]);
+        }
         DevBuf* all[] = {&descs, &tables, &tallies, &items, &nitems, &queue, &layer_jobs, &phase_jobs, &density};
         for (DevBuf* b : all)
             if (b->ptr) {
@@ -196,18 +207,25 @@ struct HipExecutor : Executor {
                          "pinned phase jobs"))) return r;
         if ((r = hipfail(hipHostMalloc((void**)&h_tally, 8ull * slot_tally_words(E->opts.max_bins) * S,
                                        hipHostMallocDefault), "pinned tallies"))) return r;
-        shape.block = 512;
-        shape.grid = ctx->n_cu * 4;
-        shape.max_layers = E->opts.max_layers;
-        shape.max_cells = E->opts.max_angles - 1;
-        shape.max_bins = E->opts.max_bins;
-        shape.retire_min = E->opts.precision == PDV_FP64 ? 1 : 12;
-        hipError_t e = plan_transport(shape, E->opts.precision, false, 0, ctx->lds_per_block, ctx->lds_per_cu);
-        if (e == hipErrorInvalidValue) {
-            err = "serving limits need more LDS per block than the device has";
-            return PDV_EINVAL;
+        const bool fp64 = E->opts.precision == PDV_FP64;
+        const int kinds[N_KIND] = {KIND_GENERIC, KIND_TABLE_LAYERED, KIND_HG_UNIFORM};
+        for (int k = 0; k < (fp64 ? 1 : N_KIND); ++k) {
+            TransportShape& sh = shape_k[k];
+            sh.kind = kinds[k];
+            sh.block = 512;
+            sh.grid = ctx->n_cu * (fp64 ? 2 : (k == 0 ? 3 : 4));
+            sh.max_layers = E->opts.max_layers;
+            sh.max_cells = E->opts.max_angles - 1;
+            sh.max_bins = E->opts.max_bins;
+            sh.retire_min = fp64 ? 1 : 12;
+            hipError_t e = plan_transport(sh, E->opts.precision, false, 0, ctx->lds_per_block, ctx->lds_per_cu);
+            if (e == hipErrorInvalidValue) {
+                err = "serving limits need more LDS per block than the device has";
+                return PDV_EINVAL;
+            }
+            if ((r = hipfail(e, "transport launch plan"))) return r;
         }
-        return hipfail(e, "transport launch plan");
+        return PDV_OK;
     }
     // Tables of the newly admitted requests, all enqueued on the context
     // stream from pinned staging; the transport launch that follows on the
@@ -297,7 +315,7 @@ struct HipExecutor : Executor {
                          h_pj[first].n_angles);
         return PDV_OK;
     }
-    int record(hipStream_t s) {
+    int record(hipStream_t s, const TransportShape& shape) {
         hipError_t e;
         if ((e = hipMemcpyAsync(items.ptr, h_items, sizeof(WorkItem) * max_items, hipMemcpyHostToDevice, s)))
             return hipfail(e, "copy items");
@@ -310,28 +328,30 @@ struct HipExecutor : Executor {
         return hipfail(e, "transport launch");
     }
     std::vector<Req*> copied;    // requests whose results the last launch copied back
-    int run(const std::vector<WorkItem>& its, const std::vector<Req*>& finishing) override {
+    int run(const std::vector<WorkItem>& its, const std::vector<Req*>& finishing, int kind) override {
         copied.clear();
         if (its.empty()) return PDV_OK;
         hipStream_t s = ctx->stream;
         copied = finishing;
         std::memcpy(h_items, its.data(), sizeof(WorkItem) * its.size());
         *h_nitems = (int)its.size();
+        const int k = E->opts.precision == PDV_FP64 ? 0 : kind_index(kind);
         int r;
         if (E->opts.use_graph) {
-            if (!gexec) {
+            if (!gexec_k[k]) {
                 if ((r = hipfail(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture")))
                     return r;
-                const int rr = record(s);
-                hipError_t e = hipStreamEndCapture(s, &graph);
+                const int rr = record(s, shape_k[k]);
+                hipError_t e = hipStreamEndCapture(s, &graph_k[k]);
                 if (rr) return rr;
                 if ((r = hipfail(e, "end capture"))) return r;
-                if ((r = hipfail(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0), "graph instantiate")))
+                if ((r = hipfail(hipGraphInstantiate(&gexec_k[k], graph_k[k], nullptr, nullptr, 0),
+                                 "graph instantiate")))
                     return r;
             }
-            if ((r = hipfail(hipGraphLaunch(gexec, s), "graph launch"))) return r;
+            if ((r = hipfail(hipGraphLaunch(gexec_k[k], s), "graph launch"))) return r;
         } else {
-            if ((r = record(s))) return r;
+            if ((r = record(s, shape_k[k]))) return r;
         }
         // the result copies of the requests this launch finishes follow it
         // on the stream, so one wait covers both
@@ -406,7 +426,7 @@ struct HostExecutor : Executor {
         for (Req* q : adm) std::fill(slots[q->slot].begin(), slots[q->slot].end(), 0);
         return PDV_OK;
     }
-    int run(const std::vector<WorkItem>& its, const std::vector<Req*>&) override {
+    int run(const std::vector<WorkItem>& its, const std::vector<Req*>&, int) override {
         ++iter;
         if (E->opts.host_fail_iteration && iter == (uint64_t)E->opts.host_fail_iteration) {
             err = "injected executor failure";
@@ -513,6 +533,8 @@ void ServeEngine::loop() {
         int rc = exec->prepare(admitted);
         const double t_prep = now_s();
         std::vector<WorkItem> items;
+        constexpr int KIND_NONE = -2;
+        int kind = KIND_NONE;
         if (rc == PDV_OK) {
             std::unique_lock<std::mutex> lk(mu);
             uint64_t open = 0;
@@ -532,6 +554,11 @@ void ServeEngine::loop() {
             for (auto& q : active) {
                 if (q->cancel) continue;
                 uint64_t take = std::min<uint64_t>(q->p.n_packets - q->issued, share);
+                if (take > 0 && (int)items.size() < opts.max_items) {
+                    // the kernel kind all of this launch's sets share
+                    const int k = launch_kind_of(&q->p, 1);
+                    kind = (kind == KIND_NONE || kind == k) ? k : KIND_GENERIC;
+                }
                 while (take > 0 && (int)items.size() < opts.max_items) {
                     const uint64_t c = std::min<uint64_t>(take, ppi);
                     items.push_back(WorkItem{(uint32_t)q->slot, 0, q->p.pid_begin + q->issued, c});
@@ -546,7 +573,7 @@ void ServeEngine::loop() {
             for (auto& q : active)
                 if (!q->cancel && q->issued >= q->p.n_packets) finishing.push_back(q.get());
         }
-        if (rc == PDV_OK) rc = exec->run(items, finishing);
+        if (rc == PDV_OK) rc = exec->run(items, finishing, kind == KIND_NONE ? KIND_GENERIC : kind);
         const double t_run = now_s();
         // retire finished requests: one batched copy of their results
         std::vector<std::shared_ptr<Req>> done_now;
