@@ -535,6 +535,7 @@ void ServeEngine::loop() {
         std::vector<WorkItem> items;
         constexpr int KIND_NONE = -2;
         int kind = KIND_NONE;
+        std::vector<double> cost;     // estimated work of each item
         if (rc == PDV_OK) {
             std::unique_lock<std::mutex> lk(mu);
             uint64_t open = 0;
@@ -562,10 +563,20 @@ void ServeEngine::loop() {
                 while (take > 0 && (int)items.size() < opts.max_items) {
                     const uint64_t c = std::min<uint64_t>(take, ppi);
                     items.push_back(WorkItem{(uint32_t)q->slot, 0, q->p.pid_begin + q->issued, c});
+                    cost.push_back((double)c * (1.0 + q->p.tau_total));
                     q->issued += c;
                     take -= c;
                 }
             }
+            // the most expensive items first (a packet's events grow with
+            // the optical depth), so that the persistent blocks' last pulls
+            // are short ones and no single long item holds the launch open
+            std::vector<int> ord(items.size());
+            for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
+            std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+            std::vector<WorkItem> sorted(items.size());
+            for (size_t i = 0; i < ord.size(); ++i) sorted[i] = items[ord[i]];
+            items.swap(sorted);
         }
         std::vector<Req*> finishing;
         if (rc == PDV_OK) {
