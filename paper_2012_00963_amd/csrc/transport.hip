@@ -530,11 +530,10 @@ __device__ __forceinline__ Real peel_weight(const SetConst<Real>& c, const typen
     return M_ * share * M<Real>::exp_neg(M<Real>::div(T, mu_n));
 }
 
-// Event counters: packets, exits and detections are wave-uniform (counted
-// from ballots when the wave retires packets); collisions, surface hits and
-// the absorbed weight (fixed point) are per-lane sums, reduced across the
-// wave when the block changes set or retires.
-// A lane's running sums over the packets it finished in the current set.
+// Event counters: collisions, surface hits and the absorbed weight (fixed
+// point) are per-lane sums, reduced across the wave when the block changes
+// set or finishes.  A lane's running sums over the packets it finished in
+// the current set.
 // Packet, exit and detection counts are not kept per lane or per wave: a
 // block adds each work item's packet count when it takes the item, the rare
 // outcomes (a detection, a packet that ends inside the cloud) add one to a
