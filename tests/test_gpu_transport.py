@@ -326,6 +326,31 @@ def test_large_mie_full_size(ctx, oracle_mc):
     assert abs(rate_full - rate_s) < 5 * sd + 1e-12
 
 
+def test_batched_full_size(ctx, oracle_mc):
+    """The 512-set uneven batch (7.6e8 packets) as the benchmark launches it
+    (one persistent launch replayed from a captured graph): every set's
+    packet count and exact weight conservation; the three smallest sets
+    recomputed whole by the oracle; the optically thickest set run alone on
+    the GPU equals its batched tallies bitwise, and a 3e5-packet range of it
+    matches the oracle."""
+    sets = wl.batched_sets(512)
+    print("case batched full", flush=True)
+    res = ctx.spectrum_batch(sets, opts=dict(use_graph=1))
+    for p, g in zip(sets, res):
+        assert g["counts"]["packets"] == p["n_packets"]
+        assert conservation_exact(g, p["n_packets"])
+    small = sorted(range(len(sets)), key=lambda i: sets[i]["n_packets"])[:3]
+    for i in small:
+        o = oracle_mc.run(sets[i])
+        assert_parity(res[i], o, sets[i]["n_packets"])
+    k = max(range(len(sets)), key=lambda i: sets[i]["tau_total"])
+    alone = ctx.spectrum(sets[k])
+    assert np.array_equal(alone["w_fx"], res[k]["w_fx"]) and alone["sinks_fx"] == res[k]["sinks_fx"]
+    n = min(300_000, sets[k]["n_packets"])
+    part = dict(sets[k], n_packets=n, pid_begin=sets[k]["n_packets"] - n)
+    assert_parity(ctx.spectrum(part), oracle_mc.run(part, pid_begin=part["pid_begin"]), n)
+
+
 def test_autotune_is_result_invariant(ctx, tmp_path):
     from paper_2012_00963_amd import pdv
     sets = wl.batched_sets(16, seed=21, packets_scale=0.02)
