@@ -21,9 +21,12 @@ that it follows):
 
 Pins: every function is checked by the CPU tests against closed forms,
 invariants, textbook special cases, library routines or the paper's worked
-numbers.  Parity unpinned: the full multiple-scattering spectrum has no
-independent reference value (only its parts are pinned: free flight,
-samplers, Doppler telescoping, conservation, single-scattering and
-surface-only classes), and the back-scattering efficiency K_back used by the
-single-scattering comparator (eq. 25) is this build's own reading.
+numbers; the whole multiple-scattering walk is checked against the exact
+reflection of a deep, isotropically scattering slab (Chandrasekhar's
+H-function, tests/hfunc.py).  Parity unpinned: the velocity spectrum of a
+general cloud has no independent reference value (beyond that, only its
+parts are pinned: free flight, samplers, Doppler telescoping, conservation,
+single-scattering and surface-only classes), and the back-scattering
+efficiency K_back used by the single-scattering comparator (eq. 25) is this
+build's own reading.
 """
