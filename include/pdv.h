@@ -220,7 +220,9 @@ typedef struct pdv_spectrum_out {
 typedef struct pdv_launch_opts {
     int32_t block_size;          /* threads per block: 256, 512, 768 or 1024; 0 = default */
     int32_t blocks_per_cu;       /* persistent grid = blocks_per_cu x CUs; 0 = default */
-    uint64_t packets_per_item;   /* work-item size; 0 = default */
+    uint64_t packets_per_item;   /* work-item size; 0 = default (with one FP32 set of the tabulated kind and
+                                    no lists, a persistent launch's waves take items by themselves, an
+                                    eighth of a wave's share) */
     int32_t persistent;          /* 1 = persistent work queue, 0 = one block per item, -1 = default */
     int32_t use_graph;           /* 1 = capture and replay the batch as a hipGraph, 0 = direct launches */
     int32_t guide_bits;          /* search-guide cells 2^guide_bits staged in LDS, 11..14; 0 = the finest

@@ -693,9 +693,19 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
         __syncthreads();
     };
 
+    // persistent == 2 (one set, no lists): the block stages the set of item 0
+    // once and every wave then takes work items from the launch's queue by
+    // itself, whenever its packet range runs out, without waiting for its
+    // lanes to finish the packets they hold; the block meets only when the
+    // queue is empty.  Otherwise the block takes items one at a time and
+    // shares each among its waves.
+    // (list-writing launches keep block items: a wave's staged entries share
+    // one high packet-id word, that of the item they came from)
+    const bool wave_items = persistent == 2 && !LIST;
     for (int it = 0;; ++it) {
         if (tid == 0) {
-            int idx = persistent ? (int)atomicAdd(queue, 1u) : (it == 0 ? (int)blockIdx.x : n_items);
+            int idx = wave_items ? (it == 0 ? 0 : n_items)
+                                 : (persistent ? (int)atomicAdd(queue, 1u) : (it == 0 ? (int)blockIdx.x : n_items));
             s_item_idx = idx;
             if (idx < n_items) s_item = items[idx];
             s_next = 0;
@@ -704,7 +714,7 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
         const int idx = (int)uniform_u32((uint32_t)s_item_idx);
         if (idx >= n_items) break;
         const int set = (int)uniform_u32(s_item.set);
-        const uint64_t pid0 = s_item.pid_begin;
+        uint64_t pid0 = s_item.pid_begin;          // the current item's first packet id (per wave with wave_items)
         const uint32_t count = (uint32_t)s_item.count;
 
         if (set != cur_set) {
@@ -760,7 +770,9 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
             __syncthreads();
         }
 
-        if (tid == 0) s_packets += count;    // read only by thread 0, at the set's flush
+        // read by thread 0 at the set's flush (with wave_items the waves add
+        // the items they take)
+        if (tid == 0 && !wave_items) s_packets += count;
         const SetConst<Real> c = load_const<Real>(descs[set]);
         const int nb = c.n_bins;
         uint32_t chunk = count / (2u * (uint32_t)(nthr >> 6));
@@ -773,6 +785,7 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
         int st = ST_EMPTY;
         bool exhausted = false;              // the item has no packets left for this wave
         uint32_t w_next = 0, w_end = 0;      // wave-private range of item-local packet indices
+        bool first_item = true;              // with wave_items: the wave has not taken an item yet
         uint64_t pid = 0;
         uint32_t q0 = 0, q1 = 0;             // the packet's fixed first-round Philox words
         uint32_t k = 0;
@@ -877,15 +890,42 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                 uint64_t empty = __ballot(st == ST_EMPTY);
                 while (empty != 0ull && !exhausted) {
                     if (w_next >= w_end) {
-                        uint32_t base = 0;
-                        if (lane == 0) base = atomicAdd(&s_next, chunk);
-                        base = uniform_u32(base);
-                        if (base >= count) {
-                            exhausted = true;
-                            break;
+                        if (wave_items) {
+                            // this wave's next work item (all of the launch's
+                            // items belong to the block's one set): its first
+                            // one is item (global wave index), so the waves do
+                            // not all meet at the queue when the launch starts;
+                            // later ones come from the queue, after the first
+                            // items of all waves
+                            uint32_t qi = 0;
+                            if (first_item) {
+                                qi = blockIdx.x * (uint32_t)(nthr >> 6) + (uint32_t)(tid >> 6);
+                                first_item = false;
+                            } else {
+                                if (lane == 0) qi = atomicAdd(queue, 1u);
+                                qi = uniform_u32(qi) + gridDim.x * (uint32_t)(nthr >> 6);
+                            }
+                            qi = uniform_u32(qi);
+                            if (qi >= (uint32_t)n_items) {
+                                exhausted = true;
+                                break;
+                            }
+                            const WorkItem wi = items[qi];
+                            pid0 = wi.pid_begin;
+                            w_next = 0;
+                            w_end = (uint32_t)wi.count;
+                            if (lane == 0) atomicAdd(&s_packets, (unsigned long long)wi.count);
+                        } else {
+                            uint32_t base = 0;
+                            if (lane == 0) base = atomicAdd(&s_next, chunk);
+                            base = uniform_u32(base);
+                            if (base >= count) {
+                                exhausted = true;
+                                break;
+                            }
+                            w_next = base;
+                            w_end = count - base < chunk ? count : base + chunk;
                         }
-                        w_next = base;
-                        w_end = count - base < chunk ? count : base + chunk;
                     }
                     const uint32_t n = (uint32_t)__popcll(empty);
                     const uint32_t avail = w_end - w_next;
