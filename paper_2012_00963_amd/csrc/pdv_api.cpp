@@ -609,31 +609,47 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return sets[a].n_packets > sets[b].n_packets; });
     h_items.clear();
-    for (int i : order) {
-        const pdv_params& p = sets[i];
-        // the set's packets in equal items of at most packets_per_item
-        // (sizes differ by one at most: no short remainder that leaves its
-        // block idle at the end); items never cross a multiple of 2^32
-        // packet ids (a list-writing launch forms detected entries' phase
-        // words with one high id word per item)
-        const uint64_t n_it = (p.n_packets + o.packets_per_item - 1) / o.packets_per_item;
-        const uint64_t even = n_it ? p.n_packets / n_it : 0, extra = n_it ? p.n_packets % n_it : 0;
-        uint64_t off = 0;
-        for (uint64_t j = 0; j < n_it; ++j) {
-            for (uint64_t len = even + (j < extra ? 1 : 0); len > 0;) {
-                WorkItem w;
-                w.set = (uint32_t)i;
-                w.pad = 0;
-                w.pid_begin = p.pid_begin + off;
-                const uint64_t to_wrap = (1ull << 32) - (w.pid_begin & 0xffffffffull);
-                w.count = std::min<uint64_t>(len, to_wrap);
-                h_items.push_back(w);
-                off += w.count;
-                len -= w.count;
+    // wave items: one descriptor of the whole set, which the kernel cuts
+    // into n_items equal items itself (a host-built list of the ~65k items
+    // of the large case cost ~0.1 ms to build and copy)
+    uint64_t n_wave_items = 0;
+    if (wave_items) {
+        const pdv_params& p = sets[0];
+        n_wave_items = (p.n_packets + o.packets_per_item - 1) / o.packets_per_item;
+        if (n_wave_items > 0x7fffffffull) return fail(PDV_EINVAL, "too many work items: raise packets_per_item");
+        WorkItem w;
+        w.set = 0;
+        w.pad = 0;
+        w.pid_begin = p.pid_begin;
+        w.count = p.n_packets;
+        if (n_wave_items) h_items.push_back(w);
+    } else {
+        for (int i : order) {
+            const pdv_params& p = sets[i];
+            // the set's packets in equal items of at most packets_per_item
+            // (sizes differ by one at most: no short remainder that leaves its
+            // block idle at the end); items never cross a multiple of 2^32
+            // packet ids (a list-writing launch forms detected entries' phase
+            // words with one high id word per item)
+            const uint64_t n_it = (p.n_packets + o.packets_per_item - 1) / o.packets_per_item;
+            const uint64_t even = n_it ? p.n_packets / n_it : 0, extra = n_it ? p.n_packets % n_it : 0;
+            uint64_t off = 0;
+            for (uint64_t j = 0; j < n_it; ++j) {
+                for (uint64_t len = even + (j < extra ? 1 : 0); len > 0;) {
+                    WorkItem w;
+                    w.set = (uint32_t)i;
+                    w.pad = 0;
+                    w.pid_begin = p.pid_begin + off;
+                    const uint64_t to_wrap = (1ull << 32) - (w.pid_begin & 0xffffffffull);
+                    w.count = std::min<uint64_t>(len, to_wrap);
+                    h_items.push_back(w);
+                    off += w.count;
+                    len -= w.count;
+                }
             }
         }
     }
-    const int n_items = (int)h_items.size();
+    const int n_items = wave_items ? (int)n_wave_items : (int)h_items.size();
 
     // ---- device buffers ----
     int r;
@@ -641,7 +657,7 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
     if ((r = ensure(tables, TableLayout::BYTES * (size_t)n_unique, "set tables"))) return r;
     if ((r = ensure(dup_src, sizeof(int) * n, "table sharing map"))) return r;
     if ((r = ensure(tallies, 8ull * tally_words_total, "tallies"))) return r;
-    if ((r = ensure(items, sizeof(WorkItem) * std::max(1, n_items), "work items"))) return r;
+    if ((r = ensure(items, sizeof(WorkItem) * std::max<size_t>(1, h_items.size()), "work items"))) return r;
     if ((r = ensure(queue, 256, "queue"))) return r;
     if ((r = ensure(layer_jobs, sizeof(LayerJob) * n, "layer jobs"))) return r;
     if ((r = ensure(phase_jobs, sizeof(PhaseJob) * n, "phase jobs"))) return r;
@@ -662,7 +678,8 @@ int pdv_ctx::run_batch(const pdv_params* sets, int n, pdv_spectrum_out* outs, co
     if (!h_density.empty())
         if ((r = hip_check(H2D(density.ptr, h_density.data(), 8 * h_density.size()), "copy densities"))) return r;
     if (n_items)
-        if ((r = hip_check(H2D(items.ptr, h_items.data(), sizeof(WorkItem) * n_items), "copy work items"))) return r;
+        if ((r = hip_check(H2D(items.ptr, h_items.data(), sizeof(WorkItem) * h_items.size()), "copy work items")))
+            return r;
 
     // ---- tables ----
     launch_layer_tables(s, n_layer_jobs, layer_jobs.ptr, (const double*)density.ptr, (uint8_t*)tables.ptr);

@@ -716,6 +716,14 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
         const int set = (int)uniform_u32(s_item.set);
         uint64_t pid0 = s_item.pid_begin;          // the current item's first packet id (per wave with wave_items)
         const uint32_t count = (uint32_t)s_item.count;
+        // wave_items: item 0 holds the whole set, cut into n_items equal
+        // items (sizes differ by one at most, larger ones first)
+        const uint64_t set_pid = s_item.pid_begin;
+        uint64_t wi_even = 0, wi_extra = 0;
+        if (wave_items) {
+            wi_even = s_item.count / (uint64_t)n_items;
+            wi_extra = s_item.count % (uint64_t)n_items;
+        }
 
         if (set != cur_set) {
             if (cur_set >= 0) flush_set(cur_set);
@@ -910,11 +918,11 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
                                 exhausted = true;
                                 break;
                             }
-                            const WorkItem wi = items[qi];
-                            pid0 = wi.pid_begin;
+                            const uint64_t q64 = qi;
+                            pid0 = set_pid + q64 * wi_even + (q64 < wi_extra ? q64 : wi_extra);
                             w_next = 0;
-                            w_end = (uint32_t)wi.count;
-                            if (lane == 0) atomicAdd(&s_packets, (unsigned long long)wi.count);
+                            w_end = (uint32_t)(wi_even + (q64 < wi_extra ? 1u : 0u));
+                            if (lane == 0) atomicAdd(&s_packets, (unsigned long long)w_end);
                         } else {
                             uint32_t base = 0;
                             if (lane == 0) base = atomicAdd(&s_next, chunk);
