@@ -531,14 +531,13 @@ __device__ __forceinline__ Real peel_weight(const SetConst<Real>& c, const typen
 }
 
 // Event counters: collisions, surface hits and the absorbed weight (fixed
-// point) are per-lane sums, reduced across the wave when the block changes
-// set or finishes.  A lane's running sums over the packets it finished in
-// the current set.
-// Packet, exit and detection counts are not kept per lane or per wave: a
-// block adds each work item's packet count when it takes the item, the rare
-// outcomes (a detection, a packet that ends inside the cloud) add one to a
-// block counter in their own branch, and the exits are the packets less
-// those that ended inside, formed at the set's flush.
+// point) are a lane's running sums over the packets it finished in the
+// current set, reduced across the wave when the block changes set or
+// finishes.  Packet, exit and detection counts are not kept per lane or per
+// wave: the packets of each work item are added when the item is taken, the
+// rare outcomes (a detection, a packet that ends inside the cloud) add one
+// to a block counter in their own branch, and the exits are the packets
+// less those that ended inside, formed at the set's flush.
 struct LaneAcc {
     uint64_t abs_particle, abs_surface;
     uint32_t collisions, surface;
@@ -583,8 +582,9 @@ transport_kernel(const SetDesc* __restrict__ descs, const uint8_t* __restrict__ 
     __shared__ WorkItem s_item;
     __shared__ int s_item_idx;
     __shared__ uint32_t s_next;
-    // the current set's packets taken by this block (written by thread 0),
-    // how many of them were detected and how many ended inside the cloud
+    // the current set's packets taken by this block (added by thread 0 per
+    // item, or by each wave for the items it takes itself), how many of them
+    // were detected and how many ended inside the cloud
     __shared__ unsigned long long s_packets, s_detected, s_ended;
 
     const LdsLayout L = lds_layout((int)sizeof(Real), max_layers, max_cells, max_bins, guide_bits,
