@@ -262,6 +262,23 @@ def test_batch_graph_replays(ctx):
             assert np.array_equal(eager[0]["w_fx"], ref[0]["w_fx"])
 
 
+def test_single_set_graph_replays(ctx):
+    # one Mie set runs with the waves taking work items themselves; replayed
+    # from a captured graph for two packet counts (the item count comes from
+    # device memory), with eager launches in between, it equals the eager result
+    a = dict(wl.large_mie(300_000), seed=51)
+    b = dict(wl.large_mie(170_001), seed=52, pid_begin=(1 << 32) - 1000)
+    refs = [ctx.spectrum_batch([p])[0] for p in (a, b)]
+    for rep in range(3):
+        for p, ref in zip((a, b), refs):
+            got = ctx.spectrum_batch([p], opts=dict(use_graph=1))[0]
+            assert ctx.last_launch()["kind"] == 1
+            assert np.array_equal(got["w_fx"], ref["w_fx"]) and got["sinks_fx"] == ref["sinks_fx"], rep
+            assert got["counts"] == ref["counts"]
+            eager = ctx.spectrum(p)
+            assert np.array_equal(eager["w_fx"], ref["w_fx"])
+
+
 def test_empty_and_degenerate(ctx):
     p = _c1(n_packets=0)
     g = ctx.spectrum(p)
