@@ -577,7 +577,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the transport would shard by packet-id ranges with one all-reduce of the tallies)",
               file=sys.stderr)
         return 2

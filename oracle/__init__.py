@@ -27,6 +27,6 @@ H-function, tests/hfunc.py).  Parity unpinned: the velocity spectrum of a
 general cloud has no independent reference value (beyond that, only its
 parts are pinned: free flight, samplers, Doppler telescoping, conservation,
 single-scattering and surface-only classes), and the back-scattering
-efficiency K_back used by the single-scattering comparator (eq. 25) is this
-build's own reading.
+efficiency K_back used by the single-scattering comparator (eq. 25) is a
+reading of the paper, not a value it prints.
 """
