@@ -73,12 +73,14 @@ float* synth_scratch(int device) {
 
 constexpr int SYNTH_CHUNK = 256;        // entries staged in LDS at a time (8 KB)
 constexpr int SYNTH_THREADS = 64;       // one wave per block
-constexpr int SYNTH_HALF = SYNTH_THREADS / 2;
-constexpr int SYNTH_RUN = 16;           // consecutive samples per lane, at most
-constexpr int SYNTH_TILE = SYNTH_RUN * SYNTH_HALF;
+constexpr int SYNTH_GROUPS = 8;         // lane groups, each taking every eighth entry
+constexpr int SYNTH_LANES = SYNTH_THREADS / SYNTH_GROUPS;
+constexpr int SYNTH_RUN = 64;           // consecutive samples per lane, at most
+constexpr int SYNTH_TILE = SYNTH_RUN * SYNTH_LANES;
 
 // Where the entries come from: an array of ListEntry records (lists written
-// by the transport, or packed from host arrays), or three separate arrays.
+// by the transport, or packed from host arrays), or, with rec null, three
+// separate arrays.
 struct EntrySrc {
     const ListEntry* rec;
     const float* w;
@@ -86,27 +88,28 @@ struct EntrySrc {
     const uint32_t* phase;
 };
 
-template <bool SOA>
 __device__ __forceinline__ void load_entry(const EntrySrc& src, uint64_t i, float& w, double& v, uint32_t& ph) {
-    if constexpr (SOA) {
-        w = src.w[i];
-        v = src.v[i];
-        ph = src.phase[i];
-    } else {
+    if (src.rec) {
         const ListEntry E = src.rec[i];
         w = E.w;
         v = E.v;
         ph = E.phase;
+    } else {
+        w = src.w[i];
+        v = src.v[i];
+        ph = src.phase[i];
     }
 }
 
 // The chunks [c0, c1) of frame entries starting at e_begin (n_entries in
 // all), accumulated over the NQ consecutive samples j0 .. j0 + NQ - 1 of the
-// frame (absolute sample index n0 for j0).  The two half-waves cover the
-// same samples and take alternate entries (lane l and lane l + 32 hold the
-// two halves of one run's sums), so each lane's run is twice as long as one
-// wave over the tile would give it.  Every lane takes part in the staging;
-// lanes whose run starts past the frame's samples only stage.
+// frame (absolute sample index n0 for j0).  The eight groups of eight lanes
+// cover the same samples and take every eighth entry (lanes l, l + 8, ...,
+// l + 56 hold the eight parts of one run's sums), so a lane's run is eight
+// times as long as one wave over the tile would give it, and the starting
+// phase of a run, its costly part, is paid once per NQ samples.  Every lane
+// takes part in the staging; lanes whose run starts past the frame's samples
+// only stage.
 //
 // Staged per entry: rp = (r, phi0), r = f / fs in cycles per sample, and
 // st = (a, s a, k, sin t) with a = sqrt(w).  The step per sample is
@@ -116,21 +119,26 @@ __device__ __forceinline__ void load_entry(const EntrySrc& src, uint64_t i, floa
 // the step accurate.  The run's samples: c_0 = cos x from the hardware unit,
 // d_0 = c_0 - cos(x - t) = c_0 k/2 - sin x sin t, then d_{q+1} = d_q - k c_q
 // and c_{q+1} = c_q + d_{q+1}; sample q adds a c_q (q even) or s a c_q (q odd).
-template <int NQ, bool SOA>
+// A lane group takes two of its entries per pass (an absent second entry
+// has zero amplitude), so that their two recurrences interleave.
+template <int NQ>
 __device__ __forceinline__ void synth_tile(const EntrySrc& src, uint64_t e_begin, uint64_t n_entries, int c0, int c1,
                                            double r_scale, double n0, bool active, float* acc, double2* s_rp,
                                            float4* s_st) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = 0.f;
+    const int grp = (int)(threadIdx.x / SYNTH_LANES);
     for (int ch = c0; ch < c1; ++ch) {
         const uint64_t e0 = (uint64_t)ch * SYNTH_CHUNK;
         const int ne = (int)(n_entries - e0 < (uint64_t)SYNTH_CHUNK ? n_entries - e0 : (uint64_t)SYNTH_CHUNK);
         __syncthreads();            // the previous chunk's entries are no longer read
+        // one entry at a time: the run's sums stay live across the staging
+#pragma unroll 1
         for (int i = threadIdx.x; i < ne; i += blockDim.x) {
             float w;
             double v;
             uint32_t ph;
-            load_entry<SOA>(src, e_begin + e0 + (uint64_t)i, w, v, ph);
+            load_entry(src, e_begin + e0 + (uint64_t)i, w, v, ph);
             const double r = v * r_scale;
             // the step in half cycles, in (-1, 1]
             double h = 2.0 * (r - floor(r));
@@ -147,55 +155,80 @@ __device__ __forceinline__ void synth_tile(const EntrySrc& src, uint64_t e_begin
         }
         __syncthreads();
         if (!active) continue;
-        // two entries per pass: their recurrences are independent chains
-        // (541 -> 524 us on the 256-frame case)
-#pragma unroll 2
-        for (int i = (int)(threadIdx.x >> 5); i < ne; i += 2) {
-            const double2 rp = s_rp[i];
-            const float4 st = s_st[i];
+        for (int i = grp; i < ne; i += 2 * SYNTH_GROUPS) {
+            const int i2 = i + SYNTH_GROUPS < ne ? i + SYNTH_GROUPS : i;
+            const double2 rpA = s_rp[i], rpB = s_rp[i2];
+            const float4 stA = s_st[i];
+            float4 stB = s_st[i2];
+            if (i2 == i) stB.x = stB.y = 0.f;
             // fractional cycles in one v_fract_f64 (x - floor(x), exact; its
             // clamp below 1 only matters where the FP32 rounding gives 1 anyway)
-            const float cyc = (float)__builtin_amdgcn_fract(fma(rp.x, n0, rp.y));
-            float c = __builtin_amdgcn_cosf(cyc);
-            acc[0] = fmaf(st.x, c, acc[0]);
+            const float cyA = (float)__builtin_amdgcn_fract(fma(rpA.x, n0, rpA.y));
+            const float cyB = (float)__builtin_amdgcn_fract(fma(rpB.x, n0, rpB.y));
+            float cA = __builtin_amdgcn_cosf(cyA), cB = __builtin_amdgcn_cosf(cyB);
+            acc[0] = fmaf(stA.x, cA, acc[0]);
+            acc[0] = fmaf(stB.x, cB, acc[0]);
             if constexpr (NQ > 1) {
-                float d = fmaf(0.5f * st.z, c, -__builtin_amdgcn_sinf(cyc) * st.w);
+                float dA = fmaf(0.5f * stA.z, cA, -__builtin_amdgcn_sinf(cyA) * stA.w);
+                float dB = fmaf(0.5f * stB.z, cB, -__builtin_amdgcn_sinf(cyB) * stB.w);
 #pragma unroll
                 for (int q = 1; q < NQ; ++q) {
-                    d = fmaf(-st.z, c, d);
-                    c += d;
-                    acc[q] = fmaf((q & 1) ? st.y : st.x, c, acc[q]);
+                    dA = fmaf(-stA.z, cA, dA);
+                    dB = fmaf(-stB.z, cB, dB);
+                    cA += dA;
+                    cB += dB;
+                    acc[q] = fmaf((q & 1) ? stA.y : stA.x, cA, acc[q]);
+                    acc[q] = fmaf((q & 1) ? stB.y : stB.x, cB, acc[q]);
                 }
             }
         }
     }
 }
 
-// One lane's run: the sums over the group's entries, the second
-// half-wave's sums added onto the first's (every lane takes part), and the
-// first half-wave's store of the run's samples below s_count.
-template <int NQ, bool SOA>
+// One lane's run: the sums over the group's entries, the other lane groups'
+// sums added onto the first group's (every lane takes part), and the first
+// group's store of the run's samples below s_count.
+template <int NQ>
 __device__ __forceinline__ void synth_run(const EntrySrc& src, uint64_t e_begin, uint64_t n_entries, int c0, int c1,
                                           double r_scale, double n0, bool active, double2* s_rp, float4* s_st,
                                           float* out, int j0, int s_count) {
     float acc[NQ];
-    synth_tile<NQ, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, acc, s_rp, s_st);
+    synth_tile<NQ>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, acc, s_rp, s_st);
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) acc[q] += __shfl_xor(acc[q], SYNTH_HALF, 64);
-    if (!active || threadIdx.x >= SYNTH_HALF) return;
+    for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+        for (int m = SYNTH_THREADS / 2; m >= SYNTH_LANES; m >>= 1) acc[q] += __shfl_xor(acc[q], m, 64);
+    }
+    if (!active || threadIdx.x >= SYNTH_LANES) return;
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
         if (j0 + q < s_count) out[j0 + q] = acc[q];
+}
+
+// The run of exactly nq samples (1 <= nq <= NQ): every run length has its
+// own unrolled code, so no sample slot is computed and thrown away.
+template <int NQ>
+__device__ __forceinline__ void synth_dispatch(int nq, const EntrySrc& src, uint64_t e_begin, uint64_t n_entries,
+                                               int c0, int c1, double r_scale, double n0, bool active,
+                                               double2* s_rp, float4* s_st, float* out, int j0, int s_count) {
+    if constexpr (NQ > 1) {
+        if (nq < NQ) {
+            synth_dispatch<NQ - 1>(nq, src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0,
+                                   s_count);
+            return;
+        }
+    }
+    synth_run<NQ>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count);
 }
 
 // Frame f owns samples [floor(f N / F), floor((f+1) N / F)) and the entries
 // [fbeg[f], fend[f]).  Block (tile, frame, group) accumulates the tile's
 // SYNTH_TILE samples over the group's entry chunks: group g takes chunks
 // [g cpg, (g+1) cpg), the last group every chunk from (G-1) cpg on.  Lane l
-// and lane l + 32 take the run of up to SYNTH_RUN consecutive samples from
-// tile sample l x nq, nq cut to what the tile's remaining samples need.  With one group the block writes the record;
+// and lanes l + 8, ..., l + 56 take the run of nq <= SYNTH_RUN consecutive
+// samples from tile sample (l mod 8) x nq, nq cut to what the tile's
+// remaining samples need.  With one group the block writes the record;
 // otherwise partial[(f G + g) max_samples + j] for the frame's sample j.
-template <bool SOA>
 __global__ void __launch_bounds__(SYNTH_THREADS)
 synth_tile_kernel(const uint64_t* __restrict__ fbeg, const uint64_t* __restrict__ fend, EntrySrc src,
                   double r_scale, int n_frames, int n_samples, int n_groups, int cpg, int max_samples,
@@ -217,29 +250,13 @@ synth_tile_kernel(const uint64_t* __restrict__ fbeg, const uint64_t* __restrict_
     c0 = c0 < used ? c0 : used;
     c1 = c1 < used ? c1 : used;
     const int left = s_count - tile_base;
-    const int nq = left >= SYNTH_TILE ? SYNTH_RUN : (left + SYNTH_HALF - 1) / SYNTH_HALF;
-    const int j0 = tile_base + (int)(threadIdx.x & (SYNTH_HALF - 1)) * nq;
+    const int nq = left >= SYNTH_TILE ? SYNTH_RUN : (left + SYNTH_LANES - 1) / SYNTH_LANES;
+    const int j0 = tile_base + (int)(threadIdx.x & (SYNTH_LANES - 1)) * nq;
     const bool active = j0 < s_count;
     const double n0 = (double)(s_begin + j0);
     float* out = n_groups == 1 ? signal + s_begin : partial + ((uint64_t)f * n_groups + g) * (uint64_t)max_samples;
-    switch (nq) {
-        case 16: synth_run<16, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
-        case 15: synth_run<15, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
-        case 14: synth_run<14, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
-        case 13: synth_run<13, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
-        case 12: synth_run<12, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
-        case 11: synth_run<11, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
-        case 10: synth_run<10, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
-        case 9: synth_run<9, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
-        case 8: synth_run<8, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
-        case 7: synth_run<7, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
-        case 6: synth_run<6, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
-        case 5: synth_run<5, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
-        case 4: synth_run<4, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
-        case 3: synth_run<3, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
-        case 2: synth_run<2, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
-        default: synth_run<1, SOA>(src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0, s_count); break;
-    }
+    synth_dispatch<SYNTH_RUN>(nq, src, e_begin, n_entries, c0, c1, r_scale, n0, active, s_rp, s_st, out, j0,
+                              s_count);
 }
 
 __global__ void synth_reduce_kernel(int n_frames, int n_samples, int n_groups, int max_samples,
@@ -414,12 +431,8 @@ hipError_t launch_synth(hipStream_t s, const SynthPlan& P, int n_frames, int n_s
     if (n_frames <= 0 || n_samples <= 0) return hipSuccess;
     const EntrySrc src{rec, w, v, phase};
     const dim3 grid((unsigned)P.tiles, (unsigned)n_frames, (unsigned)P.n_groups);
-    if (rec)
-        hipLaunchKernelGGL(synth_tile_kernel<false>, grid, dim3(SYNTH_THREADS), 0, s, fbeg, fend, src, r_scale,
-                           n_frames, n_samples, P.n_groups, P.cpg, P.max_samples, partial, signal);
-    else
-        hipLaunchKernelGGL(synth_tile_kernel<true>, grid, dim3(SYNTH_THREADS), 0, s, fbeg, fend, src, r_scale,
-                           n_frames, n_samples, P.n_groups, P.cpg, P.max_samples, partial, signal);
+    hipLaunchKernelGGL(synth_tile_kernel, grid, dim3(SYNTH_THREADS), 0, s, fbeg, fend, src, r_scale, n_frames,
+                       n_samples, P.n_groups, P.cpg, P.max_samples, partial, signal);
     if (P.n_groups > 1)
         hipLaunchKernelGGL(synth_reduce_kernel, dim3((unsigned)((P.max_samples + 255) / 256), (unsigned)n_frames),
                            dim3(256), 0, s, n_frames, n_samples, P.n_groups, P.max_samples, partial, signal);
