@@ -61,12 +61,17 @@ def test_beat_synthesis_matches_oracle(ctx):
     assert rel_l2(g, o) <= 1e-4, rel_l2(g, o)
 
 
-# frame lengths whose sample runs per thread are 1, 3, and 4 with a ragged
-# tail; the last case is a long record (4e5 samples per frame, phases up to
-# ~1e5 cycles) where only the FP64 phase at each run's start keeps the
-# carried phase exact
-@pytest.mark.parametrize("n_frames,ns,max_m", [(9, 9 * 100 + 4, 400), (6, 6 * 300 + 1, 400),
-                                               (4, 4 * 1537, 400), (5, 2_000_003, 40)])
+# Frame lengths against the synthesis layout (eight lanes per entry, tiles of
+# 512 samples, each lane a run of up to 64): frames of 5-6 samples (runs of
+# one sample, most lanes idle), 100-101 (runs of 13 with a ragged last run),
+# 300-301 (runs of 38), 520 (a full tile and a tail of one sample per lane),
+# 1000-1001 (a full tile and tails of 61 or 62 samples: two tail lengths in
+# one launch), 1537 (three full tiles and a one-sample tail); the last case
+# is a long record (4e5 samples per frame, phases up to ~1e5 cycles) where
+# only the FP64 phase at each run's start keeps the carried phase exact
+@pytest.mark.parametrize("n_frames,ns,max_m", [(7, 7 * 5 + 3, 50), (9, 9 * 100 + 4, 400), (6, 6 * 300 + 1, 400),
+                                               (2, 2 * 520, 100), (3, 3 * 1000 + 2, 300), (4, 4 * 1537, 400),
+                                               (5, 2_000_003, 40)])
 def test_beat_synthesis_sample_runs(ctx, n_frames, ns, max_m):
     print("case beat runs", n_frames, ns, max_m, flush=True)
     rng = np.random.Generator(np.random.PCG64(ns))
