@@ -306,8 +306,10 @@ void pdv_ctx::release_all() {
     }
     for (auto& h : host_pinned) (void)hipHostFree(h.ptr);
     host_pinned.clear();
-    if (tally_pinned.ptr) (void)hipHostFree(tally_pinned.ptr);
-    tally_pinned = HostPinned{};
+    for (HostPinned* h : {&tally_pinned, &counts_pinned}) {
+        if (h->ptr) (void)hipHostFree(h->ptr);
+        *h = HostPinned{};
+    }
     mem_used = 0;
     mie_key_valid = false;
     stft_nfft = 0;
