@@ -279,6 +279,24 @@ def test_single_set_graph_replays(ctx):
             assert np.array_equal(eager["w_fx"], ref["w_fx"])
 
 
+@pytest.mark.parametrize("n", [0, 1, 63, 1025, 1_572_869])
+def test_wave_item_counts(ctx, n):
+    # a single FP32 set of the tabulated kind: the kernel cuts the set into
+    # equal items that the waves take themselves (none for an empty set, one
+    # of a single packet, items of 1023-1024 packets at the largest count
+    # here); the tallies equal those of block items in a non-persistent
+    # launch of the same kernel, bit for bit
+    print("case wave items", n, flush=True)
+    p = dict(wl.large_mie(n), seed=61)
+    got = ctx.spectrum(p)
+    if n:
+        assert ctx.last_launch()["kind"] == 1
+    ref = ctx.spectrum_batch([p], opts=dict(persistent=0))[0]
+    assert np.array_equal(got["w_fx"], ref["w_fx"]) and got["sinks_fx"] == ref["sinks_fx"]
+    assert got["counts"] == ref["counts"] and got["counts"]["packets"] == n
+    assert conservation_exact(got, n)
+
+
 def test_empty_and_degenerate(ctx):
     p = _c1(n_packets=0)
     g = ctx.spectrum(p)
