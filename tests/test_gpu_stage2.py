@@ -279,6 +279,35 @@ def test_spectrogram_lists_across_pid_word_boundary(ctx, oracle_mc, precision):
     assert flipped <= (3 if precision == 0 else 0), flipped
 
 
+def test_beat_synthesis_maximum_frames(ctx):
+    """The largest frame count the synthesis takes (the launch grid's frame
+    dimension): 65535 frames of 3-4 samples holding 0-2 entries each; the
+    record matches the oracle, the samples of frames without entries are
+    exactly zero, and one frame more is refused."""
+    from paper_2012_00963_amd import pdv
+    rng = np.random.Generator(np.random.PCG64(37))
+    n_frames, fs, lam = 65535, 20e9, 1550e-9
+    ns = 3 * n_frames + 11
+    counts = rng.integers(0, 3, n_frames)
+    m = int(counts.sum())
+    w = rng.uniform(0.01, 1.0, m).astype(np.float32)
+    v = rng.uniform(0.0, 4000.0, m)
+    ph = rng.integers(0, 2**32, m, dtype=np.uint64).astype(np.uint32)
+    offs = np.concatenate([[0], np.cumsum(counts)])
+    lists_g = [{"w": w[a:b], "v": v[a:b], "phase_u32": ph[a:b]} for a, b in zip(offs[:-1], offs[1:])]
+    lists_o = [{"w": L["w"].astype(np.float64), "v": L["v"], "phase": L["phase_u32"].astype(np.float64) / 2**32}
+               for L in lists_g]
+    g = ctx.beat_synthesize(lists_g, lam, fs, ns)
+    o = ostage2.beat_signal(lists_o, ns, fs, lam)
+    assert rel_l2(g, o) <= 1e-4, rel_l2(g, o)
+    b = np.asarray(ostage2.frame_bounds(ns, n_frames))
+    in_empty = np.repeat(counts == 0, np.diff(b))
+    assert in_empty.any() and np.all(g[in_empty] == 0.0)
+    with pytest.raises(pdv.PdvError) as e:
+        ctx.beat_synthesize(lists_g + [lists_g[0]], lam, fs, ns + 3)
+    assert e.value.code == -1
+
+
 def test_beat_synthesis_step_extremes(ctx):
     """One entry per frame at the step sizes where a sample-to-sample
     recurrence is least accurate: zero and tiny velocities (step near 0),
