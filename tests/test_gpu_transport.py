@@ -74,6 +74,10 @@ def test_small_case_90deg_parity(ctx, oracle_mc, precision):
     dict(n_bins=1, v_lo=900.0, v_hi=1100.0),
     # isotropic scattering (HG with g = 0) with Lambert reflection and analog absorption
     dict(hg_g=0.0, surface_law=wl.SURFACE_LAMBERT, weighting=wl.WEIGHT_ANALOG, cone_half_angle=math.radians(40)),
+    # black particles (every collision takes the whole weight) and a black
+    # surface under analog absorption (every reflection ends the packet)
+    dict(albedo=0.0, tau_total=1.0, cone_half_angle=math.radians(60)),
+    dict(surface_albedo=0.0, weighting=wl.WEIGHT_ANALOG, tau_total=0.5, cone_half_angle=math.radians(60)),
 ])
 def test_variant_parity(ctx, oracle_mc, kw):
     p = _c1(n_packets=300_000, **kw)
